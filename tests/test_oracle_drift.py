@@ -1,0 +1,124 @@
+"""Pins of the analytic Verlet-buffer drift bound (appendix) and of the exact recount oracle.
+
+* The closed form is checked against adaptive numerical quadrature of the
+  Taylor-expanded double integral it is derived from; the printed V'' term
+  (sigma (r_b^2 + sigma^2) G) fails that check, the corrected 2 sigma^2 passes.
+* The single-integral identities behind the closed form at r_b = 0 have
+  textbook moments of the half-normal distribution.
+* The bound decreases monotonically with the buffer and vanishes for large buffers.
+* The exact recount equals a brute-force enumeration of missed pairs on a tiny box.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import synth
+from oracle import drift
+
+
+@pytest.mark.parametrize("rb,sigma", [(0.0, 0.03), (0.05, 0.03), (0.02, 0.05), (0.1, 0.04)])
+@pytest.mark.parametrize("v1,v2", [(1.0, 0.0), (0.0, 1.0), (-2.5, 40.0)])
+def test_closed_form_matches_quadrature(rb, sigma, v1, v2):
+    a = drift.dV_pair(rb, 1.0, sigma, 33.4, v1, v2)
+    b = drift.dV_pair_quadrature(rb, 1.0, sigma, 33.4, v1, v2)
+    assert a == pytest.approx(b, rel=1e-8, abs=1e-14)
+
+
+def test_printed_second_order_term_is_wrong():
+    """With the V'' term as printed the bound disagrees with its own integral (and goes negative)."""
+    rb, s = 0.05, 0.03
+    x = rb / s
+    G, E = drift.gauss(x), drift.E_tail(x)
+    printed = s * (rb * rb + s * s) * G - rb * (rb * rb + 3 * s * s) * E
+    corrected = s * (rb * rb + 2 * s * s) * G - rb * (rb * rb + 3 * s * s) * E
+    # the integral the term comes from: 3 * int_0^inf v^2 E((rb+v)/s) dv
+    I2, _ = integrate.quad(lambda v: v * v * drift.E_tail((rb + v) / s), 0, 50 * s, epsabs=0, epsrel=1e-12)
+    assert corrected == pytest.approx(3 * I2, rel=1e-9)
+    assert printed < 0 < 3 * I2
+
+
+def test_half_normal_moments_at_zero_buffer():
+    """r_b = 0: int_0^inf v E(v/s) dv = s^2/4 and int_0^inf v^2 E(v/s) dv = s^3 sqrt(2/pi)/3 (half-normal moments)."""
+    s = 0.037
+    x = 0.0
+    G, E = drift.gauss(x), drift.E_tail(x)
+    I1 = 0.5 * ((0 + s * s) * E - 0)
+    I2 = (s * (0 + 2 * s * s) * G - 0) / 3
+    assert I1 == pytest.approx(s * s / 4, rel=1e-14)
+    assert I2 == pytest.approx(s ** 3 * math.sqrt(2 / math.pi) / 3, rel=1e-14)
+
+
+def _spce_kw(nstlist=10, T=300.0):
+    n_mol = 32000
+    L = 9.86
+    return dict(T=T, dt=0.002, nstlist=nstlist, masses=[synth.MASS_O, synth.MASS_H], charges=[synth.Q_O, synth.Q_H],
+                c6c12=synth.lj_table_spce(), counts=[n_mol, 2 * n_mol], volume=L ** 3, rc=1.0, beta=3.12,
+                f=synth.COULOMB_F)
+
+
+def test_bound_monotone_and_vanishing():
+    kw = _spce_kw()
+    rbs = np.arange(0.0, 0.4, 0.005)
+    d = np.array([drift.drift_rate(rb, **kw) for rb in rbs])
+    assert np.all(np.diff(d) < 0)
+    assert d[-1] < 1e-6 * d[0]
+    # longer list lifetimes need larger buffers
+    b10 = drift.min_buffer(0.005, **kw)
+    b20 = drift.min_buffer(0.005, **_spce_kw(nstlist=20))
+    b40 = drift.min_buffer(0.005, **_spce_kw(nstlist=40))
+    assert 0 < b10 < b20 < b40
+
+
+def test_recount_matches_bruteforce():
+    """Missed-pair energy from the cluster thresholds equals a direct enumeration (tiny box, 4x4 and 8x8)."""
+    b = synth.water_box(120, 1.65, seed=3)   # L > 2 (rc + rb_max)
+    spce = synth.lj_table_spce()
+    rc, beta = 0.6, 5.2
+    rng = np.random.default_rng(9)
+    xt = (b.xyz.astype(np.float64) + rng.normal(0, 0.03, b.xyz.shape)).astype(np.float32)
+    db, nb = 0.01, 20
+    rl = rc + db * nb
+    for m, n in ((4, 4), (8, 8)):
+        c_bb = 0.2
+        hist = oracle.recount(b.xyz, xt, b.q, b.type, b.box, b.excl_off, b.excl_idx, spce, rc, beta, synth.COULOMB_F,
+                              m, n, rl, c_bb, db, nb)
+        g = oracle.grid_sort(b.xyz, b.box, m, n)
+        for k in (0, 3, 9):
+            rlk = rc + k * db
+            ent = oracle.pairlist(g, b.box, np.float32(rlk), max(0.0, rlk - c_bb), b.excl_off, b.excl_idx)
+            listed = set()
+            for e in ent:
+                for a in range(m):
+                    for c in range(n):
+                        sa, sb = int(e["ci"]) * m + a, int(e["cj"]) * n + c
+                        if g["perm"][sa] >= 0 and g["perm"][sb] >= 0 and not (e["shift"] == 13 and sa >= sb):
+                            listed.add((sa, sb, int(e["shift"])))
+            # every non-excluded (slot pair, image) in canonical orientation that is within rc after the
+            # displacement but not listed; displaced position = wrapped position + (x_t - x_0)
+            real = np.nonzero(g["perm"] >= 0)[0]
+            disp = xt.astype(np.float64) - b.xyz.astype(np.float64)
+            pos = g["xs"][real].astype(np.float64) + disp[g["perm"][real]]
+            Lf = b.box.astype(np.float32).astype(np.float64)
+            miss = 0.0
+            for s in range(13, 27):
+                sv = np.array([s // 9 - 1, (s // 3) % 3 - 1, s % 3 - 1]) * Lf
+                for ka, sa in enumerate(real):
+                    d = pos[ka] + sv - pos
+                    r = np.sqrt((d * d).sum(1))
+                    for kb in np.nonzero(r < rc)[0]:
+                        sb = real[kb]
+                        if s == 13 and sb <= sa:
+                            continue
+                        i, j = int(g["perm"][sa]), int(g["perm"][sb])
+                        if i // 3 == j // 3 or (int(sa), int(sb), s) in listed:
+                            continue
+                        rr = r[kb]
+                        c6, c12 = spce[b.type[i], b.type[j]]
+                        v = c12 / rr ** 12 - c6 / rr ** 6 - (c12 / rc ** 12 - c6 / rc ** 6)
+                        qq = synth.COULOMB_F * float(b.q[i]) * float(b.q[j])
+                        v += qq * (math.erfc(beta * rr) / rr - math.erfc(beta * rc) / rc)
+                        miss += v
+            assert hist[k:].sum() == pytest.approx(miss, rel=1e-6, abs=1e-9)
