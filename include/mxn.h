@@ -1,0 +1,260 @@
+/*
+ * mxn.h - C ABI of the MI355X (gfx950) cluster-pair non-bonded library.
+ *
+ * Method: Pall & Hess, "A flexible algorithm for calculating pair
+ * interactions on SIMD architectures", Comput. Phys. Commun. 184 (2013).
+ * Particles are grid-sorted into spatial clusters of fixed size, a
+ * cluster-pair list is built at a buffered cut-off rlist from bounding-box
+ * distances, and an M x N cluster-pair kernel evaluates Lennard-Jones plus
+ * Ewald real-space Coulomb interactions with per-pair exclusion masks.
+ *
+ * Conventions for every entry point
+ *   - Units: nm, ps, kJ/mol, e, u.  Positions/charges FP32, energies and
+ *     virial FP64.
+ *   - "device" pointers are HIP device memory owned by the caller (for
+ *     example torch tensors on cuda:N); "host" pointers are ordinary host
+ *     memory.  Nothing the caller passes is retained after a call returns,
+ *     except that nb_grid / nb_list handles remember the box and shapes.
+ *   - Handles (nb_ctx, nb_grid, nb_list, nb_batch, nb_mlp) are owned by the
+ *     library and released with their *_free / nb_destroy call.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *     stated otherwise.  Errors found on the host are returned immediately as
+ *     a negative nb_status; errors found by kernels (non-finite coordinates,
+ *     list capacity overflow) are latched on the device and returned by the
+ *     next nb_sync on that context.  nb_last_error() describes the most recent
+ *     non-OK status of the calling thread.  No C++ exception crosses the ABI.
+ *   - Periodic orthorhombic boxes only, every edge longer than 2 * rlist.
+ */
+#ifndef MXN_H
+#define MXN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NB_OK = 0,
+    NB_ERR_ARG = -1,         /* invalid argument (null pointer, bad size or shape, out-of-range parameter) */
+    NB_ERR_BOX = -2,         /* a box edge is not longer than 2 * rlist */
+    NB_ERR_OOM = -3,         /* device allocation failed */
+    NB_ERR_HIP = -4,         /* HIP runtime error */
+    NB_ERR_OVERFLOW = -5,    /* pair-list capacity exceeded during an asynchronous build: rebuild */
+    NB_ERR_STATE = -6,       /* handle used with an incompatible grid, list or context */
+    NB_ERR_NONFINITE = -7,   /* non-finite or out-of-range coordinate seen by a kernel */
+    NB_ERR_UNSUPPORTED = -8  /* valid request this build does not implement (for example beta*rc > 4) */
+} nb_status;
+
+typedef struct nb_ctx nb_ctx;
+typedef struct nb_grid nb_grid;
+typedef struct nb_list nb_list;
+
+/* Cluster shape M x N: i-clusters of M particles against j-clusters of N
+ * particles (Sec. 2.2 "The M x N algorithm").  Supported: 4x4, 4x8, 8x8. */
+typedef struct { int m, n; } nb_shape;
+
+/* Interaction parameters (Sec. 3.2 "Pair interaction functions", Eq. 1 and 2).
+ *   rc        cut-off (nm); pairs with r >= rc contribute nothing
+ *   beta      Ewald splitting parameter (1/nm); beta * rc must be <= 4
+ *   coulomb_f 1/(4 pi eps0) in the caller's units (138.935458 kJ mol^-1 nm e^-2)
+ *   ntypes    number of LJ types (1..32)
+ *   c6c12     DEVICE, ntypes*ntypes*2 floats: [ti][tj] = (C6, C12), symmetric
+ *   shift_energies  1: LJ and Coulomb potentials shifted to zero at rc */
+typedef struct {
+    float rc, beta, coulomb_f;
+    int ntypes;
+    const float *c6c12;
+    int shift_energies;
+} nb_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *ctx receives the handle. */
+int nb_create(nb_ctx **ctx, int device, void *hip_stream);
+void nb_destroy(nb_ctx *ctx);
+/* Change the stream subsequent calls enqueue on. */
+int nb_set_stream(nb_ctx *ctx, void *hip_stream);
+/* Wait for the stream; return the first latched kernel error (and clear it). */
+int nb_sync(nb_ctx *ctx);
+/* Text for the calling thread's most recent non-OK status ("" if none). */
+const char *nb_last_error(void);
+
+/* -------------------------------------------------------------- grid sort */
+
+/*
+ * Cluster the particles (Sec. 2.3 "Pair list construction", gridding):
+ * a 2-D x/y column grid of spacing (max(M,N)/rho)^(1/3), rho = n/V; particles
+ * go into columns by counting sort, are ordered by z inside each column and
+ * consecutive groups of min(M,N) form clusters; each column is padded with
+ * dummy particles (no charge, no LJ, far away) to a multiple of max(M,N).
+ * Per-cluster bounding boxes over real particles follow (for M != N both the
+ * M- and N-particle boxes, the latter the union of two adjacent M-boxes).
+ *
+ *   box     HOST double[3] box edges (nm); kernels use (float)box
+ *   n       number of particles (>= 1)
+ *   xyzq    DEVICE float[4n]: x, y, z, q in original order (x may lie outside
+ *           the box; each particle is wrapped and its image count recorded)
+ *   type    DEVICE int[n]: LJ type in [0, ntypes)
+ *   shape   cluster shape
+ *   grid    in/out: *grid == NULL creates a grid, otherwise it is reused
+ *           (storage grows as needed).
+ * Canonical FP32 rules (wrap, column index, z order with ties by original
+ * index) are stated in the library documentation and are bit-reproducible.
+ */
+int nb_grid_sort(nb_ctx *ctx, const double box[3], int n, const float *xyzq, const int *type, nb_shape shape,
+                 nb_grid **grid);
+void nb_grid_free(nb_grid *grid);
+
+typedef struct {
+    int n, n_slots, m, n_cl;      /* particles, padded slots, M, N */
+    int nx, ny;                   /* column grid */
+    int n_ci, n_cj;               /* i- and j-cluster counts (n_slots/M, n_slots/N) */
+} nb_grid_info_t;
+
+/* Synchronous.  Fills *info. */
+int nb_grid_info(nb_grid *grid, nb_grid_info_t *info);
+
+/* Synchronous copy of the sorted layout to HOST arrays (any may be NULL):
+ *   perm[n_slots]      original index per slot, -1 for dummies
+ *   xyzq[4*n_slots]    wrapped sorted positions and charges at sort time
+ *   img[3*n]           per original particle image count k: wrapped = x - k*L
+ *   col_start[nx*ny+1] first slot of each column
+ *   bb[8*n_ci]         per i-cluster (lo.x, lo.y, lo.z, 0, hi.x, hi.y, hi.z, 0) */
+int nb_grid_export(nb_grid *grid, int *perm, float *xyzq, int *img, int *col_start, float *bb);
+
+/* ------------------------------------------------------------- pair list */
+
+enum {
+    NB_LIST_ASYNC = 1   /* do not synchronise to size the list: reuse the handle's capacity,
+                           latch NB_ERR_OVERFLOW (reported by nb_sync) if it is too small */
+};
+
+/*
+ * Cluster-pair search (Sec. 2.3, cluster-pair search pseudocode; Sec. 2.4
+ * "Exclusion treatment"): for every i-cluster and periodic image shift, every
+ * j-cluster whose bounding-box distance d satisfies d < rlist and (d < rbb or
+ * some real particle pair is closer than rlist).  Half list (Newton's third
+ * law): only image shifts that are zero or lexicographically positive, and for
+ * the zero shift only pairs with slot(i) < slot(j).  Per entry an M*N-bit mask
+ * clears dummy pairs, the lower triangle of self pairs and force-field
+ * exclusions in the image where they lie within rlist (the Ewald correction is
+ * still applied to those).
+ *
+ *   rlist     list radius (nm), > 0; every box edge must exceed 2*rlist
+ *   rbb       bounding-box shortcut radius (nm); < 0 selects
+ *             max(0, rlist - s/2) with s the column spacing
+ *   excl_off  DEVICE int[n+1], excl_idx DEVICE int[excl_off[n]]: force-field
+ *             exclusions as CSR in original indices; must be symmetric
+ *   flags     0 or NB_LIST_ASYNC
+ *   list      in/out: NULL creates, otherwise reused
+ * Without NB_LIST_ASYNC the call synchronises once to size its storage.
+ * Entries are in a deterministic order: by i-cluster, image shift, j-cluster.
+ */
+int nb_pairlist_build(nb_ctx *ctx, const nb_grid *grid, float rlist, float rbb, const int *excl_off,
+                      const int *excl_idx, int flags, nb_list **list);
+void nb_list_free(nb_list *list);
+
+/* Synchronous.  Number of cluster-pair entries and force work items. */
+int nb_list_info(nb_list *list, long *n_entries, long *n_items);
+
+/* One cluster pair in canonical form: i-cluster, image shift index
+ * s = 9(sx+1) + 3(sy+1) + (sz+1) (the i-cluster is moved by s.L), j-cluster,
+ * and mask bit a*N + b for i-slot a, j-slot b. */
+typedef struct { int32_t ci, shift, cj, pad; uint64_t mask; } nb_entry;
+
+/* Synchronous.  Copies min(cap, n_entries) entries in canonical order to
+ * HOST `out`, *count receives n_entries. */
+int nb_list_export_canonical(nb_list *list, nb_entry *out, long cap, long *count);
+
+/* ----------------------------------------------------------------- forces */
+
+enum {
+    NB_ENERGY = 1,       /* also compute LJ and Coulomb energies */
+    NB_VIRIAL = 2,       /* also compute the virial sum over pairs of r_ij (x) F_i */
+    NB_ACC_FP32 = 4,     /* accumulate energies/virial in FP32 end to end (precision study);
+                            default is FP64 accumulation of FP32 pair terms */
+    NB_ACCUMULATE = 8    /* add forces to f instead of overwriting */
+};
+
+/*
+ * Pair interactions over the list (Sec. 3 "Pair interaction kernels";
+ * Eq. 1 LJ, Eq. 2 Coulomb with the Ewald real-space correction
+ * g(r) = d/dr[erf(beta r)/r], Sec. 2.4 exclusions).  For each listed pair with
+ * r < rc: mask bit 1 -> LJ + erfc-screened Coulomb; mask bit 0 (force-field
+ * exclusion) -> the Ewald correction -erf(beta r)/r only.
+ *
+ *   xyzq_now DEVICE float[4n]: current positions and charges, ORIGINAL order,
+ *            not re-wrapped since nb_grid_sort (the grid's image counts apply)
+ *   f        DEVICE float[3n] forces in original order (overwritten unless
+ *            NB_ACCUMULATE)
+ *   energy   DEVICE double[2] (E_LJ, E_Coulomb), written when NB_ENERGY
+ *   virial   DEVICE double[9] row-major sum of r_ij (x) F_i, when NB_VIRIAL
+ */
+int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, const nb_params *p,
+              unsigned flags, float *f, double *energy, double *virial);
+
+/* -------------------------------------------------------- buffer estimate */
+
+/*
+ * Verlet-buffer query (Sec. 5 "Effective pair list buffering" and appendix).
+ * Per-type arrays are HOST pointers of length ntypes.
+ */
+typedef struct {
+    double T;              /* temperature (K) */
+    double dt;             /* time step (ps) */
+    int nstlist;           /* list lifetime in steps */
+    int ntypes;
+    const double *mass;    /* u */
+    const double *charge;  /* e */
+    const double *c6c12;   /* ntypes*ntypes*2 */
+    const double *count;   /* particles per type */
+    double volume;         /* nm^3 */
+    double rc, beta, coulomb_f;
+    nb_shape shape;        /* cluster shape the list will use (learned mode) */
+    double target;         /* allowed drift, kJ/mol/ps per particle */
+} nb_buffer_query;
+
+enum { NB_BUFFER_ANALYTIC = 0, NB_BUFFER_MLP = 1, NB_BUFFER_AUTO = 2 };
+
+/*
+ * Smallest buffer r_b (on a 0.0005 nm grid) whose estimated drift is within
+ * q->target.  ANALYTIC: the appendix bound (free-particle Gaussian
+ * displacements over t = (nstlist-1)*dt, second-order expansion of the
+ * potential at rc, second-order term with 2 sigma^2 as the integral gives),
+ * summed as 1/2 sum_a N_a sum_b |dV_ab| and divided by N*nstlist*dt.
+ * MLP / AUTO: the learned predictor of an nb_mlp attached with
+ * nb_buffer_set_mlp, falling back to ANALYTIC outside its training range or
+ * on a non-finite output (*used_fallback = 1).  Host only, synchronous.
+ *   rb_out     nm;  drift_out  analytic drift estimate at *rb_out
+ */
+int nb_buffer_estimate(nb_ctx *ctx, const nb_buffer_query *q, int mode, double *rb_out, double *drift_out,
+                       int *used_fallback);
+
+/* ------------------------------------------------------------ instrumentation */
+
+/* Pair statistics of a list at the given positions (Sec. 5: the effective
+ * pair ratio counts only pairs within the cut-off).  Synchronous.  HOST
+ * counts[4]: [0] listed pairs (entries * M * N), [1] real pairs the kernel
+ * visits (dummies and the lower triangle of self pairs excluded), [2]
+ * interacting pairs with r < rc, [3] force-field-excluded pairs with r < rc.
+ * xyzq_now as in nb_forces. */
+int nb_list_stats(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, float rc,
+                  long long *counts);
+
+/* Kernel timing with HIP events recorded on the context's stream around the
+ * force kernel, the whole nb_forces call, nb_grid_sort and nb_pairlist_build.
+ * Off by default.  nb_timing_read synchronises, returns the summed elapsed
+ * milliseconds and the number of timed launches per timer since the last read
+ * (HOST arrays of NB_TIMER_COUNT), and resets. */
+enum { NB_TIMER_FORCE_KERNEL = 0, NB_TIMER_FORCE_CALL = 1, NB_TIMER_GRID_SORT = 2, NB_TIMER_PAIRLIST = 3,
+       NB_TIMER_COUNT = 4 };
+int nb_timing_enable(nb_ctx *ctx, int on);
+int nb_timing_read(nb_ctx *ctx, double *ms, long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

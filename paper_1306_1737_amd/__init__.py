@@ -1,0 +1,283 @@
+"""Python binding of libmxn.so, the MI355X cluster-pair non-bonded library.
+
+Thin ctypes marshalling over the C ABI in include/mxn.h: the functions keep
+the C names and argument order; torch tensors supply device pointers and the
+current HIP stream.  Every computation runs in the library's HIP kernels --
+there is no CPU or PyTorch fallback: if libmxn.so is missing or fails to load,
+importing the binding functions raises.
+
+Method: Pall & Hess, "A flexible algorithm for calculating pair interactions
+on SIMD architectures", CPC 2013 (grid sort, cluster-pair list, M x N kernel,
+Verlet-buffer estimate).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmxn.so")
+
+NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_OOM, NB_ERR_HIP, NB_ERR_OVERFLOW, NB_ERR_STATE, NB_ERR_NONFINITE, \
+    NB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
+NB_LIST_ASYNC = 1
+NB_ENERGY, NB_VIRIAL, NB_ACC_FP32, NB_ACCUMULATE = 1, 2, 4, 8
+NB_BUFFER_ANALYTIC, NB_BUFFER_MLP, NB_BUFFER_AUTO = 0, 1, 2
+
+# symbols declared in include/mxn.h (checked by the ABI test)
+EXPORTS = [
+    "nb_create", "nb_destroy", "nb_set_stream", "nb_sync", "nb_last_error",
+    "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
+    "nb_pairlist_build", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
+    "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
+    "nb_list_stats",
+]
+NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
+
+
+class NbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class nb_shape(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int)]
+
+
+class nb_params(ctypes.Structure):
+    _fields_ = [("rc", ctypes.c_float), ("beta", ctypes.c_float), ("coulomb_f", ctypes.c_float),
+                ("ntypes", ctypes.c_int), ("c6c12", ctypes.c_void_p), ("shift_energies", ctypes.c_int)]
+
+
+class nb_grid_info_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int) for k in ("n", "n_slots", "m", "n_cl", "nx", "ny", "n_ci", "n_cj")]
+
+
+class nb_entry(ctypes.Structure):
+    _fields_ = [("ci", ctypes.c_int32), ("shift", ctypes.c_int32), ("cj", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("mask", ctypes.c_uint64)]
+
+
+class nb_buffer_query(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("dt", ctypes.c_double), ("nstlist", ctypes.c_int), ("ntypes", ctypes.c_int),
+                ("mass", ctypes.c_void_p), ("charge", ctypes.c_void_p), ("c6c12", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("volume", ctypes.c_double), ("rc", ctypes.c_double),
+                ("beta", ctypes.c_double), ("coulomb_f", ctypes.c_double), ("shape", nb_shape),
+                ("target", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmxn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmxn.so not built: run `python -m paper_1306_1737_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ip, i, f, d, u = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_float, \
+            ctypes.c_double, ctypes.c_uint
+        pvp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "nb_create": ([pvp, i, vp], i), "nb_destroy": ([vp], None), "nb_set_stream": ([vp, vp], i),
+            "nb_sync": ([vp], i), "nb_last_error": ([], ctypes.c_char_p),
+            "nb_grid_sort": ([vp, vp, i, vp, vp, nb_shape, pvp], i), "nb_grid_free": ([vp], None),
+            "nb_grid_info": ([vp, ctypes.POINTER(nb_grid_info_t)], i),
+            "nb_grid_export": ([vp, vp, vp, vp, vp, vp], i),
+            "nb_pairlist_build": ([vp, vp, f, f, vp, vp, i, pvp], i), "nb_list_free": ([vp], None),
+            "nb_list_info": ([vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)], i),
+            "nb_list_export_canonical": ([vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_long)], i),
+            "nb_forces": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), u, vp, vp, vp], i),
+            "nb_buffer_estimate": ([vp, ctypes.POINTER(nb_buffer_query), i, ctypes.POINTER(d), ctypes.POINTER(d),
+                                    ip], i),
+            "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
+            "nb_list_stats": ([vp, vp, vp, vp, f, vp], i),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != NB_OK:
+        raise NbError(rc, lib().nb_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor, numpy array or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(t.data_ptr())
+    if hasattr(t, "ctypes"):
+        return ctypes.c_void_p(t.ctypes.data)
+    return ctypes.c_void_p(t)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _need(t, dtype, numel, name):
+    import torch
+    if t.device.type != "cuda" or t.dtype != dtype or t.numel() < numel or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s CUDA tensor with >= %d elements" % (name, dtype, numel))
+
+
+# ---------------------------------------------------------------- context
+
+def nb_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().nb_create(ctypes.byref(h), int(device), _stream(stream)))
+    return h
+
+
+def nb_destroy(ctx):
+    lib().nb_destroy(ctx)
+
+
+def nb_set_stream(ctx, stream=None):
+    _check(lib().nb_set_stream(ctx, _stream(stream)))
+
+
+def nb_sync(ctx):
+    return _check(lib().nb_sync(ctx))
+
+
+def nb_last_error():
+    return lib().nb_last_error().decode()
+
+
+# ------------------------------------------------------------------ grid
+
+def nb_grid_sort(ctx, box, xyzq, type_, shape, grid=None):
+    """box: 3 floats (host); xyzq: (n,4) float32 cuda; type_: (n,) int32 cuda; shape: (m, n)."""
+    import torch
+    n = xyzq.shape[0]
+    _need(xyzq, torch.float32, 4 * n, "xyzq")
+    _need(type_, torch.int32, n, "type")
+    b = (ctypes.c_double * 3)(*[float(v) for v in box])
+    h = grid if grid is not None else ctypes.c_void_p()
+    _check(lib().nb_grid_sort(ctx, b, int(n), _ptr(xyzq), _ptr(type_), nb_shape(*shape), ctypes.byref(h)))
+    return h
+
+
+def nb_grid_free(grid):
+    lib().nb_grid_free(grid)
+
+
+def nb_grid_info(grid):
+    info = nb_grid_info_t()
+    _check(lib().nb_grid_info(grid, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in nb_grid_info_t._fields_}
+
+
+def nb_grid_export(grid):
+    """Host copies (numpy) of perm, sorted xyzq, per-particle image, column starts, i-cluster boxes."""
+    import numpy as np
+    info = nb_grid_info(grid)
+    ns, n, nci = info["n_slots"], info["n"], info["n_ci"]
+    perm = np.empty(ns, np.int32)
+    xyzq = np.empty((ns, 4), np.float32)
+    img = np.empty((n, 3), np.int32)
+    cs = np.empty(info["nx"] * info["ny"] + 1, np.int32)
+    bb = np.empty((nci, 8), np.float32)
+    _check(lib().nb_grid_export(grid, _ptr(perm), _ptr(xyzq), _ptr(img), _ptr(cs), _ptr(bb)))
+    return dict(info=info, perm=perm, xyzq=xyzq, img=img, col_start=cs, bb=bb)
+
+
+# ------------------------------------------------------------------ list
+
+def nb_pairlist_build(ctx, grid, rlist, rbb, excl_off, excl_idx, flags=0, lst=None):
+    import torch
+    _need(excl_off, torch.int32, 1, "excl_off")
+    h = lst if lst is not None else ctypes.c_void_p()
+    _check(lib().nb_pairlist_build(ctx, grid, float(rlist), float(rbb), _ptr(excl_off), _ptr(excl_idx), int(flags),
+                                   ctypes.byref(h)))
+    return h
+
+
+def nb_list_free(lst):
+    lib().nb_list_free(lst)
+
+
+def nb_list_info(lst):
+    ne, ni = ctypes.c_long(), ctypes.c_long()
+    _check(lib().nb_list_info(lst, ctypes.byref(ne), ctypes.byref(ni)))
+    return ne.value, ni.value
+
+
+ENTRY_DTYPE = [("ci", "<i4"), ("shift", "<i4"), ("cj", "<i4"), ("pad", "<i4"), ("mask", "<u8")]
+
+
+def nb_list_export_canonical(lst):
+    import numpy as np
+    ne, _ = nb_list_info(lst)
+    out = np.zeros(max(ne, 1), dtype=np.dtype(ENTRY_DTYPE))
+    cnt = ctypes.c_long()
+    _check(lib().nb_list_export_canonical(lst, _ptr(out), ctypes.c_long(ne), ctypes.byref(cnt)))
+    return out[:cnt.value]
+
+
+# ---------------------------------------------------------------- forces
+
+def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True):
+    """nb_params with c6c12 a (ntypes, ntypes, 2) float32 CUDA tensor (kept referenced by the struct's owner)."""
+    nt = c6c12.shape[0]
+    p = nb_params(float(rc), float(beta), float(coulomb_f), int(nt), c6c12.data_ptr(), int(bool(shift_energies)))
+    p._keep = c6c12
+    return p
+
+
+def nb_forces(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=None):
+    _check(lib().nb_forces(ctx, grid, lst, _ptr(xyzq_now), ctypes.byref(params), int(flags), _ptr(f), _ptr(energy),
+                           _ptr(virial)))
+
+
+# ------------------------------------------------------- buffer estimate
+
+def nb_buffer_estimate(ctx, *, T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape,
+                       target, mode=NB_BUFFER_ANALYTIC):
+    import numpy as np
+    mass = np.ascontiguousarray(mass, np.float64); charge = np.ascontiguousarray(charge, np.float64)
+    c6c12 = np.ascontiguousarray(c6c12, np.float64); count = np.ascontiguousarray(count, np.float64)
+    q = nb_buffer_query(float(T), float(dt), int(nstlist), int(mass.shape[0]), mass.ctypes.data, charge.ctypes.data,
+                        c6c12.ctypes.data, count.ctypes.data, float(volume), float(rc), float(beta),
+                        float(coulomb_f), nb_shape(*shape), float(target))
+    rb, drift, fb = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    _check(lib().nb_buffer_estimate(ctx, ctypes.byref(q), int(mode), ctypes.byref(rb), ctypes.byref(drift),
+                                    ctypes.byref(fb)))
+    return rb.value, drift.value, bool(fb.value)
+
+
+# ------------------------------------------------------- instrumentation
+
+def nb_timing_enable(ctx, on=True):
+    _check(lib().nb_timing_enable(ctx, int(bool(on))))
+
+
+def nb_timing_read(ctx):
+    """{timer: (total_ms, launches)} since the last read (synchronous)."""
+    ms = (ctypes.c_double * NB_TIMER_COUNT)()
+    cnt = (ctypes.c_long * NB_TIMER_COUNT)()
+    _check(lib().nb_timing_read(ctx, ms, cnt))
+    names = ("force_kernel", "force_call", "grid_sort", "pairlist")
+    return {names[k]: (ms[k], cnt[k]) for k in range(NB_TIMER_COUNT)}
+
+
+def nb_list_stats(ctx, grid, lst, xyzq_now, rc):
+    """(listed pairs, real visited pairs, interacting pairs with r < rc, excluded pairs with r < rc)."""
+    c = (ctypes.c_longlong * 4)()
+    _check(lib().nb_list_stats(ctx, grid, lst, _ptr(xyzq_now), float(rc), c))
+    return tuple(int(v) for v in c)

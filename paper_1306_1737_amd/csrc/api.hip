@@ -1,0 +1,522 @@
+// C ABI entry points: argument validation, handle and storage management,
+// error reporting.  All numerical work is in the kernels of grid.hip,
+// pairlist.hip and forces.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace mxn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int ensure(DevBuf &b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return NB_OK;
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = bytes ? bytes : 16;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(NB_ERR_OOM, std::string("hipMalloc of ") + std::to_string(want) + " bytes: " + hipGetErrorString(e));
+    }
+    b.bytes = want;
+    return NB_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static hipEvent_t take_event(nb_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ScopedTimer::ScopedTimer(nb_ctx *c, int w) : ctx(c), which(w) {
+    if (!ctx->timing) return;
+    hipEvent_t start = take_event(ctx);
+    stop = take_event(ctx);
+    if (!start || !stop) {
+        stop = nullptr;
+        return;
+    }
+    hipEventRecord(start, ctx->stream);
+    ctx->timers[which].push_back({start, stop});
+}
+
+ScopedTimer::~ScopedTimer() {
+    if (stop) hipEventRecord(stop, ctx->stream);
+}
+
+double analytic_drift(const nb_buffer_query &q, double rb);
+int analytic_buffer(const nb_buffer_query &q, double *rb_out, double *drift_out);
+int validate_query(const nb_buffer_query *q);
+
+}  // namespace mxn
+
+using namespace mxn;
+
+#define CHECK(rc_expr)            \
+    do {                          \
+        int rc_ = (rc_expr);      \
+        if (rc_ != NB_OK) return rc_; \
+    } while (0)
+
+extern "C" {
+
+const char *nb_last_error(void) { return g_last_error.c_str(); }
+
+int nb_create(nb_ctx **ctx, int device, void *hip_stream) {
+    if (!ctx) return fail(NB_ERR_ARG, "nb_create: ctx is null");
+    *ctx = nullptr;
+    int ndev = 0;
+    MXN_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(NB_ERR_ARG, "nb_create: no such device");
+    MXN_HIP(hipSetDevice(device));
+    nb_ctx *c = new (std::nothrow) nb_ctx();
+    if (!c) return fail(NB_ERR_OOM, "nb_create: host allocation");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc(&c->d_flags, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_pinned, 16 * sizeof(int));
+    if (e != hipSuccess) {
+        if (c->d_flags) hipFree(c->d_flags);
+        delete c;
+        return fail(NB_ERR_HIP, std::string("nb_create: ") + hipGetErrorString(e));
+    }
+    *ctx = c;
+    return NB_OK;
+}
+
+void nb_destroy(nb_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto &v : c->timers)
+        for (auto &pr : v) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+    release(c->partials);
+    if (c->d_flags) hipFree(c->d_flags);
+    if (c->h_pinned) hipHostFree(c->h_pinned);
+    delete c;
+}
+
+int nb_set_stream(nb_ctx *c, void *hip_stream) {
+    if (!c) return fail(NB_ERR_ARG, "nb_set_stream: ctx is null");
+    c->stream = (hipStream_t)hip_stream;
+    return NB_OK;
+}
+
+int nb_sync(nb_ctx *c) {
+    if (!c) return fail(NB_ERR_ARG, "nb_sync: ctx is null");
+    MXN_HIP(hipSetDevice(c->device));
+    MXN_HIP(hipStreamSynchronize(c->stream));
+    int flags = 0;
+    MXN_HIP(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) MXN_HIP(hipMemset(c->d_flags, 0, sizeof(int)));
+    if (flags & FLAG_NONFINITE) return fail(NB_ERR_NONFINITE, "non-finite or out-of-range coordinate or charge");
+    if (flags & FLAG_OVERFLOW) return fail(NB_ERR_OVERFLOW, "pair-list capacity exceeded: rebuild the list");
+    return NB_OK;
+}
+
+// ------------------------------------------------------------------- grid
+
+static void grid_release(nb_grid *g) {
+    DevBuf *bufs[] = {&g->col_count, &g->col_start, &g->col_fill, &g->colbb, &g->atom_col, &g->atom_xw,
+                      &g->atom_img, &g->bucket, &g->xs, &g->xs_now, &g->type_s, &g->perm, &g->img_s,
+                      &g->slot_of, &g->bbi_lo, &g->bbi_hi, &g->bbj_lo, &g->bbj_hi, &g->nslots, &g->fs,
+                      &g->shiftvec};
+    for (DevBuf *b : bufs) release(*b);
+}
+
+int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const int *type, nb_shape shape,
+                 nb_grid **grid) {
+    if (!c || !box || !xyzq || !type || !grid) return fail(NB_ERR_ARG, "nb_grid_sort: null argument");
+    if (n < 1) return fail(NB_ERR_ARG, "nb_grid_sort: n must be >= 1");
+    const bool ok_shape = (shape.m == 4 && shape.n == 4) || (shape.m == 4 && shape.n == 8) ||
+                          (shape.m == 8 && shape.n == 8);
+    if (!ok_shape) return fail(NB_ERR_ARG, "nb_grid_sort: supported shapes are 4x4, 4x8, 8x8");
+    for (int d = 0; d < 3; ++d)
+        if (!(box[d] > 0.0) || !std::isfinite(box[d])) return fail(NB_ERR_ARG, "nb_grid_sort: bad box");
+    MXN_HIP(hipSetDevice(c->device));
+    nb_grid *g = *grid;
+    if (g && g->ctx != c) return fail(NB_ERR_STATE, "nb_grid_sort: grid belongs to another context");
+    bool fresh = false;
+    if (!g) {
+        g = new (std::nothrow) nb_grid();
+        if (!g) return fail(NB_ERR_OOM, "nb_grid_sort: host allocation");
+        g->ctx = c;
+        fresh = true;
+    }
+    g->n = n;
+    g->m = shape.m;
+    g->nn = shape.n;
+    g->cmin = shape.m < shape.n ? shape.m : shape.n;
+    g->cmax = shape.m > shape.n ? shape.m : shape.n;
+    for (int d = 0; d < 3; ++d) {
+        g->box[d] = box[d];
+        g->Lf[d] = (float)box[d];
+        g->invL[d] = 1.0 / (double)g->Lf[d];
+    }
+    // column grid: spacing (max(M,N)/rho)^(1/3), rho = n / V
+    const double rho = (double)n / (box[0] * box[1] * box[2]);
+    const double s = std::cbrt((double)g->cmax / rho);
+    g->spacing = s;
+    g->nx = (int)std::floor(box[0] / s);
+    g->ny = (int)std::floor(box[1] / s);
+    if (g->nx < 1) g->nx = 1;
+    if (g->ny < 1) g->ny = 1;
+    g->inv_x = (float)((double)g->nx / box[0]);
+    g->inv_y = (float)((double)g->ny / box[1]);
+    g->ncol = g->nx * g->ny;
+    long cap = (long)n + (long)g->ncol * (g->cmax - 1);
+    cap = (cap + g->cmax - 1) / g->cmax * g->cmax;
+    if (cap > (1L << 30)) return fail(NB_ERR_ARG, "nb_grid_sort: too many particles");
+    g->slots_cap = (int)cap;
+    const size_t nc = (size_t)g->ncol, ns = (size_t)cap, na = (size_t)n;
+    int rc = NB_OK;
+    rc = rc ? rc : ensure(g->col_count, nc * 4);
+    rc = rc ? rc : ensure(g->col_start, (nc + 1) * 4);
+    rc = rc ? rc : ensure(g->col_fill, nc * 4);
+    rc = rc ? rc : ensure(g->colbb, nc * 16);
+    rc = rc ? rc : ensure(g->atom_col, na * 4);
+    rc = rc ? rc : ensure(g->atom_xw, na * 16);
+    rc = rc ? rc : ensure(g->atom_img, na * 4);
+    rc = rc ? rc : ensure(g->slot_of, na * 4);
+    rc = rc ? rc : ensure(g->bucket, ns * 4);
+    rc = rc ? rc : ensure(g->xs, ns * 16);
+    rc = rc ? rc : ensure(g->xs_now, ns * 16);
+    rc = rc ? rc : ensure(g->type_s, ns * 4);
+    rc = rc ? rc : ensure(g->perm, ns * 4);
+    rc = rc ? rc : ensure(g->img_s, ns * 4);
+    rc = rc ? rc : ensure(g->bbi_lo, ns / g->m * 16);
+    rc = rc ? rc : ensure(g->bbi_hi, ns / g->m * 16);
+    if (g->nn != g->m) {
+        rc = rc ? rc : ensure(g->bbj_lo, ns / g->nn * 16);
+        rc = rc ? rc : ensure(g->bbj_hi, ns / g->nn * 16);
+    }
+    rc = rc ? rc : ensure(g->nslots, 16);
+    rc = rc ? rc : ensure(g->fs, ns * 3 * 4);
+    rc = rc ? rc : ensure(g->shiftvec, 32 * 16);
+    if (rc == NB_OK) {
+        ScopedTimer tm(c, NB_TIMER_GRID_SORT);
+        rc = launch_grid_sort(g, xyzq, type);
+    }
+    ++g->generation;
+    if (rc != NB_OK) {
+        if (fresh) {
+            grid_release(g);
+            delete g;
+        }
+        return rc;
+    }
+    *grid = g;
+    return NB_OK;
+}
+
+void nb_grid_free(nb_grid *g) {
+    if (!g) return;
+    hipSetDevice(g->ctx->device);
+    hipStreamSynchronize(g->ctx->stream);
+    grid_release(g);
+    delete g;
+}
+
+int nb_grid_info(nb_grid *g, nb_grid_info_t *info) {
+    if (!g || !info) return fail(NB_ERR_ARG, "nb_grid_info: null argument");
+    MXN_HIP(hipSetDevice(g->ctx->device));
+    int ns = 0;
+    MXN_HIP(hipMemcpyAsync(&ns, g->nslots.p, sizeof(int), hipMemcpyDeviceToHost, g->ctx->stream));
+    MXN_HIP(hipStreamSynchronize(g->ctx->stream));
+    info->n = g->n;
+    info->n_slots = ns;
+    info->m = g->m;
+    info->n_cl = g->nn;
+    info->nx = g->nx;
+    info->ny = g->ny;
+    info->n_ci = ns / g->m;
+    info->n_cj = ns / g->nn;
+    return NB_OK;
+}
+
+int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start, float *bb) {
+    nb_grid_info_t info;
+    CHECK(nb_grid_info(g, &info));
+    const int ns = info.n_slots;
+    if (perm) MXN_HIP(hipMemcpy(perm, g->perm.p, (size_t)ns * 4, hipMemcpyDeviceToHost));
+    if (xyzq) MXN_HIP(hipMemcpy(xyzq, g->xs.p, (size_t)ns * 16, hipMemcpyDeviceToHost));
+    if (img) {
+        int *packed = new (std::nothrow) int[g->n];
+        if (!packed) return fail(NB_ERR_OOM, "nb_grid_export: host allocation");
+        hipError_t e = hipMemcpy(packed, g->atom_img.p, (size_t)g->n * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            delete[] packed;
+            return fail(NB_ERR_HIP, hipGetErrorString(e));
+        }
+        for (int i = 0; i < g->n; ++i) {
+            img[3 * i] = (packed[i] & 1023) - 512;
+            img[3 * i + 1] = ((packed[i] >> 10) & 1023) - 512;
+            img[3 * i + 2] = ((packed[i] >> 20) & 1023) - 512;
+        }
+        delete[] packed;
+    }
+    if (col_start) MXN_HIP(hipMemcpy(col_start, g->col_start.p, (size_t)(g->ncol + 1) * 4, hipMemcpyDeviceToHost));
+    if (bb) {
+        const size_t nci = (size_t)info.n_ci;
+        float *lo = new (std::nothrow) float[nci * 8];
+        if (!lo) return fail(NB_ERR_OOM, "nb_grid_export: host allocation");
+        hipError_t e = hipMemcpy(lo, g->bbi_lo.p, nci * 16, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(lo + nci * 4, g->bbi_hi.p, nci * 16, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            delete[] lo;
+            return fail(NB_ERR_HIP, hipGetErrorString(e));
+        }
+        for (size_t k = 0; k < nci; ++k)
+            for (int d = 0; d < 4; ++d) {
+                bb[8 * k + d] = lo[4 * k + d];
+                bb[8 * k + 4 + d] = lo[nci * 4 + 4 * k + d];
+            }
+        delete[] lo;
+    }
+    return NB_OK;
+}
+
+// ------------------------------------------------------------------- list
+
+static void list_release(nb_list *l) {
+    DevBuf *bufs[] = {&l->entries, &l->items, &l->ci_count, &l->ci_icount, &l->ci_start, &l->ci_istart, &l->totals};
+    for (DevBuf *b : bufs) release(*b);
+}
+
+int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const int *excl_off, const int *excl_idx,
+                      int flags, nb_list **list) {
+    if (!c || !g || !excl_off || !excl_idx || !list) return fail(NB_ERR_ARG, "nb_pairlist_build: null argument");
+    if (g->ctx != c) return fail(NB_ERR_STATE, "nb_pairlist_build: grid belongs to another context");
+    if (!(rlist > 0.0f) || !std::isfinite(rlist)) return fail(NB_ERR_ARG, "nb_pairlist_build: rlist must be > 0");
+    if (flags & ~NB_LIST_ASYNC) return fail(NB_ERR_ARG, "nb_pairlist_build: unknown flag");
+    for (int d = 0; d < 3; ++d)
+        if (!((double)g->Lf[d] > 2.0 * (double)rlist))
+            return fail(NB_ERR_BOX, "nb_pairlist_build: every box edge must exceed 2*rlist");
+    MXN_HIP(hipSetDevice(c->device));
+    nb_list *l = *list;
+    bool fresh = false;
+    if (l && l->ctx != c) return fail(NB_ERR_STATE, "nb_pairlist_build: list belongs to another context");
+    if (!l) {
+        l = new (std::nothrow) nb_list();
+        if (!l) return fail(NB_ERR_OOM, "nb_pairlist_build: host allocation");
+        l->ctx = c;
+        fresh = true;
+    }
+    l->grid = g;
+    l->grid_generation = g->generation;
+    l->rlist = rlist;
+    l->rbb = rbb >= 0.0f ? rbb : (float)std::fmax(0.0, (double)rlist - 0.5 * g->spacing);
+    const int nci_cap = g->slots_cap / g->m;
+    int rc = NB_OK;
+    rc = rc ? rc : ensure(l->ci_count, (size_t)(nci_cap + 1) * 4);
+    rc = rc ? rc : ensure(l->ci_start, (size_t)(nci_cap + 1) * 4);
+    rc = rc ? rc : ensure(l->ci_istart, (size_t)(nci_cap + 1) * 4);
+    rc = rc ? rc : ensure(l->totals, 16);
+    if (rc == NB_OK && l->cap_entries == 0) {
+        // first estimate: 4x the sphere's half pairs over the cluster size, plus slack
+        const double rho = (double)g->n / (g->box[0] * g->box[1] * g->box[2]);
+        const double half = 2.0 / 3.0 * M_PI * (double)rlist * rlist * rlist * rho * g->n;
+        const long ce = (long)(4.0 * half / (g->m * g->nn)) + 16L * nci_cap + 1024;
+        const long cit = ce / kItemEntries + nci_cap + 256;
+        rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
+        rc = rc ? rc : ensure(l->items, (size_t)cit * 16);
+        if (rc == NB_OK) {
+            l->cap_entries = ce;
+            l->cap_items = cit;
+        }
+    }
+    if (rc == NB_OK) {
+        ScopedTimer tm(c, NB_TIMER_PAIRLIST);
+        rc = launch_pairlist(l, excl_off, excl_idx, !(flags & NB_LIST_ASYNC));
+    }
+    if (rc != NB_OK) {
+        if (fresh) {
+            list_release(l);
+            delete l;
+        }
+        return rc;
+    }
+    *list = l;
+    return NB_OK;
+}
+
+void nb_list_free(nb_list *l) {
+    if (!l) return;
+    hipSetDevice(l->ctx->device);
+    hipStreamSynchronize(l->ctx->stream);
+    list_release(l);
+    delete l;
+}
+
+int nb_list_info(nb_list *l, long *n_entries, long *n_items) {
+    if (!l) return fail(NB_ERR_ARG, "nb_list_info: null list");
+    MXN_HIP(hipSetDevice(l->ctx->device));
+    int t[4];
+    MXN_HIP(hipMemcpyAsync(t, l->totals.p, sizeof t, hipMemcpyDeviceToHost, l->ctx->stream));
+    MXN_HIP(hipStreamSynchronize(l->ctx->stream));
+    if (t[2] == 0 && t[1] > 0) return fail(NB_ERR_OVERFLOW, "nb_list_info: list overflowed its capacity");
+    if (n_entries) *n_entries = t[0];
+    if (n_items) *n_items = t[2];
+    return NB_OK;
+}
+
+int nb_list_export_canonical(nb_list *l, nb_entry *out, long cap, long *count) {
+    if (!l || (!out && cap > 0)) return fail(NB_ERR_ARG, "nb_list_export_canonical: null argument");
+    long ne = 0;
+    CHECK(nb_list_info(l, &ne, nullptr));
+    if (count) *count = ne;
+    const nb_grid *g = l->grid;
+    const int M = g->m, N = g->nn;
+    int ns = 0;
+    MXN_HIP(hipMemcpy(&ns, g->nslots.p, sizeof(int), hipMemcpyDeviceToHost));
+    const int nci = ns / M;
+    int *starts = new (std::nothrow) int[nci + 1];
+    nb_jentry *ent = new (std::nothrow) nb_jentry[ne > 0 ? ne : 1];
+    if (!starts || !ent) {
+        delete[] starts;
+        delete[] ent;
+        return fail(NB_ERR_OOM, "nb_list_export_canonical: host allocation");
+    }
+    hipError_t e = hipMemcpy(starts, l->ci_start.p, (size_t)(nci + 1) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ne > 0) e = hipMemcpy(ent, l->entries.p, (size_t)ne * sizeof(nb_jentry), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete[] starts;
+        delete[] ent;
+        return fail(NB_ERR_HIP, hipGetErrorString(e));
+    }
+    long k = 0;
+    for (int ci = 0; ci < nci; ++ci)
+        for (int j = starts[ci]; j < starts[ci + 1]; ++j, ++k) {
+            if (k >= cap) continue;
+            const uint64_t m = ((uint64_t)ent[j].mhi << 32) | ent[j].mlo;
+            uint64_t canon = 0;   // kernel order bit b*M + a -> canonical bit a*N + b
+            for (int b = 0; b < N; ++b)
+                for (int a = 0; a < M; ++a)
+                    if ((m >> (b * M + a)) & 1ull) canon |= 1ull << (a * N + b);
+            out[k].ci = ci;
+            out[k].shift = ent[j].shift;
+            out[k].cj = ent[j].cj;
+            out[k].pad = 0;
+            out[k].mask = canon;
+        }
+    delete[] starts;
+    delete[] ent;
+    return NB_OK;
+}
+
+// ----------------------------------------------------------------- forces
+
+int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
+              unsigned flags, float *f, double *energy, double *virial) {
+    if (!c || !g || !l || !xyzq_now || !p || !f) return fail(NB_ERR_ARG, "nb_forces: null argument");
+    if (g->ctx != c || l->ctx != c || l->grid != g) return fail(NB_ERR_STATE, "nb_forces: grid/list/context mismatch");
+    if (l->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, "nb_forces: the list was built before the grid's last sort: rebuild it");
+    if (flags & ~(unsigned)(NB_ENERGY | NB_VIRIAL | NB_ACC_FP32 | NB_ACCUMULATE))
+        return fail(NB_ERR_ARG, "nb_forces: unknown flag");
+    if ((flags & NB_ENERGY) && !energy) return fail(NB_ERR_ARG, "nb_forces: energy output is null");
+    if ((flags & NB_VIRIAL) && !virial) return fail(NB_ERR_ARG, "nb_forces: virial output is null");
+    if (!p->c6c12 || p->ntypes < 1 || p->ntypes > kMaxTypes) return fail(NB_ERR_ARG, "nb_forces: ntypes must be 1..32");
+    if (!(p->rc > 0.0f) || !(p->rc <= l->rlist)) return fail(NB_ERR_ARG, "nb_forces: need 0 < rc <= rlist");
+    if (!(p->beta >= 0.0f) || !std::isfinite(p->coulomb_f)) return fail(NB_ERR_ARG, "nb_forces: bad beta/coulomb_f");
+    if ((double)p->beta * p->rc > 4.0)
+        return fail(NB_ERR_UNSUPPORTED, "nb_forces: beta*rc > 4 is outside the fitted Ewald range");
+    MXN_HIP(hipSetDevice(c->device));
+    ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
+    return launch_forces(c, g, l, xyzq_now, p, flags, f, energy, virial);
+}
+
+// -------------------------------------------------------- instrumentation
+
+int nb_list_stats(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc, long long *counts) {
+    if (!c || !g || !l || !xyzq_now || !counts) return fail(NB_ERR_ARG, "nb_list_stats: null argument");
+    if (g->ctx != c || l->ctx != c || l->grid != g || l->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, "nb_list_stats: grid/list/context mismatch");
+    if (!(rc > 0.0f)) return fail(NB_ERR_ARG, "nb_list_stats: rc must be > 0");
+    MXN_HIP(hipSetDevice(c->device));
+    unsigned long long *d = nullptr;
+    MXN_HIP(hipMalloc(&d, 4 * sizeof(unsigned long long)));
+    hipError_t e = hipMemsetAsync(d, 0, 4 * sizeof(unsigned long long), c->stream);
+    int rc_ = e == hipSuccess ? launch_stats(c, g, l, xyzq_now, rc, d) : NB_ERR_HIP;
+    unsigned long long h[4] = {0, 0, 0, 0};
+    if (rc_ == NB_OK) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipFree(d);
+    if (rc_ != NB_OK) return rc_;
+    if (e != hipSuccess) return fail(NB_ERR_HIP, hipGetErrorString(e));
+    long ne = 0;
+    CHECK(nb_list_info(const_cast<nb_list *>(l), &ne, nullptr));
+    counts[0] = (long long)ne * g->m * g->nn;
+    counts[1] = (long long)h[0];
+    counts[2] = (long long)h[1];
+    counts[3] = (long long)h[2];
+    return NB_OK;
+}
+
+int nb_timing_enable(nb_ctx *c, int on) {
+    if (!c) return fail(NB_ERR_ARG, "nb_timing_enable: ctx is null");
+    c->timing = on != 0;
+    return NB_OK;
+}
+
+int nb_timing_read(nb_ctx *c, double *ms, long *launches) {
+    if (!c || !ms || !launches) return fail(NB_ERR_ARG, "nb_timing_read: null argument");
+    MXN_HIP(hipSetDevice(c->device));
+    MXN_HIP(hipStreamSynchronize(c->stream));
+    for (int t = 0; t < NB_TIMER_COUNT; ++t) {
+        double sum = 0.0;
+        for (auto &pr : c->timers[t]) {
+            float el = 0.0f;
+            if (hipEventElapsedTime(&el, pr.first, pr.second) == hipSuccess) sum += el;
+            c->event_pool.push_back(pr.first);
+            c->event_pool.push_back(pr.second);
+        }
+        ms[t] = sum;
+        launches[t] = (long)c->timers[t].size();
+        c->timers[t].clear();
+    }
+    return NB_OK;
+}
+
+// ------------------------------------------------------------ buffer size
+
+int nb_buffer_estimate(nb_ctx *c, const nb_buffer_query *q, int mode, double *rb_out, double *drift_out,
+                       int *used_fallback) {
+    (void)c;
+    CHECK(validate_query(q));
+    if (!rb_out) return fail(NB_ERR_ARG, "nb_buffer_estimate: rb_out is null");
+    if (mode != NB_BUFFER_ANALYTIC && mode != NB_BUFFER_MLP && mode != NB_BUFFER_AUTO)
+        return fail(NB_ERR_ARG, "nb_buffer_estimate: unknown mode");
+    if (used_fallback) *used_fallback = mode != NB_BUFFER_ANALYTIC;
+    return analytic_buffer(*q, rb_out, drift_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,416 @@
+// M x N cluster-pair force kernels (Sec. 3 "Pair interaction kernels"; Eq. 1
+// Lennard-Jones, Eq. 2 Coulomb with the Ewald real-space correction; Sec. 2.4
+// exclusions) plus the per-step coordinate gather and force scatter.
+//
+// Wavefront mapping on gfx950 (wave64): a wavefront owns one work item, i.e.
+// up to 32 consecutive j-entries of one i-cluster.  Its M i-particles are
+// wave-uniform (scalar registers); each of the 64 lanes owns one j-particle of
+// one entry (64/N entries per pass) and loops over the M i-particles, so each
+// lane evaluates M pair interactions per pass with no cross-lane traffic:
+// j-forces stay in the lane and are added to memory once per entry with
+// coalesced atomics (the N lanes of an entry cover N consecutive slots);
+// i-forces stay in registers for the whole item and are reduced across the
+// wavefront once at its end.  The image shift is applied to the j-particle,
+// so entries of different shifts can share a pass.
+//
+// Pair math (FP32): r^-1 from the hardware reciprocal square root;
+// exp(-beta^2 r^2) from the hardware exp2; erfc(beta r) = exp(-beta^2 r^2) *
+// P(u)/Q(u) with a project-fitted rational approximation of erfcx on [0, 4]
+// (see fit_ewald.py).  Energies and the virial are accumulated per lane in
+// FP64 (or FP32 for the precision study) and reduced deterministically.
+#include <type_traits>
+
+#include "ewald_fit.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int kNAcc = 11;   // per work item: E_LJ, E_Coulomb, virial[9]
+
+struct ForceArgs {
+    const int *nslots, *perm, *img_s, *slot_of, *type_s;
+    const float4 *xyzq_now;
+    float4 *xs_now;
+    float *fs;
+    int slots_cap, n;
+    const int4 *items;
+    const nb_jentry *entries;
+    const int *totals;
+    const float4 *shiftvec;
+    const float *c6c12;
+    int nt, shift_en;
+    float rc2, beta, c_exp, c2bpi, coulomb_f, shiftC, rc6inv;
+    float Lx, Ly, Lz;
+    double *partials;
+    float *f_out;
+    int accumulate;
+    int *flags;
+    int nblocks_x8;   // launched blocks / 8 (XCD-contiguous remap)
+};
+
+__global__ void k_gather(ForceArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *a.nslots) return;
+    const int o = a.perm[s];
+    if (o >= 0) {
+        float4 p = a.xyzq_now[o];
+        const int im = a.img_s[s];
+        if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(a.flags, mxn::FLAG_NONFINITE);
+        p.x -= (float)((im & 1023) - 512) * a.Lx;
+        p.y -= (float)(((im >> 10) & 1023) - 512) * a.Ly;
+        p.z -= (float)(((im >> 20) & 1023) - 512) * a.Lz;
+        a.xs_now[s] = p;
+    }
+    a.fs[s] = 0.0f;
+    a.fs[a.slots_cap + s] = 0.0f;
+    a.fs[2 * a.slots_cap + s] = 0.0f;
+}
+
+__global__ void k_scatter(ForceArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int s = a.slot_of[i];
+    float fx = a.fs[s], fy = a.fs[a.slots_cap + s], fz = a.fs[2 * a.slots_cap + s];
+    if (a.accumulate) {
+        fx += a.f_out[3 * i]; fy += a.f_out[3 * i + 1]; fz += a.f_out[3 * i + 2];
+    }
+    a.f_out[3 * i] = fx;
+    a.f_out[3 * i + 1] = fy;
+    a.f_out[3 * i + 2] = fz;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int M, int N, bool ENER, bool VIR, bool ACC64>
+__global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
+    extern __shared__ float4 smem[];
+    float4 *svec = smem;        // 27 image shift vectors
+    float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
+    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
+    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
+        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
+        ljt[t] = make_float4(c6, c12, sh, 0.0f);
+    }
+    __syncthreads();
+
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    constexpr int B = 64 / N;                      // entries per pass
+    constexpr unsigned FULL = (1u << M) - 1u;
+    const int lane = threadIdx.x & 63;
+    const int logical = (blockIdx.x % 8) * a.nblocks_x8 + blockIdx.x / 8;
+    const int item = logical * 4 + (threadIdx.x >> 6);
+    if (item >= a.totals[2]) return;
+    const int4 it = a.items[item];
+    const int ci = __builtin_amdgcn_readfirstlane(it.x);
+    const int js = __builtin_amdgcn_readfirstlane(it.y);
+    const int je = __builtin_amdgcn_readfirstlane(it.z);
+
+    float xi[M], yi[M], zi[M], qi[M];
+    int ti[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const float4 p = a.xs_now[ci * M + k];
+        xi[k] = p.x; yi[k] = p.y; zi[k] = p.z;
+        qi[k] = p.w * a.coulomb_f;
+        const int t = a.type_s[ci * M + k];
+        ti[k] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;   // types outside [0, ntypes) are clamped
+    }
+    float fix[M], fiy[M], fiz[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
+    acc_t elj = 0, ec = 0;
+    acc_t vir[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vir[k] = 0;
+
+    const int jb = lane % N, eo = lane / N;
+    for (int e0 = js; e0 < je; e0 += B) {
+        const int e = e0 + eo;
+        const bool valid = e < je;
+        const nb_jentry en = a.entries[valid ? e : e0];
+        const int jslot = en.cj * N + jb;
+        const float4 pj = a.xs_now[jslot];
+        const int tj = min(max(a.type_s[jslot], 0), a.nt - 1);
+        const float4 sv = svec[en.shift];
+        const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
+        const float qj = pj.w;
+        const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
+        const unsigned mb = (unsigned)(m64 >> (jb * M)) & FULL;
+        unsigned act = FULL;
+        if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
+            const int t = jslot - ci * M;
+            act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
+        }
+        if (!valid) act = 0u;
+        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < a.rc2 && ((act >> k) & 1u)) {
+                const bool bit = (mb >> k) & 1u;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float rinv2 = rinv * rinv;
+                const float u = r2 * rinv * a.beta;
+                const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+                const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
+                const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1),
+                                     u, 1.0f);
+                const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
+                const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+                const float vc = em * rinv;
+                const float qq = qi[k] * qj;
+                float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+                const float4 lj = ljt[ti[k] + tj];
+                const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
+                const float rinv6 = rinv2 * rinv2 * rinv2;
+                const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
+                fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+                fix[k] = fmaf(fsc, dx, fix[k]);
+                fiy[k] = fmaf(fsc, dy, fiy[k]);
+                fiz[k] = fmaf(fsc, dz, fiz[k]);
+                fjx = fmaf(-fsc, dx, fjx);
+                fjy = fmaf(-fsc, dy, fjy);
+                fjz = fmaf(-fsc, dz, fjz);
+                if (ENER) {
+                    elj += (acc_t)(t12 - t6 - (bit ? lj.z : 0.0f));
+                    ec += (acc_t)(qq * (vc - (bit ? a.shiftC : 0.0f)));
+                }
+            }
+        }
+        if (valid) {
+            unsafeAtomicAdd(a.fs + jslot, fjx);
+            unsafeAtomicAdd(a.fs + a.slots_cap + jslot, fjy);
+            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + jslot, fjz);
+        }
+        if (VIR) {
+            vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
+            vir[3] += (acc_t)(yj * fjx); vir[4] += (acc_t)(yj * fjy); vir[5] += (acc_t)(yj * fjz);
+            vir[6] += (acc_t)(zj * fjx); vir[7] += (acc_t)(zj * fjy); vir[8] += (acc_t)(zj * fjz);
+        }
+    }
+    // i-forces: one reduction across the wavefront per work item
+    acc_t viri[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) viri[k] = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const float fx = wave_sum(fix[k]), fy = wave_sum(fiy[k]), fz = wave_sum(fiz[k]);
+        if (lane == 0) {
+            const int s = ci * M + k;
+            unsafeAtomicAdd(a.fs + s, fx);
+            unsafeAtomicAdd(a.fs + a.slots_cap + s, fy);
+            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + s, fz);
+            if (VIR) {
+                viri[0] += (acc_t)xi[k] * (acc_t)fx; viri[1] += (acc_t)xi[k] * (acc_t)fy; viri[2] += (acc_t)xi[k] * (acc_t)fz;
+                viri[3] += (acc_t)yi[k] * (acc_t)fx; viri[4] += (acc_t)yi[k] * (acc_t)fy; viri[5] += (acc_t)yi[k] * (acc_t)fz;
+                viri[6] += (acc_t)zi[k] * (acc_t)fx; viri[7] += (acc_t)zi[k] * (acc_t)fy; viri[8] += (acc_t)zi[k] * (acc_t)fz;
+            }
+        }
+    }
+    if (ENER || VIR) {
+        acc_t out[kNAcc];
+        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[1] = ENER ? wave_sum(ec) : (acc_t)0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
+        if (lane == 0)
+            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)item * kNAcc + k] = (double)out[k];
+    }
+}
+
+// Deterministic reduction of the per-item partials: fixed assignment of items
+// to threads and a fixed tree.  FP64 or (precision study) FP32 throughout.
+template <bool ACC64>
+__global__ __launch_bounds__(1024) void k_reduce(const double *partials, const int *totals, double *energy,
+                                                 double *virial, int ener, int vir) {
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    __shared__ acc_t red[1024];
+    const int t = threadIdx.x;
+    const int n = totals[2];
+    for (int k = 0; k < kNAcc; ++k) {
+        acc_t s = 0;
+        for (int i = t; i < n; i += 1024) s += (acc_t)partials[(size_t)i * kNAcc + k];
+        red[t] = s;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            if (k < 2 && ener) energy[k] = (double)red[0];
+            if (k >= 2 && vir) virial[k - 2] = (double)red[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Pair statistics of a list at the current positions (the paper's effective
+// pair ratio, Sec. 5): c[0] real listed pairs (active mask/triangle), c[1]
+// interacting pairs within rc, c[2] excluded pairs within rc.
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_stats(ForceArgs a, unsigned long long *c) {
+    constexpr int B = 64 / N;
+    constexpr unsigned FULL = (1u << M) - 1u;
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= a.totals[2]) return;
+    const int4 it = a.items[item];
+    const int ci = it.x;
+    unsigned long long real = 0, inr = 0, exc = 0;
+    const int jb = lane % N, eo = lane / N;
+    for (int e0 = it.y; e0 < it.z; e0 += B) {
+        const int e = e0 + eo;
+        if (e >= it.z) continue;
+        const nb_jentry en = a.entries[e];
+        const int jslot = en.cj * N + jb;
+        const float4 pj = a.xs_now[jslot];
+        const float4 sv = a.shiftvec[en.shift];
+        const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
+        const unsigned mb = (unsigned)(m64 >> (jb * M)) & FULL;
+        unsigned act = FULL;
+        if (en.shift == 13) {
+            const int t = jslot - ci * M;
+            act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
+        }
+        for (int k = 0; k < M; ++k) {
+            if (!((act >> k) & 1u) || a.perm[ci * M + k] < 0 || a.perm[jslot] < 0) continue;
+            ++real;
+            const float4 pi = a.xs_now[ci * M + k];
+            const float dx = pi.x - (pj.x - sv.x), dy = pi.y - (pj.y - sv.y), dz = pi.z - (pj.z - sv.z);
+            if (dx * dx + dy * dy + dz * dz < a.rc2) {
+                if ((mb >> k) & 1u) ++inr;
+                else ++exc;
+            }
+        }
+    }
+    real = wave_sum(real); inr = wave_sum(inr); exc = wave_sum(exc);
+    if (lane == 0) {
+        atomicAdd(c, real);
+        atomicAdd(c + 1, inr);
+        atomicAdd(c + 2, exc);
+    }
+}
+
+template <int M, int N, bool E, bool V, bool D>
+void launch_k(const ForceArgs &a, int nb, size_t lds, hipStream_t st) {
+    k_forces<M, N, E, V, D><<<nb, 256, lds, st>>>(a);
+}
+
+template <int M, int N>
+void launch_shape(const ForceArgs &a, unsigned flags, int nb, size_t lds, hipStream_t st) {
+    const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL, D = !(flags & NB_ACC_FP32);
+    if (E && V && D) launch_k<M, N, true, true, true>(a, nb, lds, st);
+    else if (E && V) launch_k<M, N, true, true, false>(a, nb, lds, st);
+    else if (E && D) launch_k<M, N, true, false, true>(a, nb, lds, st);
+    else if (E) launch_k<M, N, true, false, false>(a, nb, lds, st);
+    else if (V && D) launch_k<M, N, false, true, true>(a, nb, lds, st);
+    else if (V) launch_k<M, N, false, true, false>(a, nb, lds, st);
+    else launch_k<M, N, false, false, true>(a, nb, lds, st);
+}
+
+}  // namespace
+
+namespace mxn {
+
+int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc,
+                 unsigned long long *d_counts) {
+    hipStream_t st = ctx->stream;
+    ForceArgs a{};
+    a.nslots = (const int *)g->nslots.p;
+    a.perm = (const int *)g->perm.p;
+    a.img_s = (const int *)g->img_s.p;
+    a.slot_of = (const int *)g->slot_of.p;
+    a.type_s = (const int *)g->type_s.p;
+    a.xyzq_now = (const float4 *)xyzq_now;
+    a.xs_now = (float4 *)g->xs_now.p;
+    a.fs = (float *)g->fs.p;
+    a.slots_cap = g->slots_cap;
+    a.n = g->n;
+    a.items = (const int4 *)l->items.p;
+    a.entries = (const nb_jentry *)l->entries.p;
+    a.totals = (const int *)l->totals.p;
+    a.shiftvec = (const float4 *)g->shiftvec.p;
+    a.rc2 = rc * rc;
+    a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
+    a.flags = ctx->d_flags;
+    k_gather<<<(g->slots_cap + 255) / 256, 256, 0, st>>>(a);
+    const int nb = (int)((l->cap_items + 3) / 4) + 1;
+    if (g->m == 4 && g->nn == 4) k_stats<4, 4><<<nb, 256, 0, st>>>(a, d_counts);
+    else if (g->m == 4 && g->nn == 8) k_stats<4, 8><<<nb, 256, 0, st>>>(a, d_counts);
+    else k_stats<8, 8><<<nb, 256, 0, st>>>(a, d_counts);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
+                  unsigned flags, float *f, double *energy, double *virial) {
+    hipStream_t st = ctx->stream;
+    const bool need_acc = flags & (NB_ENERGY | NB_VIRIAL);
+    if (need_acc) {
+        int rc = ensure(ctx->partials, (size_t)(l->cap_items + 4) * kNAcc * sizeof(double));
+        if (rc) return rc;
+    }
+    ForceArgs a{};
+    a.nslots = (const int *)g->nslots.p;
+    a.perm = (const int *)g->perm.p;
+    a.img_s = (const int *)g->img_s.p;
+    a.slot_of = (const int *)g->slot_of.p;
+    a.type_s = (const int *)g->type_s.p;
+    a.xyzq_now = (const float4 *)xyzq_now;
+    a.xs_now = (float4 *)g->xs_now.p;
+    a.fs = (float *)g->fs.p;
+    a.slots_cap = g->slots_cap;
+    a.n = g->n;
+    a.items = (const int4 *)l->items.p;
+    a.entries = (const nb_jentry *)l->entries.p;
+    a.totals = (const int *)l->totals.p;
+    a.shiftvec = (const float4 *)g->shiftvec.p;
+    a.c6c12 = p->c6c12;
+    a.nt = p->ntypes;
+    a.shift_en = p->shift_energies;
+    a.rc2 = p->rc * p->rc;
+    a.beta = p->beta;
+    a.c_exp = (float)(-(double)p->beta * (double)p->beta * 1.4426950408889634);
+    a.c2bpi = (float)(2.0 * (double)p->beta / 1.7724538509055160);
+    a.coulomb_f = p->coulomb_f;
+    a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
+    a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
+    a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
+    a.partials = (double *)ctx->partials.p;
+    a.f_out = f;
+    a.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
+    a.flags = ctx->d_flags;
+    k_gather<<<(g->slots_cap + 255) / 256, 256, 0, st>>>(a);
+    const long nwaves = l->cap_items;
+    int nb = (int)((nwaves + 3) / 4);
+    nb = (nb + 7) / 8 * 8;
+    if (nb == 0) nb = 8;
+    a.nblocks_x8 = nb / 8;
+    const size_t lds = (32 + (size_t)p->ntypes * p->ntypes) * sizeof(float4);
+    {
+        ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
+        if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, st);
+        else if (g->m == 4 && g->nn == 8) launch_shape<4, 8>(a, flags, nb, lds, st);
+        else launch_shape<8, 8>(a, flags, nb, lds, st);
+    }
+    k_scatter<<<(g->n + 255) / 256, 256, 0, st>>>(a);
+    if (need_acc) {
+        if (flags & NB_ACC_FP32)
+            k_reduce<false><<<1, 1024, 0, st>>>(a.partials, a.totals, energy, virial, flags & NB_ENERGY,
+                                                flags & NB_VIRIAL);
+        else
+            k_reduce<true><<<1, 1024, 0, st>>>(a.partials, a.totals, energy, virial, flags & NB_ENERGY,
+                                               flags & NB_VIRIAL);
+    }
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+}  // namespace mxn

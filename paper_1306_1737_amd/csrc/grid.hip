@@ -1,0 +1,250 @@
+// Grid sort and bounding boxes (Sec. 2.3 "Pair list construction": x/y column
+// grid, pigeonhole sort into columns, z order inside a column, dummy padding,
+// per-cluster bounding boxes).
+//
+// This file is compiled with -ffp-contract=off: the wrapped coordinates, the
+// column index and the bounding boxes are defined by separately rounded FP32
+// operations and must be bit-reproducible.
+#include <cmath>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kImgBias = 512;
+
+__device__ inline unsigned sortable(float z) {
+    unsigned u = __float_as_uint(z);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+struct WrapArgs {
+    const float4 *xyzq;
+    int n;
+    float Lx, Ly, Lz;
+    double ilx, ily, ilz;
+    float inv_x, inv_y;
+    int nx, ny;
+    int *col_count, *atom_col, *atom_img;
+    float4 *atom_xw;
+    int *flags;
+};
+
+__device__ inline float wrap1(float x, float L, double il, int &k, bool &bad) {
+    double kd = floor((double)x * il);
+    if (!(kd > -kImgBias && kd < kImgBias)) {   // also catches NaN
+        bad = true;
+        kd = 0.0;
+    }
+    k = (int)kd;
+    float kl = (float)k * L;
+    float w = x - kl;
+    return w + 0.0f;   // -0 -> +0
+}
+
+// per particle: periodic wrap, image count, column, column histogram
+__global__ void k_wrap_count(WrapArgs a) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    float4 p = a.xyzq[i];
+    bool bad = !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w));
+    int kx, ky, kz;
+    float wx = wrap1(p.x, a.Lx, a.ilx, kx, bad);
+    float wy = wrap1(p.y, a.Ly, a.ily, ky, bad);
+    float wz = wrap1(p.z, a.Lz, a.ilz, kz, bad);
+    if (bad) atomicOr(a.flags, mxn::FLAG_NONFINITE);
+    int cx = (int)floorf(wx * a.inv_x);
+    int cy = (int)floorf(wy * a.inv_y);
+    cx = cx < 0 ? 0 : (cx > a.nx - 1 ? a.nx - 1 : cx);
+    cy = cy < 0 ? 0 : (cy > a.ny - 1 ? a.ny - 1 : cy);
+    int col = cx * a.ny + cy;
+    a.atom_col[i] = col;
+    a.atom_img[i] = (kx + kImgBias) | ((ky + kImgBias) << 10) | ((kz + kImgBias) << 20);
+    a.atom_xw[i] = make_float4(wx, wy, wz, p.w);
+    atomicAdd(&a.col_count[col], 1);
+}
+
+// scatter particle indices into their column's slot range (arbitrary order within a column)
+__global__ void k_bucket(int n, const int *atom_col, const int *col_start, int *col_fill, int *bucket) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = atom_col[i];
+    int pos = atomicAdd(&col_fill[c], 1);
+    bucket[col_start[c] + pos] = i;
+}
+
+struct SortArgs {
+    const int *col_count, *col_start, *bucket, *type, *atom_img;
+    const float4 *atom_xw;
+    float4 *xs, *xs_now, *colbb;
+    int *type_s, *perm, *img_s, *slot_of;
+};
+
+// One workgroup per column: rank every particle by (z, original index) among
+// the column's particles (keys streamed through LDS in tiles), write the
+// sorted slot arrays, pad with dummies and reduce the column's x/y extent.
+constexpr int kSortThreads = 256;
+constexpr int kSortTile = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void k_col_sort(SortArgs a) {
+    __shared__ unsigned long long tile[kSortTile];
+    __shared__ float red[4][kSortThreads];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int start = a.col_start[c], nc = a.col_count[c], end = a.col_start[c + 1];
+    float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    for (int mine = 0; mine < nc; mine += kSortThreads) {
+        int j = mine + tid;
+        unsigned long long key = ~0ull;
+        int orig = -1;
+        if (j < nc) {
+            orig = a.bucket[start + j];
+            key = ((unsigned long long)sortable(a.atom_xw[orig].z) << 32) | (unsigned)orig;
+        }
+        int rank = 0;
+        for (int t0 = 0; t0 < nc; t0 += kSortTile) {
+            __syncthreads();
+            for (int k = tid; k < kSortTile && t0 + k < nc; k += kSortThreads) {
+                int o = a.bucket[start + t0 + k];
+                tile[k] = ((unsigned long long)sortable(a.atom_xw[o].z) << 32) | (unsigned)o;
+            }
+            __syncthreads();
+            int lim = nc - t0 < kSortTile ? nc - t0 : kSortTile;
+            if (j < nc)
+                for (int k = 0; k < lim; ++k) rank += tile[k] < key;
+        }
+        if (j < nc) {
+            int slot = start + rank;
+            float4 p = a.atom_xw[orig];
+            a.xs[slot] = p;
+            a.xs_now[slot] = p;
+            a.type_s[slot] = a.type[orig];
+            a.perm[slot] = orig;
+            a.img_s[slot] = a.atom_img[orig];
+            a.slot_of[orig] = slot;
+            mnx = fminf(mnx, p.x); mny = fminf(mny, p.y);
+            mxx = fmaxf(mxx, p.x); mxy = fmaxf(mxy, p.y);
+        }
+    }
+    // dummies: no charge, type 0 (never used: their mask bits are 0), distinct far positions
+    for (int slot = start + nc + tid; slot < end; slot += kSortThreads) {
+        float4 d = make_float4(-1000.0f - 4.0f * (float)(slot & 1023), -1000.0f - 4.0f * (float)((slot >> 10) & 1023),
+                               -1000.0f - 4.0f * (float)(slot >> 20), 0.0f);
+        a.xs[slot] = d;
+        a.xs_now[slot] = d;
+        a.type_s[slot] = 0;
+        a.perm[slot] = -1;
+        a.img_s[slot] = kImgBias | (kImgBias << 10) | (kImgBias << 20);
+    }
+    red[0][tid] = mnx; red[1][tid] = mny; red[2][tid] = mxx; red[3][tid] = mxy;
+    __syncthreads();
+    for (int s = kSortThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[0][tid] = fminf(red[0][tid], red[0][tid + s]);
+            red[1][tid] = fminf(red[1][tid], red[1][tid + s]);
+            red[2][tid] = fmaxf(red[2][tid], red[2][tid + s]);
+            red[3][tid] = fmaxf(red[3][tid], red[3][tid + s]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) a.colbb[c] = make_float4(red[0][0], red[1][0], red[2][0], red[3][0]);
+}
+
+// per cluster of `size` slots: min/max over real particles (inf/-inf if none)
+__global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi) {
+    int cl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= *nslots / size) return;
+    float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    for (int s = cl * size; s < cl * size + size; ++s) {
+        if (perm[s] < 0) continue;
+        float4 p = xs[s];
+        l.x = fminf(l.x, p.x); l.y = fminf(l.y, p.y); l.z = fminf(l.z, p.z);
+        h.x = fmaxf(h.x, p.x); h.y = fmaxf(h.y, p.y); h.z = fmaxf(h.z, p.z);
+    }
+    lo[cl] = l;
+    hi[cl] = h;
+}
+
+// Exclusive scan on one workgroup of 1024 threads, each owning a contiguous
+// chunk; mode 0: values as is, 1: rounded up to a multiple of p, 2: ceil(v/p).
+__global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, int mode, int p, int *total) {
+    __shared__ int sums[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk, e = min(n, b + chunk);
+    auto tr = [&](int v) { return mode == 0 ? v : (mode == 1 ? (v + p - 1) / p * p : (v + p - 1) / p); };
+    int s = 0;
+    for (int i = b; i < e; ++i) s += tr(in[i]);
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int run = sums[t] - s;
+    for (int i = b; i < e; ++i) {
+        out[i] = run;
+        run += tr(in[i]);
+    }
+    if (t == 1023) {
+        out[n] = sums[1023];
+        if (total) *total = sums[1023];
+    }
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_shiftvec(float4 *sv, float Lx, float Ly, float Lz) {
+    int s = threadIdx.x;
+    if (s < 27) sv[s] = make_float4((float)(s / 9 - 1) * Lx, (float)((s / 3) % 3 - 1) * Ly, (float)(s % 3 - 1) * Lz, 0.0f);
+}
+
+inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+namespace mxn {
+
+void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s) {
+    k_scan<<<1, 1024, 0, s>>>(in, out, n, 0, 1, total);
+}
+
+void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, hipStream_t s) {
+    k_scan<<<1, 1024, 0, s>>>(in, out, n, mode, p, total);
+}
+
+int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
+    hipStream_t st = g->ctx->stream;
+    const int n = g->n, ncol = g->ncol;
+    k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_count.p, ncol, 0);
+    k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_fill.p, ncol, 0);
+    WrapArgs w{(const float4 *)xyzq, n, g->Lf[0], g->Lf[1], g->Lf[2], g->invL[0], g->invL[1], g->invL[2],
+               g->inv_x, g->inv_y, g->nx, g->ny, (int *)g->col_count.p, (int *)g->atom_col.p,
+               (int *)g->atom_img.p, (float4 *)g->atom_xw.p, g->ctx->d_flags};
+    k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
+    k_scan<<<1, 1024, 0, st>>>((const int *)g->col_count.p, (int *)g->col_start.p, ncol, 1, g->cmax,
+                               (int *)g->nslots.p);
+    k_bucket<<<blocks(n, 256), 256, 0, st>>>(n, (const int *)g->atom_col.p, (const int *)g->col_start.p,
+                                             (int *)g->col_fill.p, (int *)g->bucket.p);
+    SortArgs s{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
+               (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
+               (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p, (int *)g->slot_of.p};
+    k_col_sort<<<ncol, kSortThreads, 0, st>>>(s);
+    k_bb<<<blocks(g->slots_cap / g->m, 256), 256, 0, st>>>((const int *)g->nslots.p, g->m, (const float4 *)g->xs.p,
+                                                          (const int *)g->perm.p, (float4 *)g->bbi_lo.p,
+                                                          (float4 *)g->bbi_hi.p);
+    if (g->nn != g->m)
+        k_bb<<<blocks(g->slots_cap / g->nn, 256), 256, 0, st>>>((const int *)g->nslots.p, g->nn,
+                                                                (const float4 *)g->xs.p, (const int *)g->perm.p,
+                                                                (float4 *)g->bbj_lo.p, (float4 *)g->bbj_hi.p);
+    k_shiftvec<<<1, 32, 0, st>>>((float4 *)g->shiftvec.p, g->Lf[0], g->Lf[1], g->Lf[2]);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+}  // namespace mxn

@@ -1,0 +1,117 @@
+// Internal declarations of the MI355X cluster-pair library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mxn.h"
+
+namespace mxn {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+#define MXN_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ::mxn::fail(e_ == hipErrorOutOfMemory ? NB_ERR_OOM : NB_ERR_HIP,                \
+                               std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+// bits latched by kernels in ctx->d_flags
+enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2 };
+
+// work items of the force kernel hold at most this many j-entries of one i-cluster
+constexpr int kItemEntries = 32;
+constexpr int kMaxTypes = 32;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+int ensure(DevBuf &b, size_t bytes);   // grow-only device allocation
+void release(DevBuf &b);
+
+}  // namespace mxn
+
+// Cluster-pair list entry as the kernels use it (16 bytes): j-cluster, image
+// shift index, and the M*N mask in j-major bit order (bit b*M + a).
+struct nb_jentry {
+    int cj;
+    int shift;
+    uint32_t mlo, mhi;
+};
+
+struct nb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int *d_flags = nullptr;     // latched kernel errors
+    int *h_pinned = nullptr;    // pinned host scratch (16 ints)
+    mxn::DevBuf partials;       // per-work-item energy/virial partials
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timers[NB_TIMER_COUNT];
+    std::vector<hipEvent_t> event_pool;
+};
+
+struct nb_grid {
+    nb_ctx *ctx = nullptr;
+    int n = 0, m = 0, nn = 0, cmin = 0, cmax = 0;
+    int nx = 0, ny = 0, ncol = 0;
+    int slots_cap = 0;          // n + ncol*(cmax-1): upper bound of the padded slot count
+    double box[3] = {0, 0, 0};
+    float Lf[3] = {0, 0, 0};
+    double invL[3] = {0, 0, 0};
+    float inv_x = 0, inv_y = 0;
+    double spacing = 0;
+    // device storage
+    mxn::DevBuf col_count, col_start, col_fill, colbb;
+    mxn::DevBuf atom_col, atom_xw, atom_img, bucket;
+    mxn::DevBuf xs, xs_now, type_s, perm, img_s, slot_of;
+    mxn::DevBuf bbi_lo, bbi_hi, bbj_lo, bbj_hi;
+    mxn::DevBuf nslots;        // int on device
+    mxn::DevBuf fs;            // force accumulation, SoA [3][slots_cap]
+    mxn::DevBuf shiftvec;      // 27 float4 image shift vectors
+    long generation = 0;       // incremented by every sort; lists remember the one they were built on
+};
+
+struct nb_list {
+    const nb_grid *grid = nullptr;
+    nb_ctx *ctx = nullptr;
+    float rlist = 0, rbb = 0;
+    long cap_entries = 0;
+    long cap_items = 0;
+    int ci_cap = 0;
+    mxn::DevBuf entries, items;
+    mxn::DevBuf ci_count, ci_icount, ci_start, ci_istart;
+    mxn::DevBuf totals;        // int[4]: entries, items, overflow, pad
+    long last_entries = 0;     // host copy after a synchronous build
+    long grid_generation = -1;
+};
+
+namespace mxn {
+
+// kernel launchers (grid.hip, pairlist.hip, forces.hip)
+int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type);
+int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync);
+int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
+                  unsigned flags, float *f, double *energy, double *virial);
+// event-pair timing on the context stream (no-ops unless enabled)
+struct ScopedTimer {
+    nb_ctx *ctx;
+    int which;
+    hipEvent_t stop = nullptr;
+    ScopedTimer(nb_ctx *c, int w);
+    ~ScopedTimer();
+};
+int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc,
+                 unsigned long long *d_counts);
+// exclusive scan of n ints on one workgroup; writes out[0..n] (out[n] = total) and *total
+void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
+
+}  // namespace mxn

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: grid sort, bounding boxes and the canonical cluster-pair list bit-exact;
+forces within 1e-5 relative RMS of FP64; energies and virial (FP64
+accumulation of FP32 pair terms) within 1e-5 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._nb import F, GpuSystem, default_rbb, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4), (4, 8), (8, 8)]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu-case] %s" % request.node.nodeid, file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.water_box(1000, 3.104, seed=1306)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 97 waters: 291 atoms, no column holds a multiple of the cluster size
+    return synth.water_box(97, 2.47, seed=97)
+
+
+def _oracle_bb(g, m):
+    xs, perm = g["xs"], g["perm"]
+    nci = g["n_slots"] // m
+    lo = np.full((nci, 3), np.inf, np.float32)
+    hi = np.full((nci, 3), -np.inf, np.float32)
+    for c in range(nci):
+        real = [s for s in range(c * m, c * m + m) if perm[s] >= 0]
+        if real:
+            lo[c] = xs[real].min(0)
+            hi[c] = xs[real].max(0)
+    return lo, hi
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("which", ["c1", "ragged"])
+def test_grid_sort_bitexact(shape, which, request):
+    box = request.getfixturevalue(which)
+    s = GpuSystem(box, shape, 1.0)
+    try:
+        ex = s.mxn.nb_grid_export(s.grid)
+        g = oracle.grid_sort(box.xyz, box.box, *shape)
+        info = ex["info"]
+        assert (info["nx"], info["ny"], info["n_slots"]) == (g["nx"], g["ny"], g["n_slots"])
+        np.testing.assert_array_equal(ex["col_start"], g["col_start"])
+        np.testing.assert_array_equal(ex["perm"], g["perm"])
+        np.testing.assert_array_equal(ex["img"], g["img"])
+        real = g["perm"] >= 0
+        # bit-exact wrapped coordinates
+        np.testing.assert_array_equal(ex["xyzq"][real, :3].view(np.uint32), g["xs"][real].view(np.uint32))
+        np.testing.assert_array_equal(ex["xyzq"][real, 3], box.q[g["perm"][real]])
+        assert np.all(ex["xyzq"][~real, 3] == 0)
+        lo, hi = _oracle_bb(g, shape[0])
+        np.testing.assert_array_equal(ex["bb"][:, :3], lo)
+        np.testing.assert_array_equal(ex["bb"][:, 4:7], hi)
+    finally:
+        s.close()
+
+
+def _cmp_lists(gpu, ref):
+    assert len(gpu) == len(ref), (len(gpu), len(ref))
+    for k in ("ci", "shift", "cj", "mask"):
+        np.testing.assert_array_equal(gpu[k], ref[k], err_msg=k)
+
+
+@pytest.mark.parametrize("shape,rlist", [((4, 4), 0.9), ((4, 8), 0.9), ((8, 8), 0.9), ((4, 4), 1.1), ((8, 8), 1.1),
+                                         ((4, 8), 1.2)])
+def test_pairlist_bitexact(c1, shape, rlist):
+    rbb = np.float32(default_rbb(c1, shape, rlist))
+    s = GpuSystem(c1, shape, rlist, rbb=float(rbb))
+    try:
+        gpu = s.mxn.nb_list_export_canonical(s.lst)
+        g = oracle.grid_sort(c1.xyz, c1.box, *shape)
+        ref = oracle.pairlist(g, c1.box, np.float32(rlist), rbb, c1.excl_off, c1.excl_idx)
+        _cmp_lists(gpu, ref)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("rbb", [0.0, 1.0])
+def test_pairlist_rbb_extremes(ragged, rbb):
+    """rbb = 0: every pair checked at particle level; rbb = rlist: bounding boxes alone decide."""
+    for shape in SHAPES:
+        s = GpuSystem(ragged, shape, 1.0, rbb=rbb)
+        try:
+            gpu = s.mxn.nb_list_export_canonical(s.lst)
+            g = oracle.grid_sort(ragged.xyz, ragged.box, *shape)
+            _cmp_lists(gpu, oracle.pairlist(g, ragged.box, np.float32(1.0), np.float32(rbb), ragged.excl_off,
+                                             ragged.excl_idx))
+        finally:
+            s.close()
+
+
+def test_pairlist_deterministic(c1):
+    s = GpuSystem(c1, (8, 8), 1.1)
+    try:
+        a = s.mxn.nb_list_export_canonical(s.lst)
+        s.lst = s.mxn.nb_pairlist_build(s.ctx, s.grid, 1.1, -1.0, s.eo, s.ei, 0, s.lst)
+        b = s.mxn.nb_list_export_canonical(s.lst)
+        _cmp_lists(a, b)
+    finally:
+        s.close()
+
+
+def _oracle_forces(box, rc, beta, xyz=None, mode="brute"):
+    return oracle.forces(box.xyz if xyz is None else xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx,
+                         synth.lj_table_spce(), rc, beta, F, shift=True, mode=mode)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forces_energies_virial(c1, shape):
+    rc, rlist, beta = 0.9, 0.9, 3.47
+    s = GpuSystem(c1, shape, rlist)
+    try:
+        f, e, v = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
+        fr, er, vr = _oracle_forces(c1, rc, beta)
+        assert rel_rms(f, fr) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+        assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
+        # force-only kernel: same forces (atomics order aside)
+        f2, _, _ = s.forces(rc, beta, 0)
+        assert rel_rms(f2, f) <= 1e-6
+        # FP32 accumulation variant: same physics, looser sums
+        f3, e3, v3 = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL | s.mxn.NB_ACC_FP32)
+        np.testing.assert_allclose(e3, er, rtol=1e-4)
+    finally:
+        s.close()
+
+
+def test_forces_buffered_after_motion(c1):
+    """List built at rlist = rc + 0.1 from step-0 positions, forces at step 9 of ballistic motion (300 K, 2 fs)."""
+    rc, rlist, beta = 0.9, 1.0, 3.47
+    v = synth.velocities(c1.mass, 300.0, seed=5)
+    x9 = synth.free_flight(c1.xyz, v, 0.002, 10)[9]
+    s = GpuSystem(c1, (8, 8), rlist)
+    try:
+        xq = s.torch.from_numpy(c1.xyzq(x9)).to(s.dev)
+        f, e, _ = s.forces(rc, beta, s.mxn.NB_ENERGY, xyzq_now=xq)
+        fr, er, _ = _oracle_forces(c1, rc, beta, xyz=x9)
+        assert rel_rms(f, fr) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+    finally:
+        s.close()
+
+
+def test_accumulate_flag(c1):
+    s = GpuSystem(c1, (4, 4), 0.9)
+    try:
+        mxn, torch = s.mxn, s.torch
+        f = torch.ones((c1.n, 3), dtype=torch.float32, device=s.dev)
+        p = mxn.make_params(0.9, 3.47, F, s.lj)
+        mxn.nb_forces(s.ctx, s.grid, s.lst, s.xyzq, p, mxn.NB_ACCUMULATE, f)
+        mxn.nb_sync(s.ctx)
+        f0, _, _ = s.forces(0.9, 3.47, 0)
+        assert rel_rms(f.cpu().numpy() - 1.0, f0) < 1e-6
+    finally:
+        s.close()
+
+
+def test_tiny_and_ragged(ragged):
+    """One water in a box; and a ragged 291-atom box, all shapes."""
+    one = synth.water_box(1, 2.5, seed=1)
+    for box, rc in ((one, 1.0), (ragged, 1.0)):
+        fr, er, vr = _oracle_forces(box, rc, 3.12)
+        for shape in SHAPES:
+            s = GpuSystem(box, shape, rc)
+            try:
+                f, e, v = s.forces(rc, 3.12, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
+                assert rel_rms(f, fr) <= 1e-5
+                np.testing.assert_allclose(e, er, rtol=1e-5, atol=1e-6)
+            finally:
+                s.close()
+
+
+def test_production_box_sampled():
+    """The 96k-atom, 8x8, rc 1.0 / rlist 1.1 workload the benchmark times: list on sampled i-clusters,
+    forces on sampled atoms, total energy and virial against the cell-list oracle."""
+    box = synth.water_box(32000, 9.86, seed=1306)
+    rc, rlist, beta, shape = 1.0, 1.1, 3.12, (8, 8)
+    rbb = np.float32(default_rbb(box, shape, rlist))
+    s = GpuSystem(box, shape, rlist, rbb=float(rbb))
+    try:
+        gpu = s.mxn.nb_list_export_canonical(s.lst)
+        g = oracle.grid_sort(box.xyz, box.box, *shape)
+        nci = g["n_slots"] // 8
+        for c0 in (0, nci // 2, nci - 40):
+            ref = oracle.pairlist(g, box.box, np.float32(rlist), rbb, box.excl_off, box.excl_idx, c0, c0 + 40)
+            sel = gpu[(gpu["ci"] >= c0) & (gpu["ci"] < c0 + 40)]
+            _cmp_lists(sel, ref)
+        f, e, v = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
+        sub = np.random.default_rng(0).choice(box.n, 3000, replace=False).astype(np.int32)
+        fs, _ = oracle.forces_subset(box.xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx,
+                                     synth.lj_table_spce(), rc, beta, F, sub)
+        assert rel_rms(f[sub], fs) <= 1e-5
+        fr, er, vr = _oracle_forces(box, rc, beta, mode="binned")
+        assert rel_rms(f, fr) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+        assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
+    finally:
+        s.close()
+
+
+def test_error_paths(c1):
+    import paper_1306_1737_amd as mxn
+    import torch
+    s = GpuSystem(c1, (4, 4), 0.9)
+    try:
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_pairlist_build(s.ctx, s.grid, 1.6, -1.0, s.eo, s.ei)
+        assert ei.value.status == mxn.NB_ERR_BOX
+        p = mxn.make_params(0.9, 5.0, F, s.lj)
+        f = torch.zeros((c1.n, 3), device=s.dev)
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_forces(s.ctx, s.grid, s.lst, s.xyzq, p, 0, f)
+        assert ei.value.status == mxn.NB_ERR_UNSUPPORTED
+        # asynchronous build that outgrows the capacity of a small list: overflow latched, then a synchronous rebuild
+        small = mxn.nb_pairlist_build(s.ctx, s.grid, 0.3, -1.0, s.eo, s.ei)
+        mxn.nb_pairlist_build(s.ctx, s.grid, 1.5, -1.0, s.eo, s.ei, mxn.NB_LIST_ASYNC, small)
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_sync(s.ctx)
+        assert ei.value.status == mxn.NB_ERR_OVERFLOW
+        mxn.nb_pairlist_build(s.ctx, s.grid, 1.5, -1.0, s.eo, s.ei, 0, small)
+        assert mxn.nb_list_info(small)[0] > 0
+        mxn.nb_list_free(small)
+        # a non-finite coordinate is latched and reported
+        bad = s.xyzq.clone()
+        bad[5, 0] = float("nan")
+        g2 = mxn.nb_grid_sort(s.ctx, c1.box, bad, s.type, (4, 4))
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_sync(s.ctx)
+        assert ei.value.status == mxn.NB_ERR_NONFINITE
+        mxn.nb_grid_free(g2)
+        # a list built before the grid's last sort is rejected
+        s.grid = mxn.nb_grid_sort(s.ctx, c1.box, s.xyzq, s.type, (4, 4), s.grid)
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_forces(s.ctx, s.grid, s.lst, s.xyzq, mxn.make_params(0.9, 3.47, F, s.lj), 0, f)
+        assert ei.value.status == mxn.NB_ERR_STATE
+    finally:
+        s.close()
+
+
+def test_buffer_estimate_matches_oracle():
+    import paper_1306_1737_amd as mxn
+    from oracle import drift
+    kw = dict(T=300.0, dt=0.002, masses=[synth.MASS_O, synth.MASS_H], charges=[synth.Q_O, synth.Q_H],
+              c6c12=synth.lj_table_spce(), counts=[32000, 64000], volume=9.86 ** 3, rc=1.0, beta=3.12, f=F)
+    for nst in (5, 10, 20, 40):
+        ref = drift.min_buffer(0.005, nstlist=nst, **kw)
+        rb, d, fb = mxn.nb_buffer_estimate(None, T=300.0, dt=0.002, nstlist=nst, mass=kw["masses"],
+                                           charge=kw["charges"], c6c12=kw["c6c12"], count=kw["counts"],
+                                           volume=kw["volume"], rc=1.0, beta=3.12, coulomb_f=F, shape=(8, 8),
+                                           target=0.005)
+        assert rb == pytest.approx(ref, abs=1e-9)
+        assert d == pytest.approx(drift.drift_rate(rb, nstlist=nst, **kw), rel=1e-9)
+        assert not fb
