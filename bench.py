@@ -44,8 +44,8 @@ def cpu_baseline(box, w):
     import synth
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     os.environ["OMP_NUM_THREADS"] = str(nthreads)
-    # sample: the forces on 12 000 atoms (brute force against all 96 000 partners)
-    sub = np.arange(0, box.n, box.n // 12000, dtype=np.int32)[:12000]
+    # sample: the forces on every atom, each by brute force over all 96 000 partners
+    sub = np.arange(box.n, dtype=np.int32)
     t0 = time.perf_counter()
     oracle.forces_subset(box.xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx, synth.lj_table_spce(),
                          w.rc, w.beta, synth.COULOMB_F, sub)
@@ -72,8 +72,22 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shape", default="8x8")
+    ap.add_argument("--variant", default="direct", choices=["direct", "compact"])
+    ap.add_argument("--list-order", default="canonical", choices=["canonical", "distance"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (calibrates memory-traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.empty(args.copy_probe * (1 << 18), dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
               "(the path would shard by replica or by spatial domain, see the design notes)", file=sys.stderr)
@@ -99,10 +113,14 @@ def main():
     f = torch.zeros((box.n, 3), dtype=torch.float32, device=dev)
     e = torch.zeros(2, dtype=torch.float64, device=dev)
     ctx = mxn.nb_create(0)
+    mxn.nb_set_force_variant(ctx, mxn.NB_FORCE_DIRECT if args.variant == "direct" else mxn.NB_FORCE_COMPACT)
     params = mxn.make_params(w.rc, w.beta, synth.COULOMB_F, lj)
     state = {"grid": None, "lst": None}
 
+    order_flag = mxn.NB_LIST_BY_DISTANCE if args.list_order == "distance" else 0
+
     def step(list_flags):
+        list_flags |= order_flag
         state["grid"] = mxn.nb_grid_sort(ctx, box.box, xq[0], typ, (m, n), state["grid"])
         state["lst"] = mxn.nb_pairlist_build(ctx, state["grid"], w.rlist, -1.0, eo, ei, list_flags, state["lst"])
         for k in range(w.nstlist):
@@ -151,7 +169,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n_atoms": box.n, "box_nm": w.L, "shape": "%dx%d" % (m, n), "rc": w.rc,
                    "rlist": w.rlist, "beta": w.beta, "nstlist": w.nstlist, "energies": "every step",
-                   "force_calls_per_step": calls},
+                   "force_calls_per_step": calls, "force_kernel": args.variant, "list_order": args.list_order},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None},
         "effective_pairs_per_s": eff,

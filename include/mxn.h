@@ -128,8 +128,10 @@ int nb_grid_export(nb_grid *grid, int *perm, float *xyzq, int *img, int *col_sta
 /* ------------------------------------------------------------- pair list */
 
 enum {
-    NB_LIST_ASYNC = 1   /* do not synchronise to size the list: reuse the handle's capacity,
-                           latch NB_ERR_OVERFLOW (reported by nb_sync) if it is too small */
+    NB_LIST_ASYNC = 1,          /* do not synchronise to size the list: reuse the handle's capacity,
+                                   latch NB_ERR_OVERFLOW (reported by nb_sync) if it is too small */
+    NB_LIST_BY_DISTANCE = 2     /* store each i-cluster's entries by bounding-box distance instead of
+                                   in canonical order (groups the entries beyond the cut-off) */
 };
 
 /*
@@ -151,7 +153,9 @@ enum {
  *   flags     0 or NB_LIST_ASYNC
  *   list      in/out: NULL creates, otherwise reused
  * Without NB_LIST_ASYNC the call synchronises once to size its storage.
- * Entries are in a deterministic order: by i-cluster, image shift, j-cluster.
+ * Storage order is deterministic: by i-cluster, image shift, j-cluster
+ * (canonical), or with NB_LIST_BY_DISTANCE by i-cluster and bounding-box
+ * distance (ties in canonical order).
  */
 int nb_pairlist_build(nb_ctx *ctx, const nb_grid *grid, float rlist, float rbb, const int *excl_off,
                       const int *excl_idx, int flags, nb_list **list);
@@ -195,6 +199,16 @@ enum {
  */
 int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial);
+
+/* Force-kernel variant used by nb_forces on this context.
+ *   NB_FORCE_DIRECT (default): every listed pair is visited in lock-step with
+ *     a per-lane cut-off branch (the cut-off conditional of the paper's GPU
+ *     kernel); passes whose pairs are all beyond rc skip the interaction.
+ *   NB_FORCE_COMPACT: in-range pairs of each work item are first compacted
+ *     through LDS into full wavefront passes.
+ * Results agree to rounding; the choice is a tuning knob. */
+enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1 };
+int nb_set_force_variant(nb_ctx *ctx, int variant);
 
 /* -------------------------------------------------------- buffer estimate */
 

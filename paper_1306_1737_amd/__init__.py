@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmxn.so")
 
 NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_OOM, NB_ERR_HIP, NB_ERR_OVERFLOW, NB_ERR_STATE, NB_ERR_NONFINITE, \
     NB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
-NB_LIST_ASYNC = 1
+NB_LIST_ASYNC, NB_LIST_BY_DISTANCE = 1, 2
 NB_ENERGY, NB_VIRIAL, NB_ACC_FP32, NB_ACCUMULATE = 1, 2, 4, 8
 NB_BUFFER_ANALYTIC, NB_BUFFER_MLP, NB_BUFFER_AUTO = 0, 1, 2
 
@@ -30,8 +30,9 @@ EXPORTS = [
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
-    "nb_list_stats",
+    "nb_list_stats", "nb_set_force_variant",
 ]
+NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
 
 
@@ -94,6 +95,7 @@ def lib():
                                     ip], i),
             "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
             "nb_list_stats": ([vp, vp, vp, vp, f, vp], i),
+            "nb_set_force_variant": ([vp, i], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -238,6 +240,10 @@ def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True):
     p = nb_params(float(rc), float(beta), float(coulomb_f), int(nt), c6c12.data_ptr(), int(bool(shift_energies)))
     p._keep = c6c12
     return p
+
+
+def nb_set_force_variant(ctx, variant):
+    _check(lib().nb_set_force_variant(ctx, int(variant)))
 
 
 def nb_forces(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=None):

@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation, handle and storage management,
 // error reporting.  All numerical work is in the kernels of grid.hip,
 // pairlist.hip and forces.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -307,7 +308,7 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 // ------------------------------------------------------------------- list
 
 static void list_release(nb_list *l) {
-    DevBuf *bufs[] = {&l->entries, &l->items, &l->ci_count, &l->ci_icount, &l->ci_start, &l->ci_istart, &l->totals};
+    DevBuf *bufs[] = {&l->entries, &l->entries_canon, &l->keys, &l->items, &l->ci_count, &l->ci_icount, &l->ci_start, &l->ci_istart, &l->totals};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -316,7 +317,7 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     if (!c || !g || !excl_off || !excl_idx || !list) return fail(NB_ERR_ARG, "nb_pairlist_build: null argument");
     if (g->ctx != c) return fail(NB_ERR_STATE, "nb_pairlist_build: grid belongs to another context");
     if (!(rlist > 0.0f) || !std::isfinite(rlist)) return fail(NB_ERR_ARG, "nb_pairlist_build: rlist must be > 0");
-    if (flags & ~NB_LIST_ASYNC) return fail(NB_ERR_ARG, "nb_pairlist_build: unknown flag");
+    if (flags & ~(NB_LIST_ASYNC | NB_LIST_BY_DISTANCE)) return fail(NB_ERR_ARG, "nb_pairlist_build: unknown flag");
     for (int d = 0; d < 3; ++d)
         if (!((double)g->Lf[d] > 2.0 * (double)rlist))
             return fail(NB_ERR_BOX, "nb_pairlist_build: every box edge must exceed 2*rlist");
@@ -347,6 +348,8 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
         const long ce = (long)(4.0 * half / (g->m * g->nn)) + 16L * nci_cap + 1024;
         const long cit = ce / kItemEntries + nci_cap + 256;
         rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
+        rc = rc ? rc : ensure(l->entries_canon, (size_t)ce * sizeof(nb_jentry));
+        rc = rc ? rc : ensure(l->keys, (size_t)ce * sizeof(float));
         rc = rc ? rc : ensure(l->items, (size_t)cit * 16);
         if (rc == NB_OK) {
             l->cap_entries = ce;
@@ -355,7 +358,7 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     }
     if (rc == NB_OK) {
         ScopedTimer tm(c, NB_TIMER_PAIRLIST);
-        rc = launch_pairlist(l, excl_off, excl_idx, !(flags & NB_LIST_ASYNC));
+        rc = launch_pairlist(l, excl_off, excl_idx, !(flags & NB_LIST_ASYNC), (flags & NB_LIST_BY_DISTANCE) != 0);
     }
     if (rc != NB_OK) {
         if (fresh) {
@@ -412,6 +415,11 @@ int nb_list_export_canonical(nb_list *l, nb_entry *out, long cap, long *count) {
         delete[] ent;
         return fail(NB_ERR_HIP, hipGetErrorString(e));
     }
+    // entries may be stored by bounding-box distance: restore canonical order (shift, then j-cluster)
+    for (int ci = 0; ci < nci; ++ci)
+        std::sort(ent + starts[ci], ent + starts[ci + 1], [](const nb_jentry &x, const nb_jentry &y) {
+            return x.shift != y.shift ? x.shift < y.shift : x.cj < y.cj;
+        });
     long k = 0;
     for (int ci = 0; ci < nci; ++ci)
         for (int j = starts[ci]; j < starts[ci + 1]; ++j, ++k) {
@@ -433,6 +441,14 @@ int nb_list_export_canonical(nb_list *l, nb_entry *out, long cap, long *count) {
 }
 
 // ----------------------------------------------------------------- forces
+
+int nb_set_force_variant(nb_ctx *c, int variant) {
+    if (!c) return fail(NB_ERR_ARG, "nb_set_force_variant: ctx is null");
+    if (variant != NB_FORCE_COMPACT && variant != NB_FORCE_DIRECT)
+        return fail(NB_ERR_ARG, "nb_set_force_variant: unknown variant");
+    c->force_variant = variant;
+    return NB_OK;
+}
 
 int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial) {

@@ -46,6 +46,7 @@ struct ForceArgs {
     int accumulate;
     int *flags;
     int nblocks_x8;   // launched blocks / 8 (XCD-contiguous remap)
+    long pstride;     // partials layout: [kNAcc][pstride]
 };
 
 __global__ void k_gather(ForceArgs a) {
@@ -84,6 +85,66 @@ __device__ inline T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Sum over the 64 lanes with DPP row shifts (prefix sums inside each row of
+// 16 lanes) and row broadcasts; the total ends up in lane 63.
+__device__ inline float wave_sum_dpp(float v) {
+    int x = __float_as_int(v);
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true)));
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true)));
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true)));
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true)));
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false)));
+    x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false)));
+    return __int_as_float(x);
+}
+
+// One pass of the direct kernel's inner loop: this lane's j-particle against
+// the M i-particles.  (A uniform mask-free copy of this loop for passes
+// without exclusions, dummies or self pairs measured slower on gfx950: the
+// duplicated body costs more than the mask selects it saves.)
+template <int M, bool ENER>
+__device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float (&xi)[M], const float (&yi)[M],
+                                 const float (&zi)[M], const float (&qi)[M], const int (&ti)[M], float xj, float yj,
+                                 float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l, float (&fix)[M],
+                                 float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz, float &el,
+                                 float &ec) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2l && ((act >> k) & 1u)) {
+            const bool bit = (mb >> k) & 1u;
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float rinv2 = rinv * rinv;
+            const float u = r2 * rinv * a.beta;
+            const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+            const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
+            const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u,
+                                 1.0f);
+            const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
+            const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+            const float vc = em * rinv;
+            const float qq = qi[k] * qj;
+            float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+            const float4 lj = ljt[ti[k] + tj];
+            const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
+            const float rinv6 = rinv2 * rinv2 * rinv2;
+            const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
+            fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+            fix[k] = fmaf(fsc, dx, fix[k]);
+            fiy[k] = fmaf(fsc, dy, fiy[k]);
+            fiz[k] = fmaf(fsc, dz, fiz[k]);
+            fjx = fmaf(-fsc, dx, fjx);
+            fjy = fmaf(-fsc, dy, fjy);
+            fjz = fmaf(-fsc, dz, fjz);
+            if (ENER) {
+                el += t12 - t6 - (bit ? lj.z : 0.0f);
+                ec += qq * (vc - (bit ? a.shiftC : 0.0f));
+            }
+        }
+    }
 }
 
 template <int M, int N, bool ENER, bool VIR, bool ACC64>
@@ -148,41 +209,13 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
             act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
         }
         if (!valid) act = 0u;
-        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < a.rc2 && ((act >> k) & 1u)) {
-                const bool bit = (mb >> k) & 1u;
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float rinv2 = rinv * rinv;
-                const float u = r2 * rinv * a.beta;
-                const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
-                const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
-                const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1),
-                                     u, 1.0f);
-                const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
-                const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
-                const float vc = em * rinv;
-                const float qq = qi[k] * qj;
-                float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
-                const float4 lj = ljt[ti[k] + tj];
-                const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
-                const float rinv6 = rinv2 * rinv2 * rinv2;
-                const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
-                fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
-                fix[k] = fmaf(fsc, dx, fix[k]);
-                fiy[k] = fmaf(fsc, dy, fiy[k]);
-                fiz[k] = fmaf(fsc, dz, fiz[k]);
-                fjx = fmaf(-fsc, dx, fjx);
-                fjy = fmaf(-fsc, dy, fjy);
-                fjz = fmaf(-fsc, dz, fjz);
-                if (ENER) {
-                    elj += (acc_t)(t12 - t6 - (bit ? lj.z : 0.0f));
-                    ec += (acc_t)(qq * (vc - (bit ? a.shiftC : 0.0f)));
-                }
-            }
+        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
+        const float rc2l = valid ? a.rc2 : -1.0f;
+        pair_pass<M, ENER>(a, ljt, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, act, rc2l, fix, fiy, fiz, fjx, fjy, fjz,
+                           el, ecl);
+        if (ENER) {
+            elj += (acc_t)el;
+            ec += (acc_t)ecl;
         }
         if (valid) {
             unsafeAtomicAdd(a.fs + jslot, fjx);
@@ -201,8 +234,8 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     for (int k = 0; k < 9; ++k) viri[k] = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        const float fx = wave_sum(fix[k]), fy = wave_sum(fiy[k]), fz = wave_sum(fiz[k]);
-        if (lane == 0) {
+        const float fx = wave_sum_dpp(fix[k]), fy = wave_sum_dpp(fiy[k]), fz = wave_sum_dpp(fiz[k]);
+        if (lane == 63) {
             const int s = ci * M + k;
             unsafeAtomicAdd(a.fs + s, fx);
             unsafeAtomicAdd(a.fs + a.slots_cap + s, fy);
@@ -220,34 +253,41 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
         out[1] = ENER ? wave_sum(ec) : (acc_t)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
-        if (lane == 0)
-            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)item * kNAcc + k] = (double)out[k];
+        if (lane == 63)   // the lane that holds the i-force terms
+            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
     }
 }
 
-// Deterministic reduction of the per-item partials: fixed assignment of items
-// to threads and a fixed tree.  FP64 or (precision study) FP32 throughout.
+// Deterministic reduction of the per-item partials: one workgroup per value,
+// a fixed assignment of items to threads (coalesced, four independent
+// accumulators per thread) and a fixed tree.  FP64 or (precision study) FP32.
 template <bool ACC64>
-__global__ __launch_bounds__(1024) void k_reduce(const double *partials, const int *totals, double *energy,
-                                                 double *virial, int ener, int vir) {
+__global__ __launch_bounds__(1024) void k_reduce(const double *partials, long pstride, const int *totals,
+                                                 double *energy, double *virial, int ener, int vir) {
     using acc_t = typename std::conditional<ACC64, double, float>::type;
     __shared__ acc_t red[1024];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, k = blockIdx.x;
+    if ((k < 2 && !ener) || (k >= 2 && !vir)) return;
     const int n = totals[2];
-    for (int k = 0; k < kNAcc; ++k) {
-        acc_t s = 0;
-        for (int i = t; i < n; i += 1024) s += (acc_t)partials[(size_t)i * kNAcc + k];
-        red[t] = s;
+    const double *p = partials + (size_t)k * pstride;
+    acc_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int i = t;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        s0 += (acc_t)p[i];
+        s1 += (acc_t)p[i + 1024];
+        s2 += (acc_t)p[i + 2048];
+        s3 += (acc_t)p[i + 3072];
+    }
+    for (; i < n; i += 1024) s0 += (acc_t)p[i];
+    red[t] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
         __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if (t < w) red[t] += red[t + w];
-            __syncthreads();
-        }
-        if (t == 0) {
-            if (k < 2 && ener) energy[k] = (double)red[0];
-            if (k >= 2 && vir) virial[k - 2] = (double)red[0];
-        }
-        __syncthreads();
+    }
+    if (t == 0) {
+        if (k < 2) energy[k] = (double)red[0];
+        else virial[k - 2] = (double)red[0];
     }
 }
 
@@ -298,21 +338,238 @@ __global__ __launch_bounds__(256) void k_stats(ForceArgs a, unsigned long long *
     }
 }
 
+// LDS communication between the lanes of one wavefront
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int lane_rank(unsigned long long bal) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+}
+
+template <int N>
+constexpr int wave_lds_bytes() {
+    return mxn::kItemEntries * N * 32 + 128 * 4;
+}
+
+// Compacted variant (default).  A wavefront stages its work item's j-particles
+// in LDS (position moved into the i-cluster's image, charge, type, mask and a
+// per-slot bitmask of the i-particles within rc).  Then for each i-particle it
+// compacts the in-range j-slots into a 64-entry queue and evaluates the pair
+// interactions only in full (or final partial) 64-lane passes: the i-force
+// stays in registers (one i-particle per pass), the j-forces go to per-slot
+// LDS accumulators that are conflict-free within a pass, and at the end each
+// j-slot adds its force to memory once with a coalesced atomic.  Compared with
+// evaluating every listed pair in lock-step, this skips the pairs beyond rc
+// (about two thirds of an 8x8 list at rlist = rc + 0.1 nm) at the cost of LDS
+// staging.
+template <int M, int N, bool ENER, bool VIR, bool ACC64>
+__global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
+    constexpr int JMAX = mxn::kItemEntries * N;
+    constexpr unsigned FULL = (1u << M) - 1u;
+    extern __shared__ float4 smem[];
+    float4 *svec = smem;
+    float4 *ljt = smem + 32;
+    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
+    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
+        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
+        ljt[t] = make_float4(c6, c12, sh, 0.0f);
+    }
+    __syncthreads();
+
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    char *wb = reinterpret_cast<char *>(smem + 32 + a.nt * a.nt) + (size_t)wave * wave_lds_bytes<N>();
+    float4 *jd = reinterpret_cast<float4 *>(wb);
+    int *jinfo = reinterpret_cast<int *>(wb + JMAX * 16);
+    float *fjx = reinterpret_cast<float *>(wb + JMAX * 20);
+    float *fjy = fjx + JMAX, *fjz = fjy + JMAX;
+    int *pend = reinterpret_cast<int *>(wb + JMAX * 32);
+
+    const int logical = (blockIdx.x % 8) * a.nblocks_x8 + blockIdx.x / 8;
+    const int item = logical * 4 + wave;
+    if (item >= a.totals[2]) return;
+    const int4 it = a.items[item];
+    const int ci = __builtin_amdgcn_readfirstlane(it.x);
+    const int js = __builtin_amdgcn_readfirstlane(it.y);
+    const int je = __builtin_amdgcn_readfirstlane(it.z);
+    const int nslot = (je - js) * N;
+
+    // stage the item's j-particles
+    for (int base = 0; base < nslot; base += 64) {
+        const int jidx = base + lane;
+        const bool valid = jidx < nslot;
+        const nb_jentry en = a.entries[js + (valid ? jidx : 0) / N];
+        const int jslot = en.cj * N + (jidx % N);
+        const float4 pj = a.xs_now[jslot];
+        const int tj = min(max(a.type_s[jslot], 0), a.nt - 1);
+        const float4 sv = svec[en.shift];
+        const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
+        const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
+        const unsigned mb = (unsigned)(m64 >> ((jidx % N) * M)) & FULL;
+        unsigned act = FULL;
+        if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
+            const int t = jslot - ci * M;
+            act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
+        }
+        unsigned inr = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const float4 pik = a.xs_now[ci * M + k];
+            const float dx = pik.x - xj, dy = pik.y - yj, dz = pik.z - zj;
+            inr |= (unsigned)(dx * dx + dy * dy + dz * dz < a.rc2) << k;
+        }
+        inr &= act;
+        if (valid) {
+            jd[jidx] = make_float4(xj, yj, zj, pj.w);
+            jinfo[jidx] = tj | (int)(mb << 8) | (int)(inr << 16);
+            fjx[jidx] = 0.0f;
+            fjy[jidx] = 0.0f;
+            fjz[jidx] = 0.0f;
+        }
+    }
+    wave_lds_sync();
+
+    acc_t elj = 0, ec = 0;
+    acc_t viri[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) viri[k] = 0;
+    for (int k = 0; k < M; ++k) {
+        const float4 pik = a.xs_now[ci * M + k];
+        const float qik = pik.w * a.coulomb_f;
+        const int tt = a.type_s[ci * M + k];
+        const int tik = (tt < 0 ? 0 : (tt >= a.nt ? a.nt - 1 : tt)) * a.nt;
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f, el = 0.0f, ecl = 0.0f;
+        auto pass = [&](int pidx) {
+            if (pidx < 0) return;
+            const float4 pj = jd[pidx];
+            const int info = jinfo[pidx];
+            const float dx = pik.x - pj.x, dy = pik.y - pj.y, dz = pik.z - pj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const bool bit = (info >> (8 + k)) & 1;
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float rinv2 = rinv * rinv;
+            const float u = r2 * rinv * a.beta;
+            const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+            const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
+            const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u,
+                                 1.0f);
+            const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
+            const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+            const float vc = em * rinv;
+            const float qq = qik * pj.w;
+            float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+            const float4 lj = ljt[tik + (info & 255)];
+            const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
+            const float rinv6 = rinv2 * rinv2 * rinv2;
+            const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
+            fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+            fx = fmaf(fsc, dx, fx);
+            fy = fmaf(fsc, dy, fy);
+            fz = fmaf(fsc, dz, fz);
+            atomicAdd(fjx + pidx, -fsc * dx);
+            atomicAdd(fjy + pidx, -fsc * dy);
+            atomicAdd(fjz + pidx, -fsc * dz);
+            if (ENER) {
+                el += t12 - t6 - (bit ? lj.z : 0.0f);
+                ecl += qq * (vc - (bit ? a.shiftC : 0.0f));
+            }
+        };
+        int P = 0;
+        for (int base = 0; base < nslot; base += 64) {
+            const int jidx = base + lane;
+            const bool in = jidx < nslot && ((jinfo[jidx] >> (16 + k)) & 1);
+            const unsigned long long bal = __ballot(in);
+            if (in) pend[P + lane_rank(bal)] = jidx;
+            P += __popcll(bal);
+            if (P >= 64) {
+                wave_lds_sync();
+                pass(pend[lane]);
+                const int rem = P - 64;
+                const int carry = lane < rem ? pend[64 + lane] : 0;
+                wave_lds_sync();
+                if (lane < rem) pend[lane] = carry;
+                P = rem;
+            }
+        }
+        if (P > 0) {
+            wave_lds_sync();
+            pass(lane < P ? pend[lane] : -1);
+        }
+        wave_lds_sync();
+        fx = wave_sum(fx);
+        fy = wave_sum(fy);
+        fz = wave_sum(fz);
+        if (lane == 0) {
+            const int s = ci * M + k;
+            unsafeAtomicAdd(a.fs + s, fx);
+            unsafeAtomicAdd(a.fs + a.slots_cap + s, fy);
+            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + s, fz);
+            if (VIR) {
+                viri[0] += (acc_t)pik.x * (acc_t)fx; viri[1] += (acc_t)pik.x * (acc_t)fy; viri[2] += (acc_t)pik.x * (acc_t)fz;
+                viri[3] += (acc_t)pik.y * (acc_t)fx; viri[4] += (acc_t)pik.y * (acc_t)fy; viri[5] += (acc_t)pik.y * (acc_t)fz;
+                viri[6] += (acc_t)pik.z * (acc_t)fx; viri[7] += (acc_t)pik.z * (acc_t)fy; viri[8] += (acc_t)pik.z * (acc_t)fz;
+            }
+        }
+        if (ENER) {
+            elj += (acc_t)el;
+            ec += (acc_t)ecl;
+        }
+    }
+
+    // j-forces: one coalesced atomic per slot that received any interaction
+    acc_t vir[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vir[k] = 0;
+    for (int base = 0; base < nslot; base += 64) {
+        const int jidx = base + lane;
+        if (jidx < nslot && (jinfo[jidx] >> 16)) {
+            const nb_jentry en = a.entries[js + jidx / N];
+            const int jslot = en.cj * N + (jidx % N);
+            const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
+            unsafeAtomicAdd(a.fs + jslot, gx);
+            unsafeAtomicAdd(a.fs + a.slots_cap + jslot, gy);
+            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + jslot, gz);
+            if (VIR) {
+                const float4 pj = jd[jidx];
+                vir[0] += (acc_t)(pj.x * gx); vir[1] += (acc_t)(pj.x * gy); vir[2] += (acc_t)(pj.x * gz);
+                vir[3] += (acc_t)(pj.y * gx); vir[4] += (acc_t)(pj.y * gy); vir[5] += (acc_t)(pj.y * gz);
+                vir[6] += (acc_t)(pj.z * gx); vir[7] += (acc_t)(pj.z * gy); vir[8] += (acc_t)(pj.z * gz);
+            }
+        }
+    }
+    if (ENER || VIR) {
+        acc_t out[kNAcc];
+        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[1] = ENER ? wave_sum(ec) : (acc_t)0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
+        if (lane == 0)
+            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
+    }
+}
+
 template <int M, int N, bool E, bool V, bool D>
-void launch_k(const ForceArgs &a, int nb, size_t lds, hipStream_t st) {
-    k_forces<M, N, E, V, D><<<nb, 256, lds, st>>>(a);
+void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t st) {
+    if (variant == NB_FORCE_DIRECT)
+        k_forces<M, N, E, V, D><<<nb, 256, lds, st>>>(a);
+    else
+        k_forces_c<M, N, E, V, D><<<nb, 256, lds + 4 * wave_lds_bytes<N>(), st>>>(a);
 }
 
 template <int M, int N>
-void launch_shape(const ForceArgs &a, unsigned flags, int nb, size_t lds, hipStream_t st) {
+void launch_shape(const ForceArgs &a, unsigned flags, int nb, size_t lds, int var, hipStream_t st) {
     const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL, D = !(flags & NB_ACC_FP32);
-    if (E && V && D) launch_k<M, N, true, true, true>(a, nb, lds, st);
-    else if (E && V) launch_k<M, N, true, true, false>(a, nb, lds, st);
-    else if (E && D) launch_k<M, N, true, false, true>(a, nb, lds, st);
-    else if (E) launch_k<M, N, true, false, false>(a, nb, lds, st);
-    else if (V && D) launch_k<M, N, false, true, true>(a, nb, lds, st);
-    else if (V) launch_k<M, N, false, true, false>(a, nb, lds, st);
-    else launch_k<M, N, false, false, true>(a, nb, lds, st);
+    if (E && V && D) launch_k<M, N, true, true, true>(a, nb, lds, var, st);
+    else if (E && V) launch_k<M, N, true, true, false>(a, nb, lds, var, st);
+    else if (E && D) launch_k<M, N, true, false, true>(a, nb, lds, var, st);
+    else if (E) launch_k<M, N, true, false, false>(a, nb, lds, var, st);
+    else if (V && D) launch_k<M, N, false, true, true>(a, nb, lds, var, st);
+    else if (V) launch_k<M, N, false, true, false>(a, nb, lds, var, st);
+    else launch_k<M, N, false, false, true>(a, nb, lds, var, st);
 }
 
 }  // namespace
@@ -357,6 +614,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         int rc = ensure(ctx->partials, (size_t)(l->cap_items + 4) * kNAcc * sizeof(double));
         if (rc) return rc;
     }
+    const long pstride = l->cap_items + 4;
     ForceArgs a{};
     a.nslots = (const int *)g->nslots.p;
     a.perm = (const int *)g->perm.p;
@@ -384,6 +642,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
     a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
     a.partials = (double *)ctx->partials.p;
+    a.pstride = pstride;
     a.f_out = f;
     a.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
     a.flags = ctx->d_flags;
@@ -396,18 +655,19 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     const size_t lds = (32 + (size_t)p->ntypes * p->ntypes) * sizeof(float4);
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
-        if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, st);
-        else if (g->m == 4 && g->nn == 8) launch_shape<4, 8>(a, flags, nb, lds, st);
-        else launch_shape<8, 8>(a, flags, nb, lds, st);
+        const int var = ctx->force_variant;
+        if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, var, st);
+        else if (g->m == 4 && g->nn == 8) launch_shape<4, 8>(a, flags, nb, lds, var, st);
+        else launch_shape<8, 8>(a, flags, nb, lds, var, st);
     }
     k_scatter<<<(g->n + 255) / 256, 256, 0, st>>>(a);
     if (need_acc) {
         if (flags & NB_ACC_FP32)
-            k_reduce<false><<<1, 1024, 0, st>>>(a.partials, a.totals, energy, virial, flags & NB_ENERGY,
-                                                flags & NB_VIRIAL);
+            k_reduce<false><<<kNAcc, 1024, 0, st>>>(a.partials, pstride, a.totals, energy, virial, flags & NB_ENERGY,
+                                                    flags & NB_VIRIAL);
         else
-            k_reduce<true><<<1, 1024, 0, st>>>(a.partials, a.totals, energy, virial, flags & NB_ENERGY,
-                                               flags & NB_VIRIAL);
+            k_reduce<true><<<kNAcc, 1024, 0, st>>>(a.partials, pstride, a.totals, energy, virial, flags & NB_ENERGY,
+                                                   flags & NB_VIRIAL);
     }
     MXN_HIP(hipGetLastError());
     return NB_OK;

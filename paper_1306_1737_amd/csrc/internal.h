@@ -55,6 +55,7 @@ struct nb_ctx {
     int *h_pinned = nullptr;    // pinned host scratch (16 ints)
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     bool timing = false;
+    int force_variant = NB_FORCE_DIRECT;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timers[NB_TIMER_COUNT];
     std::vector<hipEvent_t> event_pool;
 };
@@ -87,7 +88,8 @@ struct nb_list {
     long cap_entries = 0;
     long cap_items = 0;
     int ci_cap = 0;
-    mxn::DevBuf entries, items;
+    mxn::DevBuf entries, items;    // entries: per i-cluster, ordered by bounding-box distance
+    mxn::DevBuf entries_canon, keys;   // fill-pass output in canonical order, and its sort keys
     mxn::DevBuf ci_count, ci_icount, ci_start, ci_istart;
     mxn::DevBuf totals;        // int[4]: entries, items, overflow, pad
     long last_entries = 0;     // host copy after a synchronous build
@@ -98,7 +100,7 @@ namespace mxn {
 
 // kernel launchers (grid.hip, pairlist.hip, forces.hip)
 int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type);
-int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync);
+int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync, bool by_distance);
 int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
                   unsigned flags, float *f, double *energy, double *virial);
 // event-pair timing on the context stream (no-ops unless enabled)

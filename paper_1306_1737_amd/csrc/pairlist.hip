@@ -29,7 +29,8 @@ struct SearchArgs {
     float rlist, rl2, rb2;
     int *ci_count;
     const int *ci_start, *ci_istart, *totals;
-    nb_jentry *entries;
+    nb_jentry *entries;   // canonical order (by shift, then j-cluster) within each i-cluster
+    float *keys;          // bounding-box distance^2 of each entry
     int4 *items;
     long cap_entries, cap_items;
     int nci_cap;
@@ -43,8 +44,25 @@ __device__ inline float axis_gap(float jlo, float jhi, float ilo, float ihi) {
     return m > 0.0f ? m : 0.0f;
 }
 
+// first index k in [lo, hi) with key(k) >= v for a nondecreasing key (hi if none)
+template <class F>
+__device__ inline int lower_bound(int lo, int hi, F key, float v) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (key(mid) < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Lane layout of the particle-pair checks: lane = g*M*N + b*M + a handles the
+// pair (i-slot a, j-slot b) of candidate group g, so P = 64/(M*N) candidates
+// are checked per pass and one ballot yields their masks in j-major order.
 template <int M, int N, bool FILL>
 __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+    constexpr int PAIRS = M * N;
+    constexpr int P = 64 / PAIRS;
+    constexpr unsigned long long GMASK = PAIRS == 64 ? ~0ull : ((1ull << PAIRS) - 1ull);
     const int lane = threadIdx.x & 63;
     const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ci >= a.nci_cap) return;
@@ -60,14 +78,10 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         ipos = a.ci_istart[ci];
     }
     const float4 lo = a.bbi_lo[ci], hi = a.bbi_hi[ci];
-    float ix[M], iy[M], iz[M];
-    int iorig[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        float4 p = a.xs[ci * M + k];
-        ix[k] = p.x; iy[k] = p.y; iz[k] = p.z;
-        iorig[k] = a.perm[ci * M + k];
-    }
+    const int pa = lane % M, pb = (lane / M) % N, grp = lane / PAIRS;
+    const float4 pi = a.xs[ci * M + pa];
+    const int iorig = a.perm[ci * M + pa];
+    const float zmargin = 1e-3f;   // keeps the z window conservative against rounding
     int cnt = 0;
     if (lo.x <= hi.x) {   // the cluster holds real particles
         for (int s = 13; s < 27; ++s) {
@@ -75,86 +89,137 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                         sz = (float)(s % 3 - 1) * a.Lz;
             const float slx = lo.x + sx, shx = hi.x + sx, sly = lo.y + sy, shy = hi.y + sy, slz = lo.z + sz,
                         shz = hi.z + sz;
-            float six[M], siy[M], siz[M];
-#pragma unroll
-            for (int k = 0; k < M; ++k) { six[k] = ix[k] + sx; siy[k] = iy[k] + sy; siz[k] = iz[k] + sz; }
+            const float pix = pi.x + sx, piy = pi.y + sy, piz = pi.z + sz;   // this lane's shifted i-particle
             // candidate columns: a superset, one column of margin against rounding
             int cx0 = (int)floorf((slx - a.rlist) * a.inv_x) - 1, cx1 = (int)floorf((shx + a.rlist) * a.inv_x) + 1;
             int cy0 = (int)floorf((sly - a.rlist) * a.inv_y) - 1, cy1 = (int)floorf((shy + a.rlist) * a.inv_y) + 1;
             cx0 = cx0 < 0 ? 0 : cx0; cy0 = cy0 < 0 ? 0 : cy0;
             cx1 = cx1 > a.nx - 1 ? a.nx - 1 : cx1; cy1 = cy1 > a.ny - 1 ? a.ny - 1 : cy1;
-            for (int cx = cx0; cx <= cx1; ++cx)
-                for (int cy = cy0; cy <= cy1; ++cy) {
-                    const int c = cx * a.ny + cy;
-                    const float4 cb = a.colbb[c];
-                    const float gx = axis_gap(cb.x, cb.z, slx, shx), gy = axis_gap(cb.y, cb.w, sly, shy);
-                    if (!(gx * gx + gy * gy < a.rl2)) continue;   // no cluster of this column can pass
-                    const int cj0 = a.col_start[c] / N, cj1 = a.col_start[c + 1] / N;
-                    for (int base = cj0; base < cj1; base += 64) {
-                        const int cj = base + lane;
-                        bool ok = cj < cj1;
-                        if (ok && s == 13) ok = cj * N + N - 1 > ci * M;
-                        float d2 = 0.0f;
-                        if (ok) {
-                            const float4 jl = a.bbj_lo[cj], jh = a.bbj_hi[cj];
-                            d2 = sq3(axis_gap(jl.x, jh.x, slx, shx), axis_gap(jl.y, jh.y, sly, shy),
-                                     axis_gap(jl.z, jh.z, slz, shz));
-                            ok = d2 < a.rl2;
-                        }
-                        if (ok && !(d2 < a.rb2)) {
-                            bool found = false;
-                            for (int b = 0; b < N && !found; ++b) {
-                                const int sb = cj * N + b;
-                                if (a.perm[sb] < 0) continue;
-                                const float4 pb = a.xs[sb];
+            if (cx0 > cx1 || cy0 > cy1) continue;
+            const int ncy = cy1 - cy0 + 1, ncols = (cx1 - cx0 + 1) * ncy;
+            for (int cb = 0; cb < ncols; cb += 64) {
+                // one column per lane (ascending column id): its z window of j-clusters
+                int k0 = 0, kc = 0;
+                const int cidx = cb + lane;
+                if (cidx < ncols) {
+                    const int c = (cx0 + cidx / ncy) * a.ny + cy0 + cidx % ncy;
+                    const float4 cbb = a.colbb[c];
+                    const float gx = axis_gap(cbb.x, cbb.z, slx, shx), gy = axis_gap(cbb.y, cbb.w, sly, shy);
+                    if (gx * gx + gy * gy < a.rl2) {
+                        const int j0 = a.col_start[c] / N, j1 = a.col_start[c + 1] / N;
+                        const float4 *blo = a.bbj_lo, *bhi = a.bbj_hi;
+                        k0 = lower_bound(j0, j1, [&](int k) { return bhi[k].z; }, slz - a.rlist - zmargin);
+                        const int k1 = lower_bound(k0, j1, [&](int k) { return blo[k].z; }, shz + a.rlist + zmargin);
+                        kc = k1 - k0;
+                    }
+                }
+                // flatten the windows of the 64 columns: exclusive offsets by a wave scan
+                int incl = kc;
 #pragma unroll
-                                for (int k = 0; k < M; ++k)
-                                    if (iorig[k] >= 0 && sq3(six[k] - pb.x, siy[k] - pb.y, siz[k] - pb.z) < a.rl2)
-                                        found = true;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += v;
+                }
+                const int total = __shfl(incl, 63, 64);
+                const int excl = incl - kc;
+                for (int t0 = 0; t0 < total; t0 += 64) {
+                    const int t = t0 + lane;
+                    bool ok = t < total;
+                    // owner column: the last lane whose exclusive offset is <= t (fixed six-step search,
+                    // executed by every lane so that all shuffles read active lanes)
+                    const int tt = ok ? t : total - 1;
+                    int own = 0;
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1) {
+                        const int cand = own + step;
+                        const int ev = __shfl(excl, cand < 64 ? cand : 63, 64);
+                        if (cand < 64 && ev <= tt) own = cand;
+                    }
+                    const int cj = __shfl(k0, own, 64) + (tt - __shfl(excl, own, 64));
+                    if (ok && s == 13) ok = cj * N + N - 1 > ci * M;
+                    float d2 = 0.0f;
+                    if (ok) {
+                        const float4 jl = a.bbj_lo[cj], jh = a.bbj_hi[cj];
+                        d2 = sq3(axis_gap(jl.x, jh.x, slx, shx), axis_gap(jl.y, jh.y, sly, shy),
+                                 axis_gap(jl.z, jh.z, slz, shz));
+                        ok = d2 < a.rl2;
+                    }
+                    const bool chk = ok && !(d2 < a.rb2);
+                    unsigned long long accepted = __ballot(ok && !chk);
+                    unsigned long long need = __ballot(chk);
+                    // particle-pair checks, P candidates per pass
+                    while (need) {
+                        int src = -1;
+#pragma unroll
+                        for (int g = 0; g < P; ++g) {
+                            const int f = need ? __ffsll((long long)need) - 1 : -1;
+                            if (f >= 0) need &= need - 1;
+                            if (g == grp) src = f;
+                        }
+                        bool hit = false;
+                        const int cjc = __shfl(cj, src < 0 ? 0 : src, 64);
+                        if (src >= 0 && iorig >= 0) {
+                            const int sb = cjc * N + pb;
+                            if (a.perm[sb] >= 0) {
+                                const float4 pbv = a.xs[sb];
+                                hit = sq3(pix - pbv.x, piy - pbv.y, piz - pbv.z) < a.rl2;
                             }
-                            ok = found;
                         }
-                        const unsigned long long ballot = __ballot(ok);
-                        if (FILL) {
-                            if (ok) {
-                                const int idx = wpos + __popcll(ballot & ((1ull << lane) - 1ull));
-                                // mask in j-major order: bit b*M + a
-                                unsigned long long mask = 0;
-                                for (int b = 0; b < N; ++b) {
-                                    const int sb = cj * N + b;
-                                    if (a.perm[sb] < 0) continue;
+                        const unsigned long long hb = __ballot(hit);
 #pragma unroll
-                                    for (int k = 0; k < M; ++k)
-                                        if (iorig[k] >= 0 && !(s == 13 && ci * M + k >= sb))
-                                            mask |= 1ull << (b * M + k);
-                                }
-                                // force-field exclusions in this image (within rlist)
+                        for (int g = 0; g < P; ++g) {
+                            const int sg = __shfl(src, g * PAIRS, 64);
+                            if (sg >= 0 && ((hb >> (g * PAIRS)) & GMASK)) accepted |= 1ull << sg;
+                        }
+                    }
+                    if (FILL) {
+                        // masks of the accepted candidates, in lane (= candidate) order
+                        unsigned long long todo = accepted;
+                        int base = wpos;
+                        while (todo) {
+                            int src = -1, rank = 0;
 #pragma unroll
-                                for (int k = 0; k < M; ++k) {
-                                    if (iorig[k] < 0) continue;
-                                    for (int e = a.excl_off[iorig[k]]; e < a.excl_off[iorig[k] + 1]; ++e) {
-                                        const int ps = a.slot_of[a.excl_idx[e]];
-                                        const int b = ps - cj * N;
-                                        if (b < 0 || b >= N) continue;
-                                        const unsigned long long bit = 1ull << (b * M + k);
-                                        if (!(mask & bit)) continue;
-                                        const float4 pb = a.xs[ps];
-                                        if (sq3(six[k] - pb.x, siy[k] - pb.y, siz[k] - pb.z) < a.rl2) mask &= ~bit;
+                            for (int g = 0; g < P; ++g) {
+                                const int f = todo ? __ffsll((long long)todo) - 1 : -1;
+                                if (f >= 0) todo &= todo - 1;
+                                if (g == grp) src = f;
+                            }
+                            if (src >= 0) rank = __popcll(accepted & ((1ull << src) - 1ull));
+                            const int cjc = __shfl(cj, src < 0 ? 0 : src, 64);
+                            const float d2c = __shfl(d2, src < 0 ? 0 : src, 64);
+                            bool bit = false;
+                            if (src >= 0 && iorig >= 0) {
+                                const int sb = cjc * N + pb;
+                                const int jorig = a.perm[sb];
+                                if (jorig >= 0 && !(s == 13 && ci * M + pa >= sb)) {
+                                    bit = true;
+                                    bool excluded = false;
+                                    for (int e = a.excl_off[iorig]; e < a.excl_off[iorig + 1]; ++e)
+                                        excluded |= a.excl_idx[e] == jorig;
+                                    if (excluded) {
+                                        const float4 pbv = a.xs[sb];
+                                        if (sq3(pix - pbv.x, piy - pbv.y, piz - pbv.z) < a.rl2) bit = false;
                                     }
                                 }
+                            }
+                            const unsigned long long mb = __ballot(bit);
+                            if (src >= 0 && lane % PAIRS == 0) {
+                                const unsigned long long mask = PAIRS == 64 ? mb : ((mb >> (grp * PAIRS)) & GMASK);
                                 nb_jentry en;
-                                en.cj = cj;
+                                en.cj = cjc;
                                 en.shift = s;
                                 en.mlo = (uint32_t)mask;
                                 en.mhi = (uint32_t)(mask >> 32);
-                                a.entries[idx] = en;
+                                a.entries[base + rank] = en;
+                                a.keys[base + rank] = d2c;
                             }
-                            wpos += __popcll(ballot);
-                        } else {
-                            cnt += __popcll(ballot);
                         }
+                        wpos += __popcll(accepted);
+                    } else {
+                        cnt += __popcll(accepted);
                     }
                 }
+            }
         }
     }
     if (!FILL) {
@@ -167,6 +232,32 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             const int je = js + mxn::kItemEntries < end ? js + mxn::kItemEntries : end;
             a.items[ipos + k] = make_int4(ci, js, je, 0);
         }
+    }
+}
+
+// Order the entries of each i-cluster by bounding-box distance (ties by
+// canonical position), so that the far entries, whose pairs mostly lie beyond
+// the cut-off, share force-kernel passes whose pair work can be skipped.
+// One wavefront per i-cluster, rank sort with the keys staged in LDS.
+__global__ __launch_bounds__(64) void k_sort_entries(const int *ci_start, const int *totals, long cap_entries,
+                                                     long cap_items, const nb_jentry *in, const float *keys,
+                                                     nb_jentry *out) {
+    __shared__ float sk[1024];
+    if ((long)totals[0] > cap_entries || (long)totals[1] > cap_items) return;
+    const int ci = blockIdx.x, lane = threadIdx.x;
+    const int b = ci_start[ci], n = ci_start[ci + 1] - b;
+    const bool staged = n <= 1024;
+    if (staged)
+        for (int i = lane; i < n; i += 64) sk[i] = keys[b + i];
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+        const float ki = staged ? sk[i] : keys[b + i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) {
+            const float kj = staged ? sk[j] : keys[b + j];
+            r += (kj < ki) || (kj == ki && j < i);
+        }
+        out[b + r] = in[b + i];
     }
 }
 
@@ -191,7 +282,7 @@ void run(nb_list *l, SearchArgs &a, bool fill, int nblocks, hipStream_t st) {
 
 namespace mxn {
 
-int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync) {
+int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync, bool by_distance) {
     const nb_grid *g = l->grid;
     nb_ctx *ctx = l->ctx;
     hipStream_t st = ctx->stream;
@@ -236,6 +327,10 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
             long ce = ne + ne / 8 + 1024, cit = ni + ni / 8 + 256;
             int rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
             if (rc) return rc;
+            rc = ensure(l->entries_canon, (size_t)ce * sizeof(nb_jentry));
+            if (rc) return rc;
+            rc = ensure(l->keys, (size_t)ce * sizeof(float));
+            if (rc) return rc;
             rc = ensure(l->items, (size_t)cit * sizeof(int4));
             if (rc) return rc;
             l->cap_entries = ce;
@@ -243,13 +338,18 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         }
         l->last_entries = ne;
     }
-    a.entries = (nb_jentry *)l->entries.p;
+    a.entries = (nb_jentry *)(by_distance ? l->entries_canon.p : l->entries.p);
+    a.keys = (float *)l->keys.p;
     a.items = (int4 *)l->items.p;
     a.cap_entries = l->cap_entries;
     a.cap_items = l->cap_items;
     if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, true, nblocks, st);
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
+    if (by_distance)
+        k_sort_entries<<<nci_cap, 64, 0, st>>>((const int *)l->ci_start.p, (const int *)l->totals.p, l->cap_entries,
+                                           l->cap_items, (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
+                                           (nb_jentry *)l->entries.p);
     k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_entries, l->cap_items, ctx->d_flags);
     MXN_HIP(hipGetLastError());
     return NB_OK;

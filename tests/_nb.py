@@ -11,7 +11,7 @@ F = synth.COULOMB_F
 class GpuSystem:
     """A water box on cuda:0 with a grid and a pair list built through the C ABI."""
 
-    def __init__(self, box: synth.WaterBox, shape, rlist, rbb=-1.0, ctx=None, flags=0):
+    def __init__(self, box: synth.WaterBox, shape, rlist, rbb=-1.0, ctx=None, flags=0, variant=0):
         import torch
         import paper_1306_1737_amd as mxn
         self.mxn = mxn
@@ -26,6 +26,7 @@ class GpuSystem:
         self.ei = torch.from_numpy(box.excl_idx).to(self.dev)
         self.lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(self.dev)
         self.ctx = ctx if ctx is not None else mxn.nb_create(0)
+        mxn.nb_set_force_variant(self.ctx, variant)
         self.grid = mxn.nb_grid_sort(self.ctx, box.box, self.xyzq, self.type, shape)
         self.lst = mxn.nb_pairlist_build(self.ctx, self.grid, rlist, rbb, self.eo, self.ei, flags)
 

@@ -108,12 +108,21 @@ def test_pairlist_rbb_extremes(ragged, rbb):
 
 
 def test_pairlist_deterministic(c1):
+    """Two builds give the same list; the distance-ordered storage exports the same canonical list and the
+    same forces."""
     s = GpuSystem(c1, (8, 8), 1.1)
     try:
         a = s.mxn.nb_list_export_canonical(s.lst)
+        f0, e0, _ = s.forces(1.0, 3.12, s.mxn.NB_ENERGY)
         s.lst = s.mxn.nb_pairlist_build(s.ctx, s.grid, 1.1, -1.0, s.eo, s.ei, 0, s.lst)
         b = s.mxn.nb_list_export_canonical(s.lst)
         _cmp_lists(a, b)
+        s.lst = s.mxn.nb_pairlist_build(s.ctx, s.grid, 1.1, -1.0, s.eo, s.ei, s.mxn.NB_LIST_BY_DISTANCE, s.lst)
+        c = s.mxn.nb_list_export_canonical(s.lst)
+        _cmp_lists(a, c)
+        f1, e1, _ = s.forces(1.0, 3.12, s.mxn.NB_ENERGY)
+        assert rel_rms(f1, f0) <= 1e-6
+        np.testing.assert_allclose(e1, e0, rtol=1e-7)
     finally:
         s.close()
 
@@ -123,10 +132,11 @@ def _oracle_forces(box, rc, beta, xyz=None, mode="brute"):
                          synth.lj_table_spce(), rc, beta, F, shift=True, mode=mode)
 
 
+@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_forces_energies_virial(c1, shape):
+def test_forces_energies_virial(c1, shape, variant):
     rc, rlist, beta = 0.9, 0.9, 3.47
-    s = GpuSystem(c1, shape, rlist)
+    s = GpuSystem(c1, shape, rlist, variant=variant)
     try:
         f, e, v = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
         fr, er, vr = _oracle_forces(c1, rc, beta)
@@ -143,12 +153,14 @@ def test_forces_energies_virial(c1, shape):
         s.close()
 
 
-def test_forces_buffered_after_motion(c1):
+@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forces_buffered_after_motion(c1, shape, variant):
     """List built at rlist = rc + 0.1 from step-0 positions, forces at step 9 of ballistic motion (300 K, 2 fs)."""
     rc, rlist, beta = 0.9, 1.0, 3.47
     v = synth.velocities(c1.mass, 300.0, seed=5)
     x9 = synth.free_flight(c1.xyz, v, 0.002, 10)[9]
-    s = GpuSystem(c1, (8, 8), rlist)
+    s = GpuSystem(c1, shape, rlist, variant=variant)
     try:
         xq = s.torch.from_numpy(c1.xyzq(x9)).to(s.dev)
         f, e, _ = s.forces(rc, beta, s.mxn.NB_ENERGY, xyzq_now=xq)
@@ -173,13 +185,14 @@ def test_accumulate_flag(c1):
         s.close()
 
 
-def test_tiny_and_ragged(ragged):
+@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+def test_tiny_and_ragged(ragged, variant):
     """One water in a box; and a ragged 291-atom box, all shapes."""
     one = synth.water_box(1, 2.5, seed=1)
     for box, rc in ((one, 1.0), (ragged, 1.0)):
         fr, er, vr = _oracle_forces(box, rc, 3.12)
         for shape in SHAPES:
-            s = GpuSystem(box, shape, rc)
+            s = GpuSystem(box, shape, rc, variant=variant)
             try:
                 f, e, v = s.forces(rc, 3.12, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
                 assert rel_rms(f, fr) <= 1e-5
@@ -204,6 +217,10 @@ def test_production_box_sampled():
             sel = gpu[(gpu["ci"] >= c0) & (gpu["ci"] < c0 + 40)]
             _cmp_lists(sel, ref)
         f, e, v = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
+        s.mxn.nb_set_force_variant(s.ctx, s.mxn.NB_FORCE_COMPACT)
+        fd, ed, vd = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
+        assert rel_rms(fd, f) <= 1e-6
+        np.testing.assert_allclose(ed, e, rtol=1e-7)
         sub = np.random.default_rng(0).choice(box.n, 3000, replace=False).astype(np.int32)
         fs, _ = oracle.forces_subset(box.xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx,
                                      synth.lj_table_spce(), rc, beta, F, sub)
