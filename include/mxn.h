@@ -50,6 +50,7 @@ typedef enum {
 typedef struct nb_ctx nb_ctx;
 typedef struct nb_grid nb_grid;
 typedef struct nb_list nb_list;
+typedef struct nb_mlp nb_mlp;
 
 /* Cluster shape M x N: i-clusters of M particles against j-clusters of N
  * particles (Sec. 2.2 "The M x N algorithm").  Supported: 4x4, 4x8, 8x8. */
@@ -210,6 +211,26 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
 enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1 };
 int nb_set_force_variant(nb_ctx *ctx, int variant);
 
+/* ---------------------------------------------------------- exact recount */
+
+/*
+ * Missed-pair energy of a finite Verlet buffer, counted exactly (Sec. 5
+ * "Effective pair list buffering"; the appendix bounds the same quantity).
+ * The list must have been built on `grid` from the undisplaced positions at
+ * a large radius rl with rbb = rl - c_bb.  A cluster pair is then listed at
+ * any radius r <= rl iff tau = min(d_bb + c_bb, d_min) < r (bounding-box and
+ * smallest particle distance at sort time).  For every real, non-excluded
+ * pair of the half list whose displaced distance r_t is below p->rc, the
+ * shifted potential V(r_t) - V(rc) (always shifted here) is added to
+ * hist[min(floor((tau - rc)/db), nbins - 1)] when tau >= rc.  The missed
+ * energy at buffer r_b = k*db is then sum(hist[k:]).
+ *   xyzq_t  DEVICE float[4n] displaced positions, original order, in the same
+ *           periodic images as the sorted positions (not re-wrapped)
+ *   hist    DEVICE double[nbins], overwritten
+ */
+int nb_recount(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_t, const nb_params *p,
+               float c_bb, float db, int nbins, double *hist);
+
 /* -------------------------------------------------------- buffer estimate */
 
 /*
@@ -238,14 +259,47 @@ enum { NB_BUFFER_ANALYTIC = 0, NB_BUFFER_MLP = 1, NB_BUFFER_AUTO = 2 };
  * q->target.  ANALYTIC: the appendix bound (free-particle Gaussian
  * displacements over t = (nstlist-1)*dt, second-order expansion of the
  * potential at rc, second-order term with 2 sigma^2 as the integral gives),
- * summed as 1/2 sum_a N_a sum_b |dV_ab| and divided by N*nstlist*dt.
- * MLP / AUTO: the learned predictor of an nb_mlp attached with
- * nb_buffer_set_mlp, falling back to ANALYTIC outside its training range or
- * on a non-finite output (*used_fallback = 1).  Host only, synchronous.
+ * summed as 1/2 sum_a N_a sum_b |dV_ab| and divided by N*nstlist*dt; host
+ * FP64.  MLP / AUTO: the learned predictor attached with nb_buffer_set_mlp
+ * (its inference kernel on the context's stream, synchronous), giving
+ * min(prediction + margin, analytic buffer); outside the model's feature
+ * ranges, for a non-finite prediction, or (AUTO) without a model, the
+ * analytic buffer is returned and *used_fallback = 1.  MLP without a model:
+ * NB_ERR_STATE.
+ *   ctx        may be NULL for ANALYTIC
  *   rb_out     nm;  drift_out  analytic drift estimate at *rb_out
  */
 int nb_buffer_estimate(nb_ctx *ctx, const nb_buffer_query *q, int mode, double *rb_out, double *drift_out,
                        int *used_fallback);
+
+/* ------------------------------------------------ learned buffer predictor */
+
+/*
+ * A small multilayer perceptron that predicts the minimal Verlet buffer from
+ * 8 features: temperature (K), mass-weighted displacement width
+ * sqrt(kB T t^2 <1/m>) (nm, t = (nstlist-1) dt), list lifetime (steps), mass
+ * density (g/cm^3), cut-off (nm), and the cluster shape one-hot
+ * (4x4, 4x8, 8x8).  It is trained on labels from nb_recount (the paper's
+ * drift criterion evaluated exactly, Sec. 5).  Architecture 8-64-64-1, tanh
+ * hidden layers, softplus output, MSE loss, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8); features are normalised to [-1, 1] with the ranges lo/hi given
+ * at creation.  Parameters: NB_MLP_PARAMS floats, order W1 (64x8 row-major),
+ * b1, W2 (64x64 row-major), b2, w3, b3.  Kernels run on the context's stream.
+ *   X  DEVICE float[batch*8] raw features, row-major;  y  DEVICE float[batch]
+ */
+enum { NB_MLP_FEATURES = 8, NB_MLP_PARAMS = 4801 };
+int nb_mlp_create(nb_ctx *ctx, const float *params_host, const double lo[8], const double hi[8], nb_mlp **mlp);
+void nb_mlp_free(nb_mlp *mlp);
+/* Synchronous copy of the current parameters to HOST params[NB_MLP_PARAMS]. */
+int nb_mlp_get_params(nb_mlp *mlp, float *params);
+/* One Adam step on a minibatch (one workgroup); loss: DEVICE float or NULL. */
+int nb_mlp_train_step(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float lr, float *loss);
+/* Gradient of the batch loss (DEVICE float[NB_MLP_PARAMS]) without updating the model. */
+int nb_mlp_grad(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float *grad, float *loss);
+int nb_mlp_infer(nb_ctx *ctx, const nb_mlp *mlp, const float *X, int batch, float *y);
+/* Attach (mlp != NULL) or detach the predictor used by nb_buffer_estimate;
+ * margin (nm) is added to its prediction. */
+int nb_buffer_set_mlp(nb_ctx *ctx, const nb_mlp *mlp, double margin);
 
 /* ------------------------------------------------------------ instrumentation */
 

@@ -447,6 +447,8 @@ long oracle_pairlist(int n_slots, int M, int N, const float *xs, const int *perm
  * This routine returns per-pair (tau, V_shift(r_t)) contributions binned by
  * tau into hist[nb] (FP64) such that E(k db) = sum_{k' >= k} hist[k'].
  *
+ * Domain: the pairs of cluster pairs listed at rl itself (tau < rl); the
+ * largest buffer considered is rl - rc.
  * Brute force over all pairs and all 27 images for tiny boxes: it uses the
  * canonical grid sort of section 2 to form the clusters.
  */
@@ -511,6 +513,7 @@ long oracle_recount(int n, const float *xyz0, const float *xyzt, const float *q,
                 }
                 double tau = dbb + (double)c_bb;
                 if (dmin < tau) tau = dmin;
+                if (tau >= rl) continue;           /* not listed even at the largest radius */
                 for (int a = 0; a < M; ++a) {
                     int sa = ci * M + a, oa = perm[sa];
                     if (oa < 0) continue;

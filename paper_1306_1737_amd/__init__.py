@@ -30,8 +30,11 @@ EXPORTS = [
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
-    "nb_list_stats", "nb_set_force_variant",
+    "nb_list_stats", "nb_set_force_variant", "nb_recount",
+    "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
+    "nb_buffer_set_mlp",
 ]
+NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
 
@@ -96,6 +99,11 @@ def lib():
             "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
             "nb_list_stats": ([vp, vp, vp, vp, f, vp], i),
             "nb_set_force_variant": ([vp, i], i),
+            "nb_recount": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), f, f, i, vp], i),
+            "nb_mlp_create": ([vp, vp, vp, vp, pvp], i), "nb_mlp_free": ([vp], None),
+            "nb_mlp_get_params": ([vp, vp], i), "nb_mlp_train_step": ([vp, vp, vp, vp, i, f, vp], i),
+            "nb_mlp_grad": ([vp, vp, vp, vp, i, vp, vp], i), "nb_mlp_infer": ([vp, vp, vp, i, vp], i),
+            "nb_buffer_set_mlp": ([vp, vp, d], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -251,6 +259,14 @@ def nb_forces(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=No
                            _ptr(virial)))
 
 
+# --------------------------------------------------------------- recount
+
+def nb_recount(ctx, grid, lst, xyzq_t, params, c_bb, db, nbins, hist):
+    """Missed-pair energy histogram (hist: (nbins,) float64 CUDA tensor, overwritten)."""
+    _check(lib().nb_recount(ctx, grid, lst, _ptr(xyzq_t), ctypes.byref(params), float(c_bb), float(db), int(nbins),
+                            _ptr(hist)))
+
+
 # ------------------------------------------------------- buffer estimate
 
 def nb_buffer_estimate(ctx, *, T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape,
@@ -287,3 +303,44 @@ def nb_list_stats(ctx, grid, lst, xyzq_now, rc):
     c = (ctypes.c_longlong * 4)()
     _check(lib().nb_list_stats(ctx, grid, lst, _ptr(xyzq_now), float(rc), c))
     return tuple(int(v) for v in c)
+
+
+# ------------------------------------------------------------------- MLP
+
+def nb_mlp_create(ctx, params, lo, hi):
+    """params: host float32[4801]; lo, hi: feature ranges (8 each)."""
+    import numpy as np
+    p = np.ascontiguousarray(params, np.float32)
+    if p.size != NB_MLP_PARAMS:
+        raise ValueError("need %d parameters" % NB_MLP_PARAMS)
+    lo = np.ascontiguousarray(lo, np.float64); hi = np.ascontiguousarray(hi, np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().nb_mlp_create(ctx, _ptr(p), _ptr(lo), _ptr(hi), ctypes.byref(h)))
+    return h
+
+
+def nb_mlp_free(mlp):
+    lib().nb_mlp_free(mlp)
+
+
+def nb_mlp_get_params(mlp):
+    import numpy as np
+    p = np.empty(NB_MLP_PARAMS, np.float32)
+    _check(lib().nb_mlp_get_params(mlp, _ptr(p)))
+    return p
+
+
+def nb_mlp_train_step(ctx, mlp, X, y, lr, loss=None):
+    _check(lib().nb_mlp_train_step(ctx, mlp, _ptr(X), _ptr(y), int(X.shape[0]), float(lr), _ptr(loss)))
+
+
+def nb_mlp_grad(ctx, mlp, X, y, grad, loss=None):
+    _check(lib().nb_mlp_grad(ctx, mlp, _ptr(X), _ptr(y), int(X.shape[0]), _ptr(grad), _ptr(loss)))
+
+
+def nb_mlp_infer(ctx, mlp, X, y):
+    _check(lib().nb_mlp_infer(ctx, mlp, _ptr(X), int(X.shape[0]), _ptr(y)))
+
+
+def nb_buffer_set_mlp(ctx, mlp, margin):
+    _check(lib().nb_buffer_set_mlp(ctx, mlp, float(margin)))

@@ -25,6 +25,8 @@ SOURCES = {
     "grid.hip": ["-ffp-contract=off"],
     "pairlist.hip": ["-ffp-contract=off"],
     "forces.hip": [],
+    "recount.hip": [],
+    "mlp.hip": [],
     "buffer.cpp": [],
 }
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",

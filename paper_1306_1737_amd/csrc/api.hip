@@ -522,17 +522,183 @@ int nb_timing_read(nb_ctx *c, double *ms, long *launches) {
     return NB_OK;
 }
 
+// ---------------------------------------------------------------- recount
+
+int nb_recount(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_t, const nb_params *p, float c_bb,
+               float db, int nbins, double *hist) {
+    if (!c || !g || !l || !xyzq_t || !p || !hist || !p->c6c12) return fail(NB_ERR_ARG, "nb_recount: null argument");
+    if (g->ctx != c || l->ctx != c || l->grid != g || l->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, "nb_recount: grid/list/context mismatch");
+    if (nbins < 1 || !(db > 0.0f) || !(c_bb >= 0.0f)) return fail(NB_ERR_ARG, "nb_recount: bad bins");
+    if (p->ntypes < 1 || p->ntypes > kMaxTypes || !(p->rc > 0.0f) || !(p->rc <= l->rlist) || !(p->beta >= 0.0f))
+        return fail(NB_ERR_ARG, "nb_recount: bad interaction parameters");
+    if ((double)p->beta * p->rc > 4.0) return fail(NB_ERR_UNSUPPORTED, "nb_recount: beta*rc > 4");
+    const float want = l->rlist - c_bb > 0.0f ? l->rlist - c_bb : 0.0f;
+    if (l->rbb != want) return fail(NB_ERR_ARG, "nb_recount: the list must be built with rbb = rlist - c_bb");
+    MXN_HIP(hipSetDevice(c->device));
+    return launch_recount(c, g, l, xyzq_t, p, c_bb, db, nbins, hist);
+}
+
+// -------------------------------------------------------------------- MLP
+
+int nb_mlp_create(nb_ctx *c, const float *params, const double lo[8], const double hi[8], nb_mlp **out) {
+    if (!c || !params || !lo || !hi || !out) return fail(NB_ERR_ARG, "nb_mlp_create: null argument");
+    for (int i = 0; i < 8; ++i)
+        if (!(hi[i] > lo[i]) || !std::isfinite(lo[i]) || !std::isfinite(hi[i]))
+            return fail(NB_ERR_ARG, "nb_mlp_create: every feature range needs hi > lo");
+    MXN_HIP(hipSetDevice(c->device));
+    nb_mlp *m = new (std::nothrow) nb_mlp();
+    if (!m) return fail(NB_ERR_OOM, "nb_mlp_create: host allocation");
+    m->ctx = c;
+    float lof[8], hif[8];
+    for (int i = 0; i < 8; ++i) {
+        m->lo_h[i] = lo[i];
+        m->hi_h[i] = hi[i];
+        lof[i] = (float)lo[i];
+        hif[i] = (float)hi[i];
+    }
+    int rc = ensure(m->params, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->m, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->v, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->step, 16);
+    rc = rc ? rc : ensure(m->lo, 32);
+    rc = rc ? rc : ensure(m->hi, 32);
+    hipError_t e = hipSuccess;
+    if (rc == NB_OK) {
+        e = hipMemcpy(m->params.p, params, kMlpParams * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(m->m.p, 0, kMlpParams * 4);
+        if (e == hipSuccess) e = hipMemset(m->v.p, 0, kMlpParams * 4);
+        if (e == hipSuccess) e = hipMemset(m->step.p, 0, 16);
+        if (e == hipSuccess) e = hipMemcpy(m->lo.p, lof, 32, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->hi.p, hif, 32, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(NB_ERR_HIP, std::string("nb_mlp_create: ") + hipGetErrorString(e));
+    }
+    if (rc != NB_OK) {
+        DevBuf *bufs[] = {&m->params, &m->m, &m->v, &m->step, &m->lo, &m->hi};
+        for (DevBuf *b : bufs) release(*b);
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return NB_OK;
+}
+
+void nb_mlp_free(nb_mlp *m) {
+    if (!m) return;
+    hipSetDevice(m->ctx->device);
+    hipStreamSynchronize(m->ctx->stream);
+    if (m->ctx->mlp == m) m->ctx->mlp = nullptr;
+    DevBuf *bufs[] = {&m->params, &m->m, &m->v, &m->step, &m->lo, &m->hi};
+    for (DevBuf *b : bufs) release(*b);
+    delete m;
+}
+
+int nb_mlp_get_params(nb_mlp *m, float *params) {
+    if (!m || !params) return fail(NB_ERR_ARG, "nb_mlp_get_params: null argument");
+    MXN_HIP(hipSetDevice(m->ctx->device));
+    MXN_HIP(hipStreamSynchronize(m->ctx->stream));
+    MXN_HIP(hipMemcpy(params, m->params.p, kMlpParams * 4, hipMemcpyDeviceToHost));
+    return NB_OK;
+}
+
+static int mlp_check(nb_ctx *c, const nb_mlp *m, const float *X, int batch) {
+    if (!c || !m || !X) return fail(NB_ERR_ARG, "nb_mlp: null argument");
+    if (m->ctx != c) return fail(NB_ERR_STATE, "nb_mlp: model belongs to another context");
+    if (batch < 1) return fail(NB_ERR_ARG, "nb_mlp: batch must be >= 1");
+    return NB_OK;
+}
+
+int nb_mlp_train_step(nb_ctx *c, nb_mlp *m, const float *X, const float *y, int batch, float lr, float *loss) {
+    CHECK(mlp_check(c, m, X, batch));
+    if (!y || !(lr > 0.0f)) return fail(NB_ERR_ARG, "nb_mlp_train_step: need targets and lr > 0");
+    MXN_HIP(hipSetDevice(c->device));
+    return launch_mlp_step(c, m, X, y, batch, lr, loss, nullptr);
+}
+
+int nb_mlp_grad(nb_ctx *c, nb_mlp *m, const float *X, const float *y, int batch, float *grad, float *loss) {
+    CHECK(mlp_check(c, m, X, batch));
+    if (!y || !grad) return fail(NB_ERR_ARG, "nb_mlp_grad: need targets and a gradient buffer");
+    MXN_HIP(hipSetDevice(c->device));
+    return launch_mlp_step(c, m, X, y, batch, 0.0f, loss, grad);
+}
+
+int nb_mlp_infer(nb_ctx *c, const nb_mlp *m, const float *X, int batch, float *y) {
+    CHECK(mlp_check(c, m, X, batch));
+    if (!y) return fail(NB_ERR_ARG, "nb_mlp_infer: output is null");
+    MXN_HIP(hipSetDevice(c->device));
+    return launch_mlp_infer(c, m, X, batch, y);
+}
+
+int nb_buffer_set_mlp(nb_ctx *c, const nb_mlp *m, double margin) {
+    if (!c) return fail(NB_ERR_ARG, "nb_buffer_set_mlp: ctx is null");
+    if (m && m->ctx != c) return fail(NB_ERR_STATE, "nb_buffer_set_mlp: model belongs to another context");
+    if (!(margin >= 0.0)) return fail(NB_ERR_ARG, "nb_buffer_set_mlp: margin must be >= 0");
+    c->mlp = m;
+    c->mlp_margin = margin;
+    return NB_OK;
+}
+
 // ------------------------------------------------------------ buffer size
+
+// The predictor's inputs from a query: temperature, mass-weighted
+// displacement width sqrt(kB T t^2 <1/m>) over t = (nstlist-1) dt, list
+// lifetime in steps, mass density (g/cm^3), cut-off, cluster shape one-hot.
+static bool buffer_features(const nb_buffer_query &q, float f[8]) {
+    double n = 0.0, inv_m = 0.0, mass = 0.0;
+    for (int a = 0; a < q.ntypes; ++a) {
+        n += q.count[a];
+        inv_m += q.count[a] / q.mass[a];
+        mass += q.count[a] * q.mass[a];
+    }
+    if (!(n > 0.0)) return false;
+    const double t = (q.nstlist - 1) * q.dt;
+    f[0] = (float)q.T;
+    f[1] = (float)std::sqrt(0.0083144626 * q.T * t * t * inv_m / n);
+    f[2] = (float)q.nstlist;
+    f[3] = (float)(mass / (q.volume * 602.214076));
+    f[4] = (float)q.rc;
+    const int s = q.shape.m == 4 && q.shape.n == 4 ? 0 : (q.shape.m == 4 && q.shape.n == 8 ? 1 : (q.shape.m == 8 && q.shape.n == 8 ? 2 : -1));
+    if (s < 0) return false;
+    f[5] = s == 0; f[6] = s == 1; f[7] = s == 2;
+    return true;
+}
 
 int nb_buffer_estimate(nb_ctx *c, const nb_buffer_query *q, int mode, double *rb_out, double *drift_out,
                        int *used_fallback) {
-    (void)c;
     CHECK(validate_query(q));
     if (!rb_out) return fail(NB_ERR_ARG, "nb_buffer_estimate: rb_out is null");
     if (mode != NB_BUFFER_ANALYTIC && mode != NB_BUFFER_MLP && mode != NB_BUFFER_AUTO)
         return fail(NB_ERR_ARG, "nb_buffer_estimate: unknown mode");
-    if (used_fallback) *used_fallback = mode != NB_BUFFER_ANALYTIC;
-    return analytic_buffer(*q, rb_out, drift_out);
+    double rb_a = 0.0, d_a = 0.0;
+    CHECK(analytic_buffer(*q, &rb_a, &d_a));
+    int fb = mode != NB_BUFFER_ANALYTIC;
+    double rb = rb_a;
+    if (mode != NB_BUFFER_ANALYTIC) {
+        if (!c) return fail(NB_ERR_ARG, "nb_buffer_estimate: the learned modes need a context");
+        if (!c->mlp && mode == NB_BUFFER_MLP) return fail(NB_ERR_STATE, "nb_buffer_estimate: no model attached");
+        float f[8];
+        bool in_range = c->mlp && buffer_features(*q, f);
+        if (in_range)
+            for (int i = 0; i < 5; ++i)
+                if (!(f[i] >= c->mlp->lo_h[i] && f[i] <= c->mlp->hi_h[i])) in_range = false;   // outside training data
+        if (in_range) {
+            MXN_HIP(hipSetDevice(c->device));
+            CHECK(ensure(c->mlp_io, 64));
+            float y = NAN;
+            MXN_HIP(hipMemcpyAsync(c->mlp_io.p, f, sizeof f, hipMemcpyHostToDevice, c->stream));
+            CHECK(launch_mlp_infer(c, c->mlp, (const float *)c->mlp_io.p, 1, (float *)c->mlp_io.p + 8));
+            MXN_HIP(hipMemcpyAsync(&y, (float *)c->mlp_io.p + 8, sizeof y, hipMemcpyDeviceToHost, c->stream));
+            MXN_HIP(hipStreamSynchronize(c->stream));
+            if (std::isfinite(y) && y >= 0.0f) {
+                rb = std::fmin((double)y + c->mlp_margin, rb_a);
+                fb = 0;
+            }
+        }
+    }
+    *rb_out = rb;
+    if (drift_out) *drift_out = rb == rb_a ? d_a : analytic_drift(*q, rb);
+    if (used_fallback) *used_fallback = fb;
+    return NB_OK;
 }
 
 }  // extern "C"

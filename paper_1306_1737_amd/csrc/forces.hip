@@ -576,6 +576,22 @@ void launch_shape(const ForceArgs &a, unsigned flags, int nb, size_t lds, int va
 
 namespace mxn {
 
+int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now) {
+    ForceArgs a{};
+    a.nslots = (const int *)g->nslots.p;
+    a.perm = (const int *)g->perm.p;
+    a.img_s = (const int *)g->img_s.p;
+    a.xyzq_now = (const float4 *)xyzq_now;
+    a.xs_now = (float4 *)g->xs_now.p;
+    a.fs = (float *)g->fs.p;
+    a.slots_cap = g->slots_cap;
+    a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
+    a.flags = ctx->d_flags;
+    k_gather<<<(g->slots_cap + 255) / 256, 256, 0, ctx->stream>>>(a);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
 int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc,
                  unsigned long long *d_counts) {
     hipStream_t st = ctx->stream;

@@ -48,6 +48,8 @@ struct nb_jentry {
     uint32_t mlo, mhi;
 };
 
+struct nb_mlp;
+
 struct nb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -56,6 +58,9 @@ struct nb_ctx {
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
+    const nb_mlp *mlp = nullptr;   // attached buffer predictor (nb_buffer_set_mlp)
+    double mlp_margin = 0.0;
+    mxn::DevBuf mlp_io;            // one feature row and one output for nb_buffer_estimate
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timers[NB_TIMER_COUNT];
     std::vector<hipEvent_t> event_pool;
 };
@@ -96,7 +101,18 @@ struct nb_list {
     long grid_generation = -1;
 };
 
+struct nb_mlp {
+    nb_ctx *ctx = nullptr;
+    mxn::DevBuf params, m, v, step, lo, hi;
+    double lo_h[8] = {0}, hi_h[8] = {0};
+};
+
 namespace mxn {
+
+constexpr int kMlpParams = 4801;
+int launch_mlp_step(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float lr, float *loss,
+                    float *grad_out);
+int launch_mlp_infer(nb_ctx *ctx, const nb_mlp *mlp, const float *X, int batch, float *y);
 
 // kernel launchers (grid.hip, pairlist.hip, forces.hip)
 int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type);
@@ -111,6 +127,8 @@ struct ScopedTimer {
     ScopedTimer(nb_ctx *c, int w);
     ~ScopedTimer();
 };
+int launch_recount(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_t, const nb_params *p, float c_bb,
+                   float db, int nbins, double *hist);
 int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc,
                  unsigned long long *d_counts);
 // exclusive scan of n ints on one workgroup; writes out[0..n] (out[n] = total) and *total

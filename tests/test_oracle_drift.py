@@ -122,3 +122,32 @@ def test_recount_matches_bruteforce():
                         v += qq * (math.erfc(beta * rr) / rr - math.erfc(beta * rc) / rc)
                         miss += v
             assert hist[k:].sum() == pytest.approx(miss, rel=1e-6, abs=1e-9)
+
+
+def test_mlp_backprop_matches_central_differences():
+    """FP64 backpropagation of the buffer MLP equals central finite differences of its loss."""
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    p = rng.normal(0, 0.3, mlp.NPARAM)
+    X = rng.uniform(-1, 1, (7, mlp.NF))
+    t = rng.uniform(0, 0.3, 7)
+    loss, g = mlp.loss_and_grad(p, X, t)
+    idx = rng.choice(mlp.NPARAM, 60, replace=False)
+    idx = np.concatenate([idx, [0, 511, 512 + 63, mlp.NPARAM - 1, mlp.NPARAM - 2]])
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(p); e[k] = h
+        fd = (mlp.loss_and_grad(p + e, X, t)[0] - mlp.loss_and_grad(p - e, X, t)[0]) / (2 * h)
+        assert fd == pytest.approx(g[k], rel=1e-5, abs=1e-9)
+
+
+def test_mlp_special_cases():
+    """Zero weights: the output is softplus(b3) for any input; softplus(0) = ln 2; Adam's first step
+    moves every parameter by lr g/(|g| + eps) (bias-corrected m = g, v = g^2)."""
+    from oracle import mlp
+    p = np.zeros(mlp.NPARAM); p[-1] = 0.0
+    y, _ = mlp.forward(p, np.random.default_rng(0).uniform(-1, 1, (5, mlp.NF)))
+    np.testing.assert_allclose(y, np.log(2.0), rtol=1e-15)
+    g = np.random.default_rng(1).normal(size=mlp.NPARAM)
+    p1, m, v = mlp.adam_step(np.zeros_like(g), g, np.zeros_like(g), np.zeros_like(g), 1, 0.01)
+    np.testing.assert_allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9)
