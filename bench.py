@@ -66,6 +66,92 @@ def cpu_baseline(box, w):
                       % (len(sub), box.n, dt, cpu)}
 
 
+def _gen_box(args):
+    import synth
+    nw, seed = args
+    return synth.water_box(int(nw), synth.box_edge_for(int(nw)), seed=int(seed))
+
+
+def bench_batched(args):
+    """256 uneven water boxes (1 500-24 000 atoms, log-uniform, seeded), rc 1.0 / rlist 1.1 nm: one step =
+    list rebuild of every replica + 10 force steps; the 10 force steps run either as one captured graph
+    of the batched launch (replayed), or as per-replica nb_forces launches."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1737_amd as mxn
+    from paper_1306_1737_amd import autotune
+    sizes = synth.batched_sizes(256)
+    print("[bench] generating %d replicas (%d atoms)" % (len(sizes), 3 * int(sizes.sum())), file=sys.stderr,
+          flush=True)
+    # the generator runs in C through ctypes, which releases the GIL: threads suffice
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:
+        boxes = list(pool.map(_gen_box, [(nw, 5000 + k) for k, nw in enumerate(sizes)]))
+    dev = torch.device("cuda:0")
+    rc, rlist, beta = 1.0, 1.1, 3.12
+    ctx = mxn.nb_create(0)
+    print("[bench] autotuning", file=sys.stderr, flush=True)
+    tune = autotune.tune_batch(ctx, boxes, rc, rlist, beta, reps=3, cache=None)
+    shape = tuple(tune["shape"]) if args.shape == "auto" else tuple(int(v) for v in args.shape.split("x"))
+    group = tune["group"]
+    reps = autotune.build_replicas(ctx, boxes, shape, rlist)
+    lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+    params = mxn.make_params(rc, beta, synth.COULOMB_F, lj)
+    n = len(reps)
+    energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps], [r["xyzq"] for r in reps],
+                                [r["f"] for r in reps])
+    mxn.nb_batch_set_group(batch, group)
+    mxn.nb_batch_capture(ctx, batch, params, mxn.NB_ENERGY, energy)
+    e1 = [torch.zeros(2, dtype=torch.float64, device=dev) for _ in reps]
+
+    def rebuild():
+        for r in reps:
+            r["grid"] = mxn.nb_grid_sort(ctx, r["box"].box, r["xyzq"], r["type"], shape, r["grid"])
+            r["lst"] = mxn.nb_pairlist_build(ctx, r["grid"], rlist, -1.0, r["eo"], r["ei"], mxn.NB_LIST_ASYNC, r["lst"])
+
+    def step_graph():
+        rebuild()
+        for _ in range(10):
+            mxn.nb_batch_replay(ctx, batch)
+
+    def step_loop():
+        rebuild()
+        for _ in range(10):
+            for k, r in enumerate(reps):
+                mxn.nb_forces(ctx, r["grid"], r["lst"], r["xyzq"], params, mxn.NB_ENERGY, r["f"], e1[k])
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        mxn.nb_sync(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        mxn.nb_sync(ctx)
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ms_graph = timed(step_graph)
+    ms_loop = timed(step_loop)
+    listed = sum(mxn.nb_list_info(r["lst"])[0] for r in reps) * shape[0] * shape[1]
+    result = {"metric": "atom-pair interactions/s, batched replicas", "value": listed * 10 / (ms_graph * 1e-3),
+              "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "water-256-replicas", "replicas": n, "atoms": int(sum(b.n for b in boxes)),
+                         "shape": "%dx%d" % shape, "items_per_group": group, "rc": rc, "rlist": rlist,
+                         "force_steps_per_step": 10},
+              "per_replica_launches_ms_per_step": ms_loop, "speedup_vs_per_replica": ms_loop / ms_graph,
+              "autotune": tune["table"]}
+    mxn.nb_batch_free(batch)
+    autotune.free_replicas(reps)
+    mxn.nb_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +161,7 @@ def main():
     ap.add_argument("--variant", default="direct", choices=["direct", "compact"])
     ap.add_argument("--list-order", default="canonical", choices=["canonical", "distance"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="production", choices=["production", "batched"])
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates memory-traffic counters) and exit")
     args = ap.parse_args()
@@ -92,6 +179,10 @@ def main():
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
               "(the path would shard by replica or by spatial domain, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        if args.shape == "8x8":
+            args.shape = "auto"
+        return bench_batched(args)
 
     import numpy as np
     import torch

@@ -51,6 +51,7 @@ typedef struct nb_ctx nb_ctx;
 typedef struct nb_grid nb_grid;
 typedef struct nb_list nb_list;
 typedef struct nb_mlp nb_mlp;
+typedef struct nb_batch nb_batch;
 
 /* Cluster shape M x N: i-clusters of M particles against j-clusters of N
  * particles (Sec. 2.2 "The M x N algorithm").  Supported: 4x4, 4x8, 8x8. */
@@ -210,6 +211,41 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
  * Results agree to rounding; the choice is a tuning knob. */
 enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1 };
 int nb_set_force_variant(nb_ctx *ctx, int variant);
+
+/* ------------------------------------------------------- batched replicas */
+
+/*
+ * Many independent systems of one cluster shape (for example replicas of
+ * uneven size, each too small to fill the GPU: the paper notes GPU kernels
+ * need tens of thousands of particles to approach peak, Sec. 4.2) evaluated
+ * in one launch.  Each replica keeps its own grid and list; the work items
+ * of all replicas are concatenated on the device (a prefix of the replicas'
+ * item counts, so list sizes never travel to the host) and split into eight
+ * contiguous shares, one per XCD, one wavefront per item.  nb_batch_forces enqueues: batched coordinate gather,
+ * force kernel, batched force scatter and per-replica energy
+ * reduction -- no host synchronisation, no allocation, no memset, so the
+ * sequence can be captured in a HIP graph (nb_batch_capture) and replayed.
+ *   grids, lists        HOST arrays of n_rep handles (same shape); a replica's
+ *                       list must be rebuilt after its grid is re-sorted
+ *   xyzq_now, f         HOST arrays of n_rep DEVICE pointers bound to the
+ *                       batch: positions (original order) and forces
+ *   energy              DEVICE double[2*n_rep] (E_LJ, E_Coul per replica)
+ *   virial              DEVICE double[9*n_rep]
+ * If a replica's storage moved (a synchronous list build grew it), the next
+ * nb_batch_forces refreshes the batch's tables (synchronously); a captured
+ * graph must then be captured again (nb_batch_replay returns NB_ERR_STATE).
+ * The graph keeps the params' c6c12 pointer and the output pointers passed
+ * to nb_batch_capture.  Supported flags: NB_ENERGY, NB_VIRIAL, NB_ACCUMULATE.
+ */
+int nb_batch_create(nb_ctx *ctx, int n_rep, nb_grid *const *grids, nb_list *const *lists,
+                    const float *const *xyzq_now, float *const *f, nb_batch **batch);
+void nb_batch_free(nb_batch *batch);
+/* Work items (wavefronts) per workgroup of the batched force kernel: 1, 2, 4 or 8 (default 4). */
+int nb_batch_set_group(nb_batch *batch, int items_per_group);
+int nb_batch_forces(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy, double *virial);
+int nb_batch_capture(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy,
+                     double *virial);
+int nb_batch_replay(nb_ctx *ctx, nb_batch *batch);
 
 /* ---------------------------------------------------------- exact recount */
 

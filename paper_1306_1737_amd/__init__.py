@@ -33,6 +33,8 @@ EXPORTS = [
     "nb_list_stats", "nb_set_force_variant", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp",
+    "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
+    "nb_batch_replay",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
@@ -80,6 +82,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libmxn.so not built: run `python -m paper_1306_1737_amd.build`")
+        # PyTorch supplies device memory and streams and ships its own HIP runtime: load it first so that
+        # libmxn.so binds to the same runtime instance instead of a second copy from the system ROCm.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, ip, i, f, d, u = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_float, \
             ctypes.c_double, ctypes.c_uint
@@ -104,6 +109,10 @@ def lib():
             "nb_mlp_get_params": ([vp, vp], i), "nb_mlp_train_step": ([vp, vp, vp, vp, i, f, vp], i),
             "nb_mlp_grad": ([vp, vp, vp, vp, i, vp, vp], i), "nb_mlp_infer": ([vp, vp, vp, i, vp], i),
             "nb_buffer_set_mlp": ([vp, vp, d], i),
+            "nb_batch_create": ([vp, i, vp, vp, vp, vp, pvp], i), "nb_batch_free": ([vp], None),
+            "nb_batch_set_group": ([vp, i], i), "nb_batch_forces": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
+            "nb_batch_capture": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
+            "nb_batch_replay": ([vp, vp], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -344,3 +353,38 @@ def nb_mlp_infer(ctx, mlp, X, y):
 
 def nb_buffer_set_mlp(ctx, mlp, margin):
     _check(lib().nb_buffer_set_mlp(ctx, mlp, float(margin)))
+
+
+# ----------------------------------------------------------------- batch
+
+def nb_batch_create(ctx, grids, lists, xyzq_now, forces):
+    """grids, lists: handle lists; xyzq_now, forces: CUDA tensors per replica (bound to the batch)."""
+    n = len(grids)
+    ga = (ctypes.c_void_p * n)(*[g.value for g in grids])
+    la = (ctypes.c_void_p * n)(*[lst.value for lst in lists])
+    xa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xyzq_now])
+    fa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in forces])
+    h = ctypes.c_void_p()
+    _check(lib().nb_batch_create(ctx, n, ga, la, xa, fa, ctypes.byref(h)))
+    h._keep = (list(xyzq_now), list(forces))
+    return h
+
+
+def nb_batch_free(batch):
+    lib().nb_batch_free(batch)
+
+
+def nb_batch_set_group(batch, items_per_group):
+    _check(lib().nb_batch_set_group(batch, int(items_per_group)))
+
+
+def nb_batch_forces(ctx, batch, params, flags, energy=None, virial=None):
+    _check(lib().nb_batch_forces(ctx, batch, ctypes.byref(params), int(flags), _ptr(energy), _ptr(virial)))
+
+
+def nb_batch_capture(ctx, batch, params, flags, energy=None, virial=None):
+    _check(lib().nb_batch_capture(ctx, batch, ctypes.byref(params), int(flags), _ptr(energy), _ptr(virial)))
+
+
+def nb_batch_replay(ctx, batch):
+    _check(lib().nb_batch_replay(ctx, batch))

@@ -522,6 +522,176 @@ int nb_timing_read(nb_ctx *c, double *ms, long *launches) {
     return NB_OK;
 }
 
+// ----------------------------------------------------------------- batch
+
+// (Re)build the replica table when a replica's storage moved or grew.
+static int batch_refresh(nb_batch *b, const float *const *xyzq_now, float *const *f, bool force) {
+    const size_t ds = rep_desc_size();
+    bool changed = force;
+    std::vector<long> caps(b->n_rep);
+    for (int r = 0; r < b->n_rep; ++r) {
+        const nb_list *l = b->lists[r];
+        caps[r] = l->cap_items + 4;
+        if (l->grid_generation != b->grids[r]->generation)
+            return fail(NB_ERR_STATE, "nb_batch: a replica's list was built before its grid's last sort");
+    }
+    std::vector<char> host(ds * b->n_rep);
+    std::vector<long> so(b->n_rep + 1), ao(b->n_rep + 1);
+    long pb = 0;
+    so[0] = ao[0] = 0;
+    for (int r = 0; r < b->n_rep; ++r) {
+        fill_rep_desc(host.data() + ds * r, b->grids[r], b->lists[r], xyzq_now ? xyzq_now[r] : nullptr,
+                      f ? f[r] : nullptr, pb);
+        pb += caps[r];
+        so[r + 1] = so[r] + b->grids[r]->slots_cap;
+        ao[r + 1] = ao[r] + b->grids[r]->n;
+    }
+    if (!force) {
+        // keep the bound I/O pointers (the first two fields); compare the rest with the table in use
+        const std::vector<char> &old = b->desc_host;
+        for (int r = 0; r < b->n_rep; ++r) std::memcpy(host.data() + ds * r, old.data() + ds * r, 2 * sizeof(void *));
+        changed = std::memcmp(old.data(), host.data(), ds * b->n_rep) != 0 || pb != b->pstride;
+    }
+    if (!changed) return NB_OK;
+    if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch: replica storage changed since capture: capture again");
+    CHECK(ensure(b->desc, ds * b->n_rep));
+    CHECK(ensure(b->slot_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->atom_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->item_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->partials, sizeof(double) * 11 * (size_t)pb));
+    MXN_HIP(hipMemcpy(b->desc.p, host.data(), ds * b->n_rep, hipMemcpyHostToDevice));
+    b->desc_host = host;
+    MXN_HIP(hipMemcpy(b->slot_off.p, so.data(), sizeof(long) * (b->n_rep + 1), hipMemcpyHostToDevice));
+    MXN_HIP(hipMemcpy(b->atom_off.p, ao.data(), sizeof(long) * (b->n_rep + 1), hipMemcpyHostToDevice));
+    b->pstride = pb;
+    b->total_slots = so[b->n_rep];
+    b->total_atoms = ao[b->n_rep];
+    return NB_OK;
+}
+
+int nb_batch_create(nb_ctx *c, int n_rep, nb_grid *const *grids, nb_list *const *lists, const float *const *xyzq_now,
+                    float *const *f, nb_batch **out) {
+    if (!c || n_rep < 1 || !grids || !lists || !xyzq_now || !f || !out)
+        return fail(NB_ERR_ARG, "nb_batch_create: null argument or n_rep < 1");
+    for (int r = 0; r < n_rep; ++r) {
+        if (!grids[r] || !lists[r] || !xyzq_now[r] || !f[r]) return fail(NB_ERR_ARG, "nb_batch_create: null replica");
+        if (grids[r]->ctx != c || lists[r]->ctx != c || lists[r]->grid != grids[r])
+            return fail(NB_ERR_STATE, "nb_batch_create: grid/list/context mismatch");
+        if (grids[r]->m != grids[0]->m || grids[r]->nn != grids[0]->nn)
+            return fail(NB_ERR_ARG, "nb_batch_create: all replicas need the same cluster shape");
+    }
+    MXN_HIP(hipSetDevice(c->device));
+    nb_batch *b = new (std::nothrow) nb_batch();
+    if (!b) return fail(NB_ERR_OOM, "nb_batch_create: host allocation");
+    b->ctx = c;
+    b->n_rep = n_rep;
+    b->m = grids[0]->m;
+    b->nn = grids[0]->nn;
+    b->grids.assign(grids, grids + n_rep);
+    b->lists.assign(lists, lists + n_rep);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 1;
+    b->ncu = ncu;
+    int rc = batch_refresh(b, xyzq_now, f, true);
+    if (rc != NB_OK) {
+        nb_batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return NB_OK;
+}
+
+void nb_batch_free(nb_batch *b) {
+    if (!b) return;
+    hipSetDevice(b->ctx->device);
+    hipStreamSynchronize(b->ctx->stream);
+    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    DevBuf *bufs[] = {&b->desc, &b->slot_off, &b->atom_off, &b->item_off, &b->partials};
+    for (DevBuf *d : bufs) release(*d);
+    delete b;
+}
+
+int nb_batch_set_group(nb_batch *b, int waves) {
+    if (!b || (waves != 1 && waves != 2 && waves != 4 && waves != 8))
+        return fail(NB_ERR_ARG, "nb_batch_set_group: work items per workgroup must be 1, 2, 4 or 8");
+    if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_set_group: batch already captured");
+    b->waves = waves;
+    return NB_OK;
+}
+
+static int batch_check(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial) {
+    if (!c || !b || !p || !p->c6c12) return fail(NB_ERR_ARG, "nb_batch: null argument");
+    if (b->ctx != c) return fail(NB_ERR_STATE, "nb_batch: batch belongs to another context");
+    if (flags & ~(unsigned)(NB_ENERGY | NB_VIRIAL | NB_ACCUMULATE))
+        return fail(NB_ERR_ARG, "nb_batch: supported flags are NB_ENERGY, NB_VIRIAL, NB_ACCUMULATE");
+    if ((flags & NB_ENERGY) && !energy) return fail(NB_ERR_ARG, "nb_batch: energy output is null");
+    if ((flags & NB_VIRIAL) && !virial) return fail(NB_ERR_ARG, "nb_batch: virial output is null");
+    if (p->ntypes < 1 || p->ntypes > kMaxTypes || !(p->rc > 0.0f) || !(p->beta >= 0.0f))
+        return fail(NB_ERR_ARG, "nb_batch: bad interaction parameters");
+    for (int r = 0; r < b->n_rep; ++r)
+        if (!(p->rc <= b->lists[r]->rlist)) return fail(NB_ERR_ARG, "nb_batch: rc exceeds a replica's rlist");
+    if ((double)p->beta * p->rc > 4.0) return fail(NB_ERR_UNSUPPORTED, "nb_batch: beta*rc > 4");
+    return NB_OK;
+}
+
+int nb_batch_forces(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial) {
+    CHECK(batch_check(c, b, p, flags, energy, virial));
+    MXN_HIP(hipSetDevice(c->device));
+    CHECK(batch_refresh(b, nullptr, nullptr, false));
+    return launch_batch(c, b, p, flags, energy, virial);
+}
+
+int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial) {
+    CHECK(batch_check(c, b, p, flags, energy, virial));
+    MXN_HIP(hipSetDevice(c->device));
+    if (b->graph_exec) {
+        hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    CHECK(batch_refresh(b, nullptr, nullptr, false));
+    if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    MXN_HIP(hipStreamSynchronize(c->stream));
+    hipStream_t saved = c->stream;
+    const bool timing = c->timing;
+    c->stream = b->capture_stream;
+    c->timing = false;
+    hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? launch_batch(c, b, p, flags, energy, virial) : NB_ERR_HIP;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+    c->stream = saved;
+    c->timing = timing;
+    if (e != hipSuccess || e2 != hipSuccess || rc != NB_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc != NB_OK ? rc : fail(NB_ERR_HIP, std::string("nb_batch_capture: ") +
+                                                       hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b->graph_exec = nullptr;
+        return fail(NB_ERR_HIP, std::string("nb_batch_capture: instantiate: ") + hipGetErrorString(e));
+    }
+    return NB_OK;
+}
+
+int nb_batch_replay(nb_ctx *c, nb_batch *b) {
+    if (!c || !b) return fail(NB_ERR_ARG, "nb_batch_replay: null argument");
+    if (b->ctx != c) return fail(NB_ERR_STATE, "nb_batch_replay: batch belongs to another context");
+    if (!b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_replay: nothing captured");
+    MXN_HIP(hipSetDevice(c->device));
+    CHECK(batch_refresh(b, nullptr, nullptr, false));
+    ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
+    MXN_HIP(hipGraphLaunch(b->graph_exec, c->stream));
+    return NB_OK;
+}
+
 // ---------------------------------------------------------------- recount
 
 int nb_recount(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_t, const nb_params *p, float c_bb,

@@ -27,6 +27,47 @@ namespace {
 
 constexpr int kNAcc = 11;   // per work item: E_LJ, E_Coulomb, virial[9]
 
+// Per-system arrays a work item touches (one system, or one replica of a batch).
+// Pointers into global memory.  The view's arrays are typed so, because a
+// pointer read from a device table (batched replicas) is otherwise a generic
+// one: loads through it could not be scalar and atomics would go through flat
+// addressing.
+template <class T> using gptr = __attribute__((address_space(1))) T *;
+
+struct SysView {
+    gptr<const float4> xs_now;
+    gptr<const int> type_s;
+    gptr<float> fs;
+    int slots_cap;
+    gptr<const int4> items;
+    gptr<const nb_jentry> entries;
+    gptr<double> partials;
+    long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
+};
+
+// Vector loads through global pointers (component-wise, merged into one
+// 16-byte load by the compiler).
+__device__ inline float4 ld(gptr<const float4> p) {
+    const gptr<const float> q = (gptr<const float>)p;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+__device__ inline int4 ld(gptr<const int4> p) {
+    const gptr<const int> q = (gptr<const int>)p;
+    return make_int4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ inline nb_jentry ld(gptr<const nb_jentry> p) {
+    const int4 t = ld((gptr<const int4>)p);
+    return nb_jentry{t.x, t.y, (uint32_t)t.z, (uint32_t)t.w};
+}
+
+__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fs, int slots_cap,
+                                    const int4 *items, const nb_jentry *entries, double *partials, long pstride,
+                                    long pbase) {
+    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float>)fs, slots_cap,
+                   (gptr<const int4>)items, (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
+}
+
 struct ForceArgs {
     const int *nslots, *perm, *img_s, *slot_of, *type_s;
     const float4 *xyzq_now;
@@ -45,7 +86,6 @@ struct ForceArgs {
     float *f_out;
     int accumulate;
     int *flags;
-    int nblocks_x8;   // launched blocks / 8 (XCD-contiguous remap)
     long pstride;     // partials layout: [kNAcc][pstride]
 };
 
@@ -147,27 +187,34 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
     }
 }
 
-template <int M, int N, bool ENER, bool VIR, bool ACC64>
-__global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
-    extern __shared__ float4 smem[];
-    float4 *svec = smem;        // 27 image shift vectors
-    float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
-    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
-    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
-        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
-        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
-        ljt[t] = make_float4(c6, c12, sh, 0.0f);
-    }
-    __syncthreads();
+// One work item of the direct kernel: up to 32 j-entries of one i-cluster on
+// one wavefront (lane = entry slot x j-particle), i-forces in registers.
+// Work items are split between the eight XCDs by the device-side item count:
+// workgroups go to the XCDs round-robin by index, so XCD x = blockIdx % 8
+// takes the x-th contiguous eighth of the items (neighbouring i-clusters share
+// j-clusters, which then stay in one L2) and every XCD gets an equal share
+// however far the launched grid (sized from the list capacity) exceeds it.
+// Items of this workgroup's wavefronts: first_item() + wave; -1 past the end.
+__device__ inline long xcd_block_first(long total, int waves_per_block) {
+    const long per = (total + 7) / 8;
+    const long k = (long)(blockIdx.x / 8) * waves_per_block;
+    return k < per ? k : -1;
+}
+__device__ inline long xcd_item(long total, int waves_per_block, int wave) {
+    const long per = (total + 7) / 8;
+    const long k = (long)(blockIdx.x / 8) * waves_per_block + wave;
+    if (k >= per) return -1;
+    const long it = (long)(blockIdx.x % 8) * per + k;
+    return it < total ? it : -1;
+}
 
+template <int M, int N, bool ENER, bool VIR, bool ACC64>
+__device__ inline void force_item(const ForceArgs &a, const SysView &v, const float4 *ljt, const float4 *svec,
+                                  int item, int lane) {
     using acc_t = typename std::conditional<ACC64, double, float>::type;
     constexpr int B = 64 / N;                      // entries per pass
     constexpr unsigned FULL = (1u << M) - 1u;
-    const int lane = threadIdx.x & 63;
-    const int logical = (blockIdx.x % 8) * a.nblocks_x8 + blockIdx.x / 8;
-    const int item = logical * 4 + (threadIdx.x >> 6);
-    if (item >= a.totals[2]) return;
-    const int4 it = a.items[item];
+    const int4 it = ld(v.items + item);
     const int ci = __builtin_amdgcn_readfirstlane(it.x);
     const int js = __builtin_amdgcn_readfirstlane(it.y);
     const int je = __builtin_amdgcn_readfirstlane(it.z);
@@ -176,10 +223,10 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     int ti[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        const float4 p = a.xs_now[ci * M + k];
+        const float4 p = ld(v.xs_now + ci * M + k);
         xi[k] = p.x; yi[k] = p.y; zi[k] = p.z;
         qi[k] = p.w * a.coulomb_f;
-        const int t = a.type_s[ci * M + k];
+        const int t = v.type_s[ci * M + k];
         ti[k] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;   // types outside [0, ntypes) are clamped
     }
     float fix[M], fiy[M], fiz[M];
@@ -194,10 +241,10 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     for (int e0 = js; e0 < je; e0 += B) {
         const int e = e0 + eo;
         const bool valid = e < je;
-        const nb_jentry en = a.entries[valid ? e : e0];
+        const nb_jentry en = ld(v.entries + (valid ? e : e0));
         const int jslot = en.cj * N + jb;
-        const float4 pj = a.xs_now[jslot];
-        const int tj = min(max(a.type_s[jslot], 0), a.nt - 1);
+        const float4 pj = ld(v.xs_now + jslot);
+        const int tj = min(max(v.type_s[jslot], 0), a.nt - 1);
         const float4 sv = svec[en.shift];
         const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
         const float qj = pj.w;
@@ -218,9 +265,9 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
             ec += (acc_t)ecl;
         }
         if (valid) {
-            unsafeAtomicAdd(a.fs + jslot, fjx);
-            unsafeAtomicAdd(a.fs + a.slots_cap + jslot, fjy);
-            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + jslot, fjz);
+            unsafeAtomicAdd((float *)(v.fs + jslot), fjx);
+            unsafeAtomicAdd((float *)(v.fs + v.slots_cap + jslot), fjy);
+            unsafeAtomicAdd((float *)(v.fs + 2 * v.slots_cap + jslot), fjz);
         }
         if (VIR) {
             vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
@@ -237,9 +284,9 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
         const float fx = wave_sum_dpp(fix[k]), fy = wave_sum_dpp(fiy[k]), fz = wave_sum_dpp(fiz[k]);
         if (lane == 63) {
             const int s = ci * M + k;
-            unsafeAtomicAdd(a.fs + s, fx);
-            unsafeAtomicAdd(a.fs + a.slots_cap + s, fy);
-            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + s, fz);
+            unsafeAtomicAdd((float *)(v.fs + s), fx);
+            unsafeAtomicAdd((float *)(v.fs + v.slots_cap + s), fy);
+            unsafeAtomicAdd((float *)(v.fs + 2 * v.slots_cap + s), fz);
             if (VIR) {
                 viri[0] += (acc_t)xi[k] * (acc_t)fx; viri[1] += (acc_t)xi[k] * (acc_t)fy; viri[2] += (acc_t)xi[k] * (acc_t)fz;
                 viri[3] += (acc_t)yi[k] * (acc_t)fx; viri[4] += (acc_t)yi[k] * (acc_t)fy; viri[5] += (acc_t)yi[k] * (acc_t)fz;
@@ -254,8 +301,30 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
         if (lane == 63)   // the lane that holds the i-force terms
-            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
+            for (int k = 0; k < kNAcc; ++k) v.partials[(size_t)k * v.pstride + v.pbase + item] = (double)out[k];
     }
+}
+
+template <int M, int N, bool ENER, bool VIR, bool ACC64>
+__global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
+    const long total = a.totals[2];
+    if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
+    extern __shared__ float4 smem[];
+    float4 *svec = smem;        // 27 image shift vectors
+    float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
+    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
+    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
+        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
+        ljt[t] = make_float4(c6, c12, sh, 0.0f);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const long item = xcd_item(total, 4, threadIdx.x >> 6);
+    if (item < 0) return;
+    const SysView v = make_view(a.xs_now, a.type_s, a.fs, a.slots_cap, a.items, a.entries, a.partials, a.pstride, 0);
+    force_item<M, N, ENER, VIR, ACC64>(a, v, ljt, svec, (int)item, lane);
 }
 
 // Deterministic reduction of the per-item partials: one workgroup per value,
@@ -369,6 +438,8 @@ template <int M, int N, bool ENER, bool VIR, bool ACC64>
 __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
     constexpr int JMAX = mxn::kItemEntries * N;
     constexpr unsigned FULL = (1u << M) - 1u;
+    const long total = a.totals[2];
+    if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
     extern __shared__ float4 smem[];
     float4 *svec = smem;
     float4 *ljt = smem + 32;
@@ -389,9 +460,8 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
     float *fjy = fjx + JMAX, *fjz = fjy + JMAX;
     int *pend = reinterpret_cast<int *>(wb + JMAX * 32);
 
-    const int logical = (blockIdx.x % 8) * a.nblocks_x8 + blockIdx.x / 8;
-    const int item = logical * 4 + wave;
-    if (item >= a.totals[2]) return;
+    const long item = xcd_item(total, 4, wave);
+    if (item < 0) return;
     const int4 it = a.items[item];
     const int ci = __builtin_amdgcn_readfirstlane(it.x);
     const int js = __builtin_amdgcn_readfirstlane(it.y);
@@ -572,6 +642,180 @@ void launch_shape(const ForceArgs &a, unsigned flags, int nb, size_t lds, int va
     else launch_k<M, N, false, false, true>(a, nb, lds, var, st);
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched replicas: many independent systems of one cluster shape in one
+// launch per stage.  Work items of all replicas form one index space (a
+// device-side prefix of the replicas' item counts), split between the XCDs
+// like a single system's.  Each replica keeps its own grid and list; the
+// kernels see them through a device table.
+
+struct RepDesc {
+    const float4 *xyzq_now;
+    float *f_out;
+    float4 *xs_now;
+    const int *type_s, *perm, *img_s, *slot_of, *nslots;
+    float *fs;
+    int slots_cap, n;
+    const int4 *items;
+    const nb_jentry *entries;
+    const int *totals;
+    const float4 *shiftvec;
+    float Lx, Ly, Lz;
+    long pbase;   // first partial slot of this replica
+};
+
+struct BatchArgs {
+    const RepDesc *rep;
+    int n_rep;
+    const long *slot_off, *atom_off;   // host-known prefixes (slots_cap, n)
+    long *item_off;                    // device prefix of the replicas' item counts
+    int waves;                         // wavefronts (work items) per workgroup
+    double *partials;
+    long pstride;
+    double *energy, *virial;
+    int accumulate;
+    int *flags;
+};
+
+__device__ inline int find_rep(const long *off, int n, long x) {
+    int lo = 0, hi = n - 1;   // last r with off[r] <= x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Exclusive prefix of the replicas' item counts (one workgroup of 1024
+// threads: contiguous runs per thread, then a scan of the run sums).
+__global__ __launch_bounds__(1024) void k_batch_prefix(BatchArgs b) {
+    __shared__ long run[1024];
+    const int t = threadIdx.x, per = (b.n_rep + 1023) / 1024;
+    const int r0 = t * per, r1 = min(r0 + per, b.n_rep);
+    long s = 0;
+    for (int r = r0; r < r1; ++r) s += b.rep[r].totals[2];
+    run[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan
+        const long v = t >= o ? run[t - o] : 0;
+        __syncthreads();
+        run[t] += v;
+        __syncthreads();
+    }
+    long acc = run[t] - s;
+    for (int r = r0; r < r1; ++r) {
+        b.item_off[r] = acc;
+        acc += b.rep[r].totals[2];
+    }
+    if (t == 1023) b.item_off[b.n_rep] = run[1023];
+}
+
+__global__ void k_batch_gather(BatchArgs b) {
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.slot_off[b.n_rep]) return;
+    const int r = find_rep(b.slot_off, b.n_rep, g);
+    const RepDesc &d = b.rep[r];
+    const int s = (int)(g - b.slot_off[r]);
+    if (s >= *d.nslots) return;
+    const int o = d.perm[s];
+    if (o >= 0) {
+        float4 p = d.xyzq_now[o];
+        const int im = d.img_s[s];
+        if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(b.flags, mxn::FLAG_NONFINITE);
+        p.x -= (float)((im & 1023) - 512) * d.Lx;
+        p.y -= (float)(((im >> 10) & 1023) - 512) * d.Ly;
+        p.z -= (float)(((im >> 20) & 1023) - 512) * d.Lz;
+        d.xs_now[s] = p;
+    }
+    d.fs[s] = 0.0f;
+    d.fs[d.slots_cap + s] = 0.0f;
+    d.fs[2 * d.slots_cap + s] = 0.0f;
+}
+
+// One launch over the concatenated work items of all replicas, one
+// wavefront per item (split between the XCDs like the single-system kernel);
+// the replica of an item is found by binary search in the item prefix.
+template <int M, int N, bool ENER, bool VIR>
+__global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) {
+    const long total = b.item_off[b.n_rep];
+    if (xcd_block_first(total, b.waves) < 0) return;   // whole workgroup past the end
+    extern __shared__ float4 ljt[];
+    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
+        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
+        ljt[t] = make_float4(c6, c12, sh, 0.0f);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long idx = xcd_item(total, b.waves, threadIdx.x >> 6);
+    if (idx < 0) return;
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
+    const RepDesc &d = b.rep[r];
+    const SysView v = make_view(d.xs_now, d.type_s, d.fs, d.slots_cap, d.items, d.entries, b.partials, b.pstride,
+                                d.pbase);
+    force_item<M, N, ENER, VIR, true>(a, v, ljt, d.shiftvec, (int)(idx - b.item_off[r]), lane);
+}
+
+__global__ void k_batch_scatter(BatchArgs b) {
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.atom_off[b.n_rep]) return;
+    const int r = find_rep(b.atom_off, b.n_rep, g);
+    const RepDesc &d = b.rep[r];
+    const int i = (int)(g - b.atom_off[r]);
+    const int s = d.slot_of[i];
+    float fx = d.fs[s], fy = d.fs[d.slots_cap + s], fz = d.fs[2 * d.slots_cap + s];
+    if (b.accumulate) {
+        fx += d.f_out[3 * i]; fy += d.f_out[3 * i + 1]; fz += d.f_out[3 * i + 2];
+    }
+    d.f_out[3 * i] = fx;
+    d.f_out[3 * i + 1] = fy;
+    d.f_out[3 * i + 2] = fz;
+}
+
+// one workgroup per replica: its energies (and virial) from the per-item partials, in a fixed order
+__global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs b, int ener, int vir) {
+    __shared__ double red[256];
+    const int r = blockIdx.x, t = threadIdx.x;
+    const RepDesc &d = b.rep[r];
+    const int n = d.totals[2];
+    for (int k = 0; k < kNAcc; ++k) {
+        if ((k < 2 && !ener) || (k >= 2 && !vir)) continue;
+        double s = 0.0;
+        for (int i = t; i < n; i += 256) s += b.partials[(size_t)k * b.pstride + d.pbase + i];
+        red[t] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            if (k < 2) b.energy[2 * r + k] = red[0];
+            else b.virial[9 * r + k - 2] = red[0];
+        }
+        __syncthreads();
+    }
+}
+
+template <int M, int N, bool E, bool V>
+int launch_batch_forces_k(const ForceArgs &a, const BatchArgs &b, long cap_items, size_t lds, hipStream_t st) {
+    // enough workgroups for every XCD to hold an eighth of the capacity
+    const long per = (cap_items + 7) / 8;
+    const long nb = 8 * std::max(1L, (per + b.waves - 1) / b.waves);
+    k_batch_forces<M, N, E, V><<<(unsigned)nb, 64 * b.waves, lds, st>>>(a, b);
+    return NB_OK;
+}
+
+template <int M, int N>
+int launch_batch_shape(const ForceArgs &a, const BatchArgs &b, unsigned flags, long cap_items, size_t lds,
+                       hipStream_t st) {
+    const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL;
+    if (E && V) return launch_batch_forces_k<M, N, true, true>(a, b, cap_items, lds, st);
+    if (E) return launch_batch_forces_k<M, N, true, false>(a, b, cap_items, lds, st);
+    if (V) return launch_batch_forces_k<M, N, false, true>(a, b, cap_items, lds, st);
+    return launch_batch_forces_k<M, N, false, false>(a, b, cap_items, lds, st);
+}
 }  // namespace
 
 namespace mxn {
@@ -667,7 +911,6 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     int nb = (int)((nwaves + 3) / 4);
     nb = (nb + 7) / 8 * 8;
     if (nb == 0) nb = 8;
-    a.nblocks_x8 = nb / 8;
     const size_t lds = (32 + (size_t)p->ntypes * p->ntypes) * sizeof(float4);
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
@@ -687,6 +930,73 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     }
     MXN_HIP(hipGetLastError());
     return NB_OK;
+}
+
+
+int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, double *energy, double *virial) {
+    hipStream_t st = ctx->stream;
+    ForceArgs a{};
+    a.c6c12 = p->c6c12;
+    a.nt = p->ntypes;
+    a.shift_en = p->shift_energies;
+    a.rc2 = p->rc * p->rc;
+    a.beta = p->beta;
+    a.c_exp = (float)(-(double)p->beta * (double)p->beta * 1.4426950408889634);
+    a.c2bpi = (float)(2.0 * (double)p->beta / 1.7724538509055160);
+    a.coulomb_f = p->coulomb_f;
+    a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
+    a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
+    BatchArgs b{};
+    b.rep = (const RepDesc *)bt->desc.p;
+    b.n_rep = bt->n_rep;
+    b.slot_off = (const long *)bt->slot_off.p;
+    b.atom_off = (const long *)bt->atom_off.p;
+    b.item_off = (long *)bt->item_off.p;
+    b.waves = bt->waves;
+    b.partials = (double *)bt->partials.p;
+    b.pstride = bt->pstride;
+    b.energy = energy;
+    b.virial = virial;
+    b.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
+    b.flags = ctx->d_flags;
+    k_batch_prefix<<<1, 1024, 0, st>>>(b);
+    k_batch_gather<<<(int)((bt->total_slots + 255) / 256), 256, 0, st>>>(b);
+    const size_t lds = (size_t)p->ntypes * p->ntypes * sizeof(float4);
+    {
+        ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
+        if (bt->m == 4 && bt->nn == 4) launch_batch_shape<4, 4>(a, b, flags, bt->pstride, lds, st);
+        else if (bt->m == 4 && bt->nn == 8) launch_batch_shape<4, 8>(a, b, flags, bt->pstride, lds, st);
+        else launch_batch_shape<8, 8>(a, b, flags, bt->pstride, lds, st);
+    }
+    k_batch_scatter<<<(int)((bt->total_atoms + 255) / 256), 256, 0, st>>>(b);
+    if (flags & (NB_ENERGY | NB_VIRIAL))
+        k_batch_reduce<<<bt->n_rep, 256, 0, st>>>(b, (flags & NB_ENERGY) != 0, (flags & NB_VIRIAL) != 0);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+size_t rep_desc_size() { return sizeof(RepDesc); }
+
+void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *xyzq_now, float *f, long pbase) {
+    RepDesc d{};
+    d.xyzq_now = (const float4 *)xyzq_now;
+    d.f_out = f;
+    d.xs_now = (float4 *)g->xs_now.p;
+    d.type_s = (const int *)g->type_s.p;
+    d.perm = (const int *)g->perm.p;
+    d.img_s = (const int *)g->img_s.p;
+    d.slot_of = (const int *)g->slot_of.p;
+    d.nslots = (const int *)g->nslots.p;
+    d.fs = (float *)g->fs.p;
+    d.slots_cap = g->slots_cap;
+    d.n = g->n;
+    d.items = (const int4 *)l->items.p;
+    d.entries = (const nb_jentry *)l->entries.p;
+    d.totals = (const int *)l->totals.p;
+    d.shiftvec = (const float4 *)g->shiftvec.p;
+    d.Lx = g->Lf[0]; d.Ly = g->Lf[1]; d.Lz = g->Lf[2];
+    d.pbase = pbase;
+    *(RepDesc *)out = d;
 }
 
 }  // namespace mxn

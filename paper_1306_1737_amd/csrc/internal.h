@@ -101,6 +101,20 @@ struct nb_list {
     long grid_generation = -1;
 };
 
+struct nb_batch {
+    nb_ctx *ctx = nullptr;
+    int n_rep = 0, m = 0, nn = 0, waves = 4, ncu = 1;
+    long total_slots = 0, total_atoms = 0, pstride = 0;
+    std::vector<const nb_grid *> grids;
+    std::vector<const nb_list *> lists;
+    std::vector<long> generations;
+    mxn::DevBuf desc, slot_off, atom_off, item_off, partials;
+    std::vector<char> desc_host;   // the replica table as last copied to the device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+};
+
 struct nb_mlp {
     nb_ctx *ctx = nullptr;
     mxn::DevBuf params, m, v, step, lo, hi;
@@ -110,6 +124,9 @@ struct nb_mlp {
 namespace mxn {
 
 constexpr int kMlpParams = 4801;
+int launch_batch(nb_ctx *ctx, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial);
+size_t rep_desc_size();
+void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *xyzq_now, float *f, long pbase);
 int launch_mlp_step(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float lr, float *loss,
                     float *grad_out);
 int launch_mlp_infer(nb_ctx *ctx, const nb_mlp *mlp, const float *X, int batch, float *y);

@@ -1,0 +1,110 @@
+"""Batched replicas: one persistent launch over many uneven systems equals per-system evaluation; the
+captured HIP graph replays correctly between eager work; the autotuner returns a valid, cached choice."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._nb import F, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu-case] %s" % request.node.nodeid, file=sys.stderr, flush=True)
+    yield
+
+
+SIZES = [500, 1237, 733, 2100, 560, 1800]   # waters per replica (uneven)
+
+
+def _replicas(torch, mxn, ctx, shape, rlist=1.1):
+    dev = torch.device("cuda:0")
+    reps = []
+    for k, nw in enumerate(SIZES):
+        b = synth.water_box(nw, synth.box_edge_for(nw), seed=300 + k)
+        r = dict(box=b, xyzq=torch.from_numpy(b.xyzq()).to(dev), type=torch.from_numpy(b.type).to(dev),
+                 eo=torch.from_numpy(b.excl_off).to(dev), ei=torch.from_numpy(b.excl_idx).to(dev),
+                 f=torch.zeros((b.n, 3), dtype=torch.float32, device=dev))
+        r["grid"] = mxn.nb_grid_sort(ctx, b.box, r["xyzq"], r["type"], shape)
+        r["lst"] = mxn.nb_pairlist_build(ctx, r["grid"], rlist, -1.0, r["eo"], r["ei"])
+        reps.append(r)
+    return reps
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (8, 8)])
+def test_batch_matches_per_replica_and_graph_replays(shape):
+    import torch
+    import paper_1306_1737_amd as mxn
+    dev = torch.device("cuda:0")
+    ctx = mxn.nb_create(0)
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(1.0, 3.12, F, lj)
+        reps = _replicas(torch, mxn, ctx, shape)
+        n = len(reps)
+        # per-replica reference through nb_forces
+        ref_f, ref_e = [], []
+        for r in reps:
+            f = torch.zeros_like(r["f"]); e = torch.zeros(2, dtype=torch.float64, device=dev)
+            mxn.nb_forces(ctx, r["grid"], r["lst"], r["xyzq"], p, mxn.NB_ENERGY, f, e)
+            mxn.nb_sync(ctx)
+            ref_f.append(f.cpu().numpy().astype(np.float64)); ref_e.append(e.cpu().numpy())
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+
+        def check():
+            e = energy.cpu().numpy().reshape(n, 2)
+            for k, r in enumerate(reps):
+                assert rel_rms(r["f"].cpu().numpy().astype(np.float64), ref_f[k]) <= 1e-6
+                np.testing.assert_allclose(e[k], ref_e[k], rtol=1e-9)
+
+        for g in (1, 2, 4, 8):
+            mxn.nb_batch_set_group(batch, g)
+            mxn.nb_batch_forces(ctx, batch, p, mxn.NB_ENERGY, energy)
+            mxn.nb_sync(ctx)
+            check()
+        mxn.nb_batch_capture(ctx, batch, p, mxn.NB_ENERGY, energy)
+        for rep in range(4):
+            for r in reps:
+                r["f"].fill_(float("nan"))      # eager work between replays
+            energy.zero_()
+            torch.cuda.synchronize()
+            mxn.nb_batch_replay(ctx, batch)
+            mxn.nb_sync(ctx)
+            check()
+        mxn.nb_batch_free(batch)
+        # one replica against the FP64 oracle
+        b = reps[1]["box"]
+        fr, er, _ = oracle.forces(b.xyz, b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(), 1.0, 3.12, F)
+        assert rel_rms(ref_f[1], fr) <= 1e-5
+        np.testing.assert_allclose(ref_e[1], er, rtol=1e-5)
+        for r in reps:
+            mxn.nb_list_free(r["lst"]); mxn.nb_grid_free(r["grid"])
+    finally:
+        mxn.nb_destroy(ctx)
+
+
+def test_autotuner_choice_is_valid_and_cached(tmp_path):
+    import torch
+    import paper_1306_1737_amd as mxn
+    from paper_1306_1737_amd import autotune
+    ctx = mxn.nb_create(0)
+    try:
+        boxes = [synth.water_box(nw, synth.box_edge_for(nw), seed=900 + k) for k, nw in enumerate(SIZES)]
+        cache = tmp_path / "tune.json"
+        res = autotune.tune_batch(ctx, boxes, rc=1.0, rlist=1.1, beta=3.12, reps=3, cache=str(cache))
+        assert tuple(res["shape"]) in autotune.SHAPES and res["group"] in autotune.GROUPS
+        assert len(res["table"]) == len(autotune.SHAPES) * len(autotune.GROUPS)
+        best = min(res["table"], key=lambda row: row["ms"])
+        assert (tuple(best["shape"]), best["group"]) == (tuple(res["shape"]), res["group"])
+        again = autotune.tune_batch(ctx, boxes, rc=1.0, rlist=1.1, beta=3.12, reps=3, cache=str(cache))
+        assert again["cached"] and (tuple(again["shape"]), again["group"]) == (tuple(res["shape"]), res["group"])
+        assert json.loads(cache.read_text())
+    finally:
+        mxn.nb_destroy(ctx)
