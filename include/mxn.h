@@ -212,6 +212,13 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
 enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1 };
 int nb_set_force_variant(nb_ctx *ctx, int variant);
 
+/* Wavefronts that share the pair search of one i-cluster (each takes a
+ * contiguous share of the candidate grid columns of every image shift): 1, 2,
+ * 4 or 8, or 0 (default) to choose from the number of i-clusters so that small
+ * systems still fill the GPU.  The list's content does not depend on it; the
+ * order of entries within an i-cluster does (part by part). */
+int nb_set_search_parts(nb_ctx *ctx, int parts);
+
 /* ------------------------------------------------------- batched replicas */
 
 /*

@@ -30,7 +30,7 @@ EXPORTS = [
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
-    "nb_list_stats", "nb_set_force_variant", "nb_recount",
+    "nb_list_stats", "nb_set_force_variant", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp",
     "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
@@ -104,6 +104,7 @@ def lib():
             "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
             "nb_list_stats": ([vp, vp, vp, vp, f, vp], i),
             "nb_set_force_variant": ([vp, i], i),
+            "nb_set_search_parts": ([vp, i], i),
             "nb_recount": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), f, f, i, vp], i),
             "nb_mlp_create": ([vp, vp, vp, vp, pvp], i), "nb_mlp_free": ([vp], None),
             "nb_mlp_get_params": ([vp, vp], i), "nb_mlp_train_step": ([vp, vp, vp, vp, i, f, vp], i),
@@ -261,6 +262,11 @@ def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True):
 
 def nb_set_force_variant(ctx, variant):
     _check(lib().nb_set_force_variant(ctx, int(variant)))
+
+
+def nb_set_search_parts(ctx, parts):
+    """Wavefronts per i-cluster in the pair search: 1, 2, 4, 8, or 0 for automatic."""
+    _check(lib().nb_set_search_parts(ctx, int(parts)))
 
 
 def nb_forces(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=None):

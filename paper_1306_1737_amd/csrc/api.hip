@@ -308,7 +308,8 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 // ------------------------------------------------------------------- list
 
 static void list_release(nb_list *l) {
-    DevBuf *bufs[] = {&l->entries, &l->entries_canon, &l->keys, &l->items, &l->ci_count, &l->ci_icount, &l->ci_start, &l->ci_istart, &l->totals};
+    DevBuf *bufs[] = {&l->entries, &l->entries_canon, &l->keys,       &l->items,      &l->ci_count,
+                      &l->ci_start, &l->ci_istart,      &l->part_count, &l->part_start, &l->totals};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -340,6 +341,8 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     rc = rc ? rc : ensure(l->ci_count, (size_t)(nci_cap + 1) * 4);
     rc = rc ? rc : ensure(l->ci_start, (size_t)(nci_cap + 1) * 4);
     rc = rc ? rc : ensure(l->ci_istart, (size_t)(nci_cap + 1) * 4);
+    rc = rc ? rc : ensure(l->part_count, ((size_t)nci_cap * kMaxSearchParts + 1) * 4);
+    rc = rc ? rc : ensure(l->part_start, ((size_t)nci_cap * kMaxSearchParts + 1) * 4);
     rc = rc ? rc : ensure(l->totals, 16);
     if (rc == NB_OK && l->cap_entries == 0) {
         // first estimate: 4x the sphere's half pairs over the cluster size, plus slack
@@ -441,6 +444,14 @@ int nb_list_export_canonical(nb_list *l, nb_entry *out, long cap, long *count) {
 }
 
 // ----------------------------------------------------------------- forces
+
+int nb_set_search_parts(nb_ctx *c, int parts) {
+    if (!c) return fail(NB_ERR_ARG, "nb_set_search_parts: ctx is null");
+    if (parts != 0 && parts != 1 && parts != 2 && parts != 4 && parts != 8)
+        return fail(NB_ERR_ARG, "nb_set_search_parts: parts must be 0 (automatic), 1, 2, 4 or 8");
+    c->search_parts = parts;
+    return NB_OK;
+}
 
 int nb_set_force_variant(nb_ctx *c, int variant) {
     if (!c) return fail(NB_ERR_ARG, "nb_set_force_variant: ctx is null");

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -29,6 +30,7 @@ enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2 };
 
 // work items of the force kernel hold at most this many j-entries of one i-cluster
 constexpr int kItemEntries = 32;
+constexpr int kMaxSearchParts = 8;   // wavefronts that may share the pair search of one i-cluster
 constexpr int kMaxTypes = 32;
 
 struct DevBuf {
@@ -58,6 +60,7 @@ struct nb_ctx {
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
+    int search_parts = 0;   // 0: chosen from the number of i-clusters
     const nb_mlp *mlp = nullptr;   // attached buffer predictor (nb_buffer_set_mlp)
     double mlp_margin = 0.0;
     mxn::DevBuf mlp_io;            // one feature row and one output for nb_buffer_estimate
@@ -95,7 +98,7 @@ struct nb_list {
     int ci_cap = 0;
     mxn::DevBuf entries, items;    // entries: per i-cluster, ordered by bounding-box distance
     mxn::DevBuf entries_canon, keys;   // fill-pass output in canonical order, and its sort keys
-    mxn::DevBuf ci_count, ci_icount, ci_start, ci_istart;
+    mxn::DevBuf ci_count, ci_start, ci_istart, part_count, part_start;
     mxn::DevBuf totals;        // int[4]: entries, items, overflow, pad
     long last_entries = 0;     // host copy after a synchronous build
     long grid_generation = -1;

@@ -3,9 +3,10 @@
 // GPU as the paper planned.  One wavefront per i-cluster: for each kept image
 // shift it walks the candidate grid columns in increasing column order and
 // tests that column's j-clusters 64 at a time (one per lane) against the
-// bounding-box criterion, falling back to the particle-pair check outside the
-// rBB shortcut.  A count pass, a deterministic scan and a fill pass give a
-// list whose order depends only on the input.
+// bounding-box criterion; a lane whose candidate lies outside the rBB
+// shortcut checks the candidate's particle pairs itself.  A count pass, a
+// deterministic scan and a fill pass give a list whose order depends only on
+// the input.
 //
 // Compiled with -ffp-contract=off: the inclusion predicate and the
 // exclusion-in-image test are defined by separately rounded FP32 operations.
@@ -27,13 +28,13 @@ struct SearchArgs {
     float Lx, Ly, Lz, inv_x, inv_y;
     int nx, ny;
     float rlist, rl2, rb2;
-    int *ci_count;
-    const int *ci_start, *ci_istart, *totals;
-    nb_jentry *entries;   // canonical order (by shift, then j-cluster) within each i-cluster
+    int *part_count;                     // entries found by each (i-cluster, part)
+    const int *part_start, *ci_start, *ci_istart, *totals;
+    nb_jentry *entries;   // per i-cluster: part by part, each part in (shift, j-cluster) order
     float *keys;          // bounding-box distance^2 of each entry
     int4 *items;
     long cap_entries, cap_items;
-    int nci_cap;
+    int nci_cap, parts;
 };
 
 __device__ inline float sq3(float x, float y, float z) { return (x * x + y * y) + z * z; }
@@ -55,33 +56,78 @@ __device__ inline int lower_bound(int lo, int hi, F key, float v) {
     return lo;
 }
 
-// Lane layout of the particle-pair checks: lane = g*M*N + b*M + a handles the
-// pair (i-slot a, j-slot b) of candidate group g, so P = 64/(M*N) candidates
-// are checked per pass and one ballot yields their masks in j-major order.
+// Candidates are handled one per lane: a lane owning a candidate j-cluster
+// outside the rBB shortcut checks its M x N particle pairs itself (all loads
+// independent, early exit on the first pair within rlist), and in the fill
+// pass builds the interaction mask of an accepted candidate from the
+// particles' realness, the self-pair triangle and the i-cluster's exclusions
+// (their partners' slots and positions staged in LDS once per wavefront).
+// a.parts wavefronts share an i-cluster: part p takes the p-th contiguous
+// share of every image shift's candidate columns.
+constexpr int kExclStage = 64;   // staged exclusion partners per wavefront
+
 template <int M, int N, bool FILL>
 __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
-    constexpr int PAIRS = M * N;
-    constexpr int P = 64 / PAIRS;
-    constexpr unsigned long long GMASK = PAIRS == 64 ? ~0ull : ((1ull << PAIRS) - 1ull);
-    const int lane = threadIdx.x & 63;
-    const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr unsigned FULL = (1u << M) - 1u;
+    __shared__ float4 xpos[4][kExclStage];
+    __shared__ int xinfo[4][kExclStage];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gw = blockIdx.x * 4 + w;
+    const int P = a.parts, ci = gw / P, part = gw % P;
     if (ci >= a.nci_cap) return;
     const int nci = *a.nslots / M;
     if (ci >= nci) {   // beyond the padded slot count of this sort: contributes nothing to the scans
-        if (!FILL && lane == 0) a.ci_count[ci] = 0;
+        if (!FILL && lane == 0) a.part_count[gw] = 0;
         return;
     }
-    int wpos = 0, ipos = 0;
+    int wpos = 0;
     if (FILL) {
         if ((long)a.totals[0] > a.cap_entries || (long)a.totals[1] > a.cap_items) return;   // overflow: latched later
-        wpos = a.ci_start[ci];
-        ipos = a.ci_istart[ci];
+        wpos = a.part_start[gw];
     }
     const float4 lo = a.bbi_lo[ci], hi = a.bbi_hi[ci];
-    const int pa = lane % M, pb = (lane / M) % N, grp = lane / PAIRS;
-    const float4 pi = a.xs[ci * M + pa];
-    const int iorig = a.perm[ci * M + pa];
+    // the i-cluster (uniform across the wavefront)
+    float ix[M], iy[M], iz[M];
+    unsigned ireal = 0;
+#pragma unroll
+    for (int ia = 0; ia < M; ++ia) {
+        const float4 p = a.xs[ci * M + ia];
+        ix[ia] = p.x; iy[ia] = p.y; iz[ia] = p.z;
+        ireal |= (a.perm[ci * M + ia] >= 0 ? 1u : 0u) << ia;
+    }
     const float zmargin = 1e-3f;   // keeps the z window conservative against rounding
+    const float pmargin = 1e-3f;   // keeps the particle-to-box prefilter conservative
+    const float rp2 = (a.rlist + pmargin) * (a.rlist + pmargin);
+    // exclusion partners of the i-particles: (slot * 8 + i-index, position), staged in LDS
+    int nexcl = 0;
+    bool staged = true;
+    if (FILL) {
+        int e0 = 0, e1 = 0;
+        if (lane < M && ((ireal >> lane) & 1u)) {
+            const int io = a.perm[ci * M + lane];
+            e0 = a.excl_off[io];
+            e1 = a.excl_off[io + 1];
+        }
+        int incl = e1 - e0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        nexcl = __shfl(incl, 63, 64);
+        staged = nexcl <= kExclStage && (long)a.nci_cap * M < (1L << 28);   // slot * 8 + i-index fits an int
+        if (staged && lane < M) {
+            int q = incl - (e1 - e0);
+            for (int e = e0; e < e1; ++e, ++q) {
+                const int ps = a.slot_of[a.excl_idx[e]];
+                xinfo[w][q] = ps * 8 + lane;
+                xpos[w][q] = a.xs[ps];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     int cnt = 0;
     if (lo.x <= hi.x) {   // the cluster holds real particles
         for (int s = 13; s < 27; ++s) {
@@ -89,19 +135,26 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                         sz = (float)(s % 3 - 1) * a.Lz;
             const float slx = lo.x + sx, shx = hi.x + sx, sly = lo.y + sy, shy = hi.y + sy, slz = lo.z + sz,
                         shz = hi.z + sz;
-            const float pix = pi.x + sx, piy = pi.y + sy, piz = pi.z + sz;   // this lane's shifted i-particle
             // candidate columns: a superset, one column of margin against rounding
             int cx0 = (int)floorf((slx - a.rlist) * a.inv_x) - 1, cx1 = (int)floorf((shx + a.rlist) * a.inv_x) + 1;
             int cy0 = (int)floorf((sly - a.rlist) * a.inv_y) - 1, cy1 = (int)floorf((shy + a.rlist) * a.inv_y) + 1;
             cx0 = cx0 < 0 ? 0 : cx0; cy0 = cy0 < 0 ? 0 : cy0;
             cx1 = cx1 > a.nx - 1 ? a.nx - 1 : cx1; cy1 = cy1 > a.ny - 1 ? a.ny - 1 : cy1;
             if (cx0 > cx1 || cy0 > cy1) continue;
+            // wrapped particles lie in [0, L): no z window can be hit from beyond that range
+            if (slz - a.rlist - zmargin > a.Lz + zmargin || shz + a.rlist + zmargin < -zmargin) continue;
+            float px[M], py[M], pz[M];   // shifted i-particles
+#pragma unroll
+            for (int ia = 0; ia < M; ++ia) {
+                px[ia] = ix[ia] + sx; py[ia] = iy[ia] + sy; pz[ia] = iz[ia] + sz;
+            }
             const int ncy = cy1 - cy0 + 1, ncols = (cx1 - cx0 + 1) * ncy;
-            for (int cb = 0; cb < ncols; cb += 64) {
+            const int c_lo = ncols * part / P, c_hi = ncols * (part + 1) / P;   // this part's columns
+            for (int cb = c_lo; cb < c_hi; cb += 64) {
                 // one column per lane (ascending column id): its z window of j-clusters
                 int k0 = 0, kc = 0;
                 const int cidx = cb + lane;
-                if (cidx < ncols) {
+                if (cidx < c_hi) {
                     const int c = (cx0 + cidx / ncy) * a.ny + cy0 + cidx % ncy;
                     const float4 cbb = a.colbb[c];
                     const float gx = axis_gap(cbb.x, cbb.z, slx, shx), gy = axis_gap(cbb.y, cbb.w, sly, shy);
@@ -144,75 +197,69 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                                  axis_gap(jl.z, jh.z, slz, shz));
                         ok = d2 < a.rl2;
                     }
-                    const bool chk = ok && !(d2 < a.rb2);
-                    unsigned long long accepted = __ballot(ok && !chk);
-                    unsigned long long need = __ballot(chk);
-                    // particle-pair checks, P candidates per pass
-                    while (need) {
-                        int src = -1;
-#pragma unroll
-                        for (int g = 0; g < P; ++g) {
-                            const int f = need ? __ffsll((long long)need) - 1 : -1;
-                            if (f >= 0) need &= need - 1;
-                            if (g == grp) src = f;
-                        }
+                    bool acc = ok;
+                    if (ok && !(d2 < a.rb2)) {
+                        // particle-pair check of this lane's candidate
                         bool hit = false;
-                        const int cjc = __shfl(cj, src < 0 ? 0 : src, 64);
-                        if (src >= 0 && iorig >= 0) {
-                            const int sb = cjc * N + pb;
-                            if (a.perm[sb] >= 0) {
-                                const float4 pbv = a.xs[sb];
-                                hit = sq3(pix - pbv.x, piy - pbv.y, piz - pbv.z) < a.rl2;
-                            }
-                        }
-                        const unsigned long long hb = __ballot(hit);
+                        for (int b = 0; b < N && !hit; ++b) {
+                            const int sb = cj * N + b;
+                            const float4 pj = a.xs[sb];
+                            if (a.perm[sb] < 0) continue;
+                            const float g = sq3(axis_gap(pj.x, pj.x, slx, shx), axis_gap(pj.y, pj.y, sly, shy),
+                                                axis_gap(pj.z, pj.z, slz, shz));
+                            if (!(g < rp2)) continue;   // too far from the whole i-cluster
 #pragma unroll
-                        for (int g = 0; g < P; ++g) {
-                            const int sg = __shfl(src, g * PAIRS, 64);
-                            if (sg >= 0 && ((hb >> (g * PAIRS)) & GMASK)) accepted |= 1ull << sg;
+                            for (int ia = 0; ia < M; ++ia)
+                                hit |= ((ireal >> ia) & 1u) && sq3(px[ia] - pj.x, py[ia] - pj.y, pz[ia] - pj.z) < a.rl2;
                         }
+                        acc = hit;
                     }
+                    const unsigned long long accepted = __ballot(acc);
                     if (FILL) {
-                        // masks of the accepted candidates, in lane (= candidate) order
-                        unsigned long long todo = accepted;
-                        int base = wpos;
-                        while (todo) {
-                            int src = -1, rank = 0;
+                        if (acc) {
+                            // mask bit b*M + a: both particles real, slot(i) < slot(j) for the unshifted
+                            // self/overlapping pair, not an exclusion in this image
+                            unsigned long long mask = 0;
 #pragma unroll
-                            for (int g = 0; g < P; ++g) {
-                                const int f = todo ? __ffsll((long long)todo) - 1 : -1;
-                                if (f >= 0) todo &= todo - 1;
-                                if (g == grp) src = f;
+                            for (int b = 0; b < N; ++b) {
+                                const int sb = cj * N + b;
+                                unsigned keep = a.perm[sb] >= 0 ? ireal : 0u;
+                                if (s == 13) {
+                                    const int tr = sb - ci * M;
+                                    keep &= tr >= M ? FULL : (tr <= 0 ? 0u : (1u << tr) - 1u);
+                                }
+                                mask |= (unsigned long long)keep << (b * M);
                             }
-                            if (src >= 0) rank = __popcll(accepted & ((1ull << src) - 1ull));
-                            const int cjc = __shfl(cj, src < 0 ? 0 : src, 64);
-                            const float d2c = __shfl(d2, src < 0 ? 0 : src, 64);
-                            bool bit = false;
-                            if (src >= 0 && iorig >= 0) {
-                                const int sb = cjc * N + pb;
-                                const int jorig = a.perm[sb];
-                                if (jorig >= 0 && !(s == 13 && ci * M + pa >= sb)) {
-                                    bit = true;
-                                    bool excluded = false;
-                                    for (int e = a.excl_off[iorig]; e < a.excl_off[iorig + 1]; ++e)
-                                        excluded |= a.excl_idx[e] == jorig;
-                                    if (excluded) {
-                                        const float4 pbv = a.xs[sb];
-                                        if (sq3(pix - pbv.x, piy - pbv.y, piz - pbv.z) < a.rl2) bit = false;
+                            if (staged) {
+                                for (int q = 0; q < nexcl; ++q) {
+                                    const int v = xinfo[w][q], ia = v & 7, b = (v >> 3) - cj * N;
+                                    if (b < 0 || b >= N) continue;
+                                    const float4 pj = xpos[w][q];
+                                    if (sq3(px[ia] - pj.x, py[ia] - pj.y, pz[ia] - pj.z) < a.rl2)
+                                        mask &= ~(1ull << (b * M + ia));
+                                }
+                            } else {   // more partners than staged: read them from the CSR arrays
+                                for (int ia = 0; ia < M; ++ia) {
+                                    if (!((ireal >> ia) & 1u)) continue;
+                                    const int io = a.perm[ci * M + ia];
+                                    for (int e = a.excl_off[io]; e < a.excl_off[io + 1]; ++e) {
+                                        const int ps = a.slot_of[a.excl_idx[e]];
+                                        const int b = ps - cj * N;
+                                        if (b < 0 || b >= N) continue;
+                                        const float4 pj = a.xs[ps];
+                                        if (sq3(px[ia] - pj.x, py[ia] - pj.y, pz[ia] - pj.z) < a.rl2)
+                                            mask &= ~(1ull << (b * M + ia));
                                     }
                                 }
                             }
-                            const unsigned long long mb = __ballot(bit);
-                            if (src >= 0 && lane % PAIRS == 0) {
-                                const unsigned long long mask = PAIRS == 64 ? mb : ((mb >> (grp * PAIRS)) & GMASK);
-                                nb_jentry en;
-                                en.cj = cjc;
-                                en.shift = s;
-                                en.mlo = (uint32_t)mask;
-                                en.mhi = (uint32_t)(mask >> 32);
-                                a.entries[base + rank] = en;
-                                a.keys[base + rank] = d2c;
-                            }
+                            const int rank = __popcll(accepted & ((1ull << lane) - 1ull));
+                            nb_jentry en;
+                            en.cj = cj;
+                            en.shift = s;
+                            en.mlo = (uint32_t)mask;
+                            en.mhi = (uint32_t)(mask >> 32);
+                            a.entries[wpos + rank] = en;
+                            a.keys[wpos + rank] = d2;
                         }
                         wpos += __popcll(accepted);
                     } else {
@@ -223,9 +270,9 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         }
     }
     if (!FILL) {
-        if (lane == 0) a.ci_count[ci] = cnt;
-    } else {
-        const int start = a.ci_start[ci], end = a.ci_start[ci + 1];
+        if (lane == 0) a.part_count[gw] = cnt;
+    } else if (part == 0) {
+        const int start = a.ci_start[ci], end = a.ci_start[ci + 1], ipos = a.ci_istart[ci];
         const int nit = (end - start + mxn::kItemEntries - 1) / mxn::kItemEntries;
         for (int k = lane; k < nit; k += 64) {
             const int js = start + k * mxn::kItemEntries;
@@ -259,6 +306,15 @@ __global__ __launch_bounds__(64) void k_sort_entries(const int *ci_start, const 
         }
         out[b + r] = in[b + i];
     }
+}
+
+// Per i-cluster entry counts and offsets from the per-part offsets.
+__global__ void k_ci_offsets(const int *part_start, int nci_cap, int parts, int *ci_count, int *ci_start) {
+    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci > nci_cap) return;
+    const int s = part_start[(long)ci * parts];
+    ci_start[ci] = s;
+    if (ci < nci_cap) ci_count[ci] = part_start[(long)(ci + 1) * parts] - s;
 }
 
 // totals: [0] entries, [1] items (from the scans); writes [2] = usable item
@@ -306,17 +362,31 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     a.rlist = l->rlist;
     volatile float rl2 = l->rlist * l->rlist, rb2 = l->rbb * l->rbb;
     a.rl2 = rl2; a.rb2 = rb2;
-    a.ci_count = (int *)l->ci_count.p;
+    a.part_count = (int *)l->part_count.p;
+    a.part_start = (const int *)l->part_start.p;
     a.ci_start = (const int *)l->ci_start.p;
     a.ci_istart = (const int *)l->ci_istart.p;
     a.totals = (const int *)l->totals.p;
     a.nci_cap = nci_cap;
-    const int nblocks = (nci_cap + 3) / 4;
+    // parts per i-cluster: the largest power of two up to 8 that keeps about 6000
+    // wavefronts or fewer (measured on MI355X: more parts only add per-part overhead
+    // once the GPU holds that many latency-bound wavefronts)
+    int parts = ctx->search_parts;
+    if (parts == 0) {
+        const long nci = std::max(1, g->n / g->m);
+        parts = 1;
+        while (parts < kMaxSearchParts && nci * parts * 2 <= 6000) parts *= 2;
+    }
+    a.parts = parts;
+    const int nblocks = (int)(((long)nci_cap * parts + 3) / 4);
     // count pass
     if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, false, nblocks, st);
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, false, nblocks, st);
     else run<8, 8>(l, a, false, nblocks, st);
-    launch_scan_mode((const int *)l->ci_count.p, (int *)l->ci_start.p, nci_cap, 0, 1, (int *)l->totals.p, st);
+    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_start.p, nci_cap * parts, 0, 1,
+                     (int *)l->totals.p, st);
+    k_ci_offsets<<<(nci_cap + 256) / 256, 256, 0, st>>>((const int *)l->part_start.p, nci_cap, parts,
+                                                      (int *)l->ci_count.p, (int *)l->ci_start.p);
     launch_scan_mode((const int *)l->ci_count.p, (int *)l->ci_istart.p, nci_cap, 2, kItemEntries,
                      (int *)l->totals.p + 1, st);
     if (sync) {

@@ -19,6 +19,7 @@
  * is redrawn; such fallbacks are counted and returned.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -168,6 +169,10 @@ int synth_water_rsa(int n_mol, const double L[3], uint64_t seed, double d_oo, do
         int c = cell_of(&g, m);
         g.next[i] = g.head[c];
         g.head[c] = i;
+        if (n_mol >= 200000 && (i + 1) % 100000 == 0) {   /* large boxes take minutes: report progress */
+            fprintf(stderr, "[synth] %d of %d molecules placed\n", i + 1, n_mol);
+            fflush(stderr);
+        }
     }
     free(g.head);
     free(g.next);

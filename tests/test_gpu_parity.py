@@ -93,6 +93,27 @@ def test_pairlist_bitexact(c1, shape, rlist):
         s.close()
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+def test_pairlist_same_for_every_search_split(c1, shape):
+    """Wavefronts sharing one i-cluster's search (1, 2, 4, 8) change only the order of its entries."""
+    rbb = np.float32(default_rbb(c1, shape, 1.0))
+    g = oracle.grid_sort(c1.xyz, c1.box, *shape)
+    ref = oracle.pairlist(g, c1.box, np.float32(1.0), rbb, c1.excl_off, c1.excl_idx)
+    s = GpuSystem(c1, shape, 1.0, rbb=float(rbb))
+    try:
+        for parts in (1, 2, 4, 8, 0):
+            s.mxn.nb_set_search_parts(s.ctx, parts)
+            lst = s.mxn.nb_pairlist_build(s.ctx, s.grid, 1.0, float(rbb), s.eo, s.ei)
+            try:
+                _cmp_lists(s.mxn.nb_list_export_canonical(lst), ref)
+            finally:
+                s.mxn.nb_list_free(lst)
+        with pytest.raises(s.mxn.NbError):
+            s.mxn.nb_set_search_parts(s.ctx, 3)
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("rbb", [0.0, 1.0])
 def test_pairlist_rbb_extremes(ragged, rbb):
     """rbb = 0: every pair checked at particle level; rbb = rlist: bounding boxes alone decide."""
