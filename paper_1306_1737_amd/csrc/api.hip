@@ -146,7 +146,7 @@ int nb_sync(nb_ctx *c) {
 // ------------------------------------------------------------------- grid
 
 static void grid_release(nb_grid *g) {
-    DevBuf *bufs[] = {&g->col_count, &g->col_start, &g->col_fill, &g->colbb, &g->atom_col, &g->atom_xw,
+    DevBuf *bufs[] = {&g->col_count, &g->col_start, &g->col_fill, &g->colbb, &g->col_hist, &g->atom_col, &g->atom_xw,
                       &g->atom_img, &g->bucket, &g->xs, &g->xs_now, &g->type_s, &g->perm, &g->img_s,
                       &g->slot_of, &g->bbi_lo, &g->bbi_hi, &g->bbj_lo, &g->bbj_hi, &g->nslots, &g->fs,
                       &g->shiftvec};
@@ -202,6 +202,7 @@ int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const
     rc = rc ? rc : ensure(g->col_count, nc * 4);
     rc = rc ? rc : ensure(g->col_start, (nc + 1) * 4);
     rc = rc ? rc : ensure(g->col_fill, nc * 4);
+    rc = rc ? rc : ensure(g->col_hist, nc * (size_t)hist_blocks(n) * 4);
     rc = rc ? rc : ensure(g->colbb, nc * 16);
     rc = rc ? rc : ensure(g->atom_col, na * 4);
     rc = rc ? rc : ensure(g->atom_xw, na * 16);

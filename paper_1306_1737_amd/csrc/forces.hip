@@ -187,8 +187,6 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
     }
 }
 
-// One work item of the direct kernel: up to 32 j-entries of one i-cluster on
-// one wavefront (lane = entry slot x j-particle), i-forces in registers.
 // Work items are split between the eight XCDs by the device-side item count:
 // workgroups go to the XCDs round-robin by index, so XCD x = blockIdx % 8
 // takes the x-th contiguous eighth of the items (neighbouring i-clusters share
@@ -208,6 +206,11 @@ __device__ inline long xcd_item(long total, int waves_per_block, int wave) {
     return it < total ? it : -1;
 }
 
+// One work item of the direct kernel: up to 32 j-entries of one i-cluster on
+// one wavefront (lane = entry slot x j-particle), i-forces in registers.
+// (Issuing a pass's j-force atomics after the next pass's loads, so that the
+// in-order wait for those loads does not include them, measured slower on
+// gfx950: it costs registers and occupancy for no gain.)
 template <int M, int N, bool ENER, bool VIR, bool ACC64>
 __device__ inline void force_item(const ForceArgs &a, const SysView &v, const float4 *ljt, const float4 *svec,
                                   int item, int lane) {

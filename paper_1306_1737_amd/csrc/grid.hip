@@ -42,10 +42,16 @@ __device__ inline float wrap1(float x, float L, double il, int &k, bool &bad) {
     return w + 0.0f;   // -0 -> +0
 }
 
-// per particle: periodic wrap, image count, column, column histogram
-__global__ void k_wrap_count(WrapArgs a) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+// Column counting without global atomics (many particles share few columns,
+// and same-address atomics serialise): each workgroup histograms its block of
+// kHistAtoms particles in LDS and writes the histogram as one column of the
+// matrix hist[column][block]; a per-column prefix over blocks then gives every
+// block its offset inside each column, and the block places its particles
+// with LDS atomics.  The placement order inside a column is arbitrary (the
+// column sort ranks by z and index).
+constexpr int kHistThreads = 1024;
+
+__device__ inline int wrap_column(const WrapArgs &a, int i) {
     float4 p = a.xyzq[i];
     bool bad = !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w));
     int kx, ky, kz;
@@ -61,7 +67,48 @@ __global__ void k_wrap_count(WrapArgs a) {
     a.atom_col[i] = col;
     a.atom_img[i] = (kx + kImgBias) | ((ky + kImgBias) << 10) | ((kz + kImgBias) << 20);
     a.atom_xw[i] = make_float4(wx, wy, wz, p.w);
-    atomicAdd(&a.col_count[col], 1);
+    return col;
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_wrap_hist(WrapArgs a, int ncol, int nhb, int *hist) {
+    extern __shared__ int h[];
+    for (int c = threadIdx.x; c < ncol; c += kHistThreads) h[c] = 0;
+    __syncthreads();
+    const int b0 = blockIdx.x * mxn::kHistAtoms, b1 = min(a.n, b0 + mxn::kHistAtoms);
+    for (int i = b0 + threadIdx.x; i < b1; i += kHistThreads) atomicAdd(&h[wrap_column(a, i)], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncol; c += kHistThreads) hist[(long)c * nhb + blockIdx.x] = h[c];
+}
+
+// per column: counts over blocks -> exclusive offsets per block, total count
+__global__ void k_col_prefix(int ncol, int nhb, int *hist, int *col_count) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    int *row = hist + (long)c * nhb;
+    int s = 0;
+    for (int b = 0; b < nhb; ++b) {
+        const int v = row[b];
+        row[b] = s;
+        s += v;
+    }
+    col_count[c] = s;
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_bucket_hist(int n, int ncol, int nhb, const int *atom_col,
+                                                             const int *col_start, const int *hist, int *bucket) {
+    extern __shared__ int off[];
+    for (int c = threadIdx.x; c < ncol; c += kHistThreads) off[c] = col_start[c] + hist[(long)c * nhb + blockIdx.x];
+    __syncthreads();
+    const int b0 = blockIdx.x * mxn::kHistAtoms, b1 = min(n, b0 + mxn::kHistAtoms);
+    for (int i = b0 + threadIdx.x; i < b1; i += kHistThreads) bucket[atomicAdd(&off[atom_col[i]], 1)] = i;
+}
+
+// per particle: periodic wrap, image count, column, column histogram by
+// global atomics (the path for grids with more columns than fit in LDS)
+__global__ void k_wrap_count(WrapArgs a) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    atomicAdd(&a.col_count[wrap_column(a, i)], 1);
 }
 
 // scatter particle indices into their column's slot range (arbitrary order within a column)
@@ -221,16 +268,30 @@ void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *tota
 int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
     hipStream_t st = g->ctx->stream;
     const int n = g->n, ncol = g->ncol;
-    k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_count.p, ncol, 0);
-    k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_fill.p, ncol, 0);
     WrapArgs w{(const float4 *)xyzq, n, g->Lf[0], g->Lf[1], g->Lf[2], g->invL[0], g->invL[1], g->invL[2],
                g->inv_x, g->inv_y, g->nx, g->ny, (int *)g->col_count.p, (int *)g->atom_col.p,
                (int *)g->atom_img.p, (float4 *)g->atom_xw.p, g->ctx->d_flags};
-    k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
+    const bool lds_hist = ncol <= kMaxHistColumns;
+    const int nhb = hist_blocks(n);
+    const size_t hb = (size_t)ncol * sizeof(int);
+    if (lds_hist) {
+        k_wrap_hist<<<nhb, kHistThreads, hb, st>>>(w, ncol, nhb, (int *)g->col_hist.p);
+        k_col_prefix<<<blocks(ncol, 256), 256, 0, st>>>(ncol, nhb, (int *)g->col_hist.p, (int *)g->col_count.p);
+    } else {
+        k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_count.p, ncol, 0);
+        k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
+    }
     k_scan<<<1, 1024, 0, st>>>((const int *)g->col_count.p, (int *)g->col_start.p, ncol, 1, g->cmax,
                                (int *)g->nslots.p);
-    k_bucket<<<blocks(n, 256), 256, 0, st>>>(n, (const int *)g->atom_col.p, (const int *)g->col_start.p,
-                                             (int *)g->col_fill.p, (int *)g->bucket.p);
+    if (lds_hist) {
+        k_bucket_hist<<<nhb, kHistThreads, hb, st>>>(n, ncol, nhb, (const int *)g->atom_col.p,
+                                                     (const int *)g->col_start.p, (const int *)g->col_hist.p,
+                                                     (int *)g->bucket.p);
+    } else {
+        k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_fill.p, ncol, 0);
+        k_bucket<<<blocks(n, 256), 256, 0, st>>>(n, (const int *)g->atom_col.p, (const int *)g->col_start.p,
+                                                 (int *)g->col_fill.p, (int *)g->bucket.p);
+    }
     SortArgs s{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
                (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
                (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p, (int *)g->slot_of.p};

@@ -30,6 +30,9 @@ enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2 };
 
 // work items of the force kernel hold at most this many j-entries of one i-cluster
 constexpr int kItemEntries = 32;
+constexpr int kHistAtoms = 4096;         // particles per workgroup in the column histogram
+constexpr int kMaxHistColumns = 16384;   // larger grids count columns with global atomics
+inline int hist_blocks(int n) { return n < 1 ? 1 : (n + kHistAtoms - 1) / kHistAtoms; }
 constexpr int kMaxSearchParts = 8;   // wavefronts that may share the pair search of one i-cluster
 constexpr int kMaxTypes = 32;
 
@@ -79,7 +82,7 @@ struct nb_grid {
     float inv_x = 0, inv_y = 0;
     double spacing = 0;
     // device storage
-    mxn::DevBuf col_count, col_start, col_fill, colbb;
+    mxn::DevBuf col_count, col_start, col_fill, colbb, col_hist;
     mxn::DevBuf atom_col, atom_xw, atom_img, bucket;
     mxn::DevBuf xs, xs_now, type_s, perm, img_s, slot_of;
     mxn::DevBuf bbi_lo, bbi_hi, bbj_lo, bbj_hi;
