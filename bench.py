@@ -74,8 +74,9 @@ def _gen_box(args):
 
 def bench_batched(args):
     """256 uneven water boxes (1 500-24 000 atoms, log-uniform, seeded), rc 1.0 / rlist 1.1 nm: one step =
-    list rebuild of every replica + 10 force steps; the 10 force steps run either as one captured graph
-    of the batched launch (replayed), or as per-replica nb_forces launches."""
+    grid sort + list rebuild of every replica + 10 force steps, either as one replayed graph of the batched
+    launches (one launch per stage for all replicas), or as per-replica nb_grid_sort / nb_pairlist_build /
+    nb_forces calls."""
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import torch
@@ -103,21 +104,17 @@ def bench_batched(args):
     batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps], [r["xyzq"] for r in reps],
                                 [r["f"] for r in reps])
     mxn.nb_batch_set_group(batch, group)
-    mxn.nb_batch_capture(ctx, batch, params, mxn.NB_ENERGY, energy)
+    mxn.nb_batch_bind_topology(batch, [r["type"] for r in reps], [r["eo"] for r in reps], [r["ei"] for r in reps])
+    mxn.nb_batch_capture_cycle(ctx, batch, 10, params, mxn.NB_ENERGY, energy)
     e1 = [torch.zeros(2, dtype=torch.float64, device=dev) for _ in reps]
 
-    def rebuild():
+    def step_graph():
+        mxn.nb_batch_replay(ctx, batch)
+
+    def step_loop():
         for r in reps:
             r["grid"] = mxn.nb_grid_sort(ctx, r["box"].box, r["xyzq"], r["type"], shape, r["grid"])
             r["lst"] = mxn.nb_pairlist_build(ctx, r["grid"], rlist, -1.0, r["eo"], r["ei"], mxn.NB_LIST_ASYNC, r["lst"])
-
-    def step_graph():
-        rebuild()
-        for _ in range(10):
-            mxn.nb_batch_replay(ctx, batch)
-
-    def step_loop():
-        rebuild()
         for _ in range(10):
             for k, r in enumerate(reps):
                 mxn.nb_forces(ctx, r["grid"], r["lst"], r["xyzq"], params, mxn.NB_ENERGY, r["f"], e1[k])

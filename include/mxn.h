@@ -130,8 +130,9 @@ int nb_grid_export(nb_grid *grid, int *perm, float *xyzq, int *img, int *col_sta
 /* ------------------------------------------------------------- pair list */
 
 enum {
-    NB_LIST_ASYNC = 1,          /* do not synchronise to size the list: reuse the handle's capacity,
-                                   latch NB_ERR_OVERFLOW (reported by nb_sync) if it is too small */
+    NB_LIST_ASYNC = 1,          /* do not synchronise: search once into the regions reserved by the
+                                   handle's last synchronous build; latch NB_ERR_OVERFLOW (reported
+                                   by nb_sync) if an i-cluster outgrows its region */
     NB_LIST_BY_DISTANCE = 2     /* store each i-cluster's entries by bounding-box distance instead of
                                    in canonical order (groups the entries beyond the cut-off) */
 };
@@ -152,11 +153,18 @@ enum {
  *             max(0, rlist - s/2) with s the column spacing
  *   excl_off  DEVICE int[n+1], excl_idx DEVICE int[excl_off[n]]: force-field
  *             exclusions as CSR in original indices; must be symmetric
- *   flags     0 or NB_LIST_ASYNC
+ *   flags     0, NB_LIST_ASYNC, NB_LIST_BY_DISTANCE
  *   list      in/out: NULL creates, otherwise reused
- * Without NB_LIST_ASYNC the call synchronises once to size its storage.
- * Storage order is deterministic: by i-cluster, image shift, j-cluster
- * (canonical), or with NB_LIST_BY_DISTANCE by i-cluster and bounding-box
+ * Storage: each (i-cluster, search part) owns an equal region of the entry
+ * array.  A synchronous build (no NB_LIST_ASYNC; also the first build of a
+ * handle and any build after the grid's capacity changed) counts the
+ * entries, sizes every region to the largest count plus a quarter plus 8
+ * (synchronising once), then fills the regions.  An asynchronous build
+ * searches once and fills the regions, with no host synchronisation (it can
+ * be captured in a graph); a region that would overflow latches
+ * NB_ERR_OVERFLOW, and the next synchronous build re-sizes.
+ * Order is deterministic: regions by i-cluster, each region by image shift
+ * and j-cluster (canonical), or with NB_LIST_BY_DISTANCE by bounding-box
  * distance (ties in canonical order).
  */
 int nb_pairlist_build(nb_ctx *ctx, const nb_grid *grid, float rlist, float rbb, const int *excl_off,
@@ -215,8 +223,9 @@ int nb_set_force_variant(nb_ctx *ctx, int variant);
 /* Wavefronts that share the pair search of one i-cluster (each takes a
  * contiguous share of the candidate grid columns of every image shift): 1, 2,
  * 4 or 8, or 0 (default) to choose from the number of i-clusters so that small
- * systems still fill the GPU.  The list's content does not depend on it; the
- * order of entries within an i-cluster does (part by part). */
+ * systems still fill the GPU.  Takes effect at a list's next synchronous
+ * build.  The list's content does not depend on it; the order of entries
+ * within an i-cluster does (part by part). */
 int nb_set_search_parts(nb_ctx *ctx, int parts);
 
 /* ------------------------------------------------------- batched replicas */
@@ -253,6 +262,24 @@ int nb_batch_forces(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned f
 int nb_batch_capture(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy,
                      double *virial);
 int nb_batch_replay(nb_ctx *ctx, nb_batch *batch);
+
+/*
+ * Batched list rebuild: the grid sort (Sec. 2.3) and the pair search of
+ * every replica, each stage one launch over all replicas, from the bound
+ * positions.  Every replica's list must have had a synchronous build on its
+ * grid (which sizes its regions); the rebuild then fills those regions like
+ * an NB_LIST_ASYNC build, at the list's own rlist and rbb, latching
+ * NB_ERR_OVERFLOW if a region overflows.  No host synchronisation.
+ *   type, excl_off, excl_idx   HOST arrays of n_rep DEVICE pointers (each as
+ *                              for nb_grid_sort / nb_pairlist_build)
+ * nb_batch_capture_cycle captures one rebuild followed by nsteps batched force
+ * evaluations as a single graph, replayed with nb_batch_replay.
+ */
+int nb_batch_bind_topology(nb_batch *batch, const int *const *type, const int *const *excl_off,
+                           const int *const *excl_idx);
+int nb_batch_rebuild(nb_ctx *ctx, nb_batch *batch);
+int nb_batch_capture_cycle(nb_ctx *ctx, nb_batch *batch, int nsteps, const nb_params *p, unsigned flags,
+                           double *energy, double *virial);
 
 /* ---------------------------------------------------------- exact recount */
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp",
     "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
-    "nb_batch_replay",
+    "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
@@ -114,6 +114,8 @@ def lib():
             "nb_batch_set_group": ([vp, i], i), "nb_batch_forces": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
             "nb_batch_capture": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
             "nb_batch_replay": ([vp, vp], i),
+            "nb_batch_bind_topology": ([vp, vp, vp, vp], i), "nb_batch_rebuild": ([vp, vp], i),
+            "nb_batch_capture_cycle": ([vp, vp, i, ctypes.POINTER(nb_params), u, vp, vp], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -394,3 +396,22 @@ def nb_batch_capture(ctx, batch, params, flags, energy=None, virial=None):
 
 def nb_batch_replay(ctx, batch):
     _check(lib().nb_batch_replay(ctx, batch))
+
+
+def nb_batch_bind_topology(batch, types, excl_offs, excl_idxs):
+    """types, excl_offs, excl_idxs: int32 CUDA tensors per replica (kept alive by the batch handle)."""
+    n = len(types)
+    ta = (ctypes.c_void_p * n)(*[t.data_ptr() for t in types])
+    oa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in excl_offs])
+    ia = (ctypes.c_void_p * n)(*[t.data_ptr() for t in excl_idxs])
+    _check(lib().nb_batch_bind_topology(batch, ta, oa, ia))
+    batch._keep_topology = (list(types), list(excl_offs), list(excl_idxs))
+
+
+def nb_batch_rebuild(ctx, batch):
+    _check(lib().nb_batch_rebuild(ctx, batch))
+
+
+def nb_batch_capture_cycle(ctx, batch, nsteps, params, flags, energy=None, virial=None):
+    _check(lib().nb_batch_capture_cycle(ctx, batch, int(nsteps), ctypes.byref(params), int(flags), _ptr(energy),
+                                        _ptr(virial)))

@@ -309,8 +309,8 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 // ------------------------------------------------------------------- list
 
 static void list_release(nb_list *l) {
-    DevBuf *bufs[] = {&l->entries, &l->entries_canon, &l->keys,       &l->items,      &l->ci_count,
-                      &l->ci_start, &l->ci_istart,      &l->part_count, &l->part_start, &l->totals};
+    DevBuf *bufs[] = {&l->entries,    &l->entries_canon, &l->keys,        &l->items,
+                      &l->part_count, &l->part_start,    &l->part_istart, &l->totals};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -339,27 +339,12 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     l->rbb = rbb >= 0.0f ? rbb : (float)std::fmax(0.0, (double)rlist - 0.5 * g->spacing);
     const int nci_cap = g->slots_cap / g->m;
     int rc = NB_OK;
-    rc = rc ? rc : ensure(l->ci_count, (size_t)(nci_cap + 1) * 4);
-    rc = rc ? rc : ensure(l->ci_start, (size_t)(nci_cap + 1) * 4);
-    rc = rc ? rc : ensure(l->ci_istart, (size_t)(nci_cap + 1) * 4);
-    rc = rc ? rc : ensure(l->part_count, ((size_t)nci_cap * kMaxSearchParts + 1) * 4);
-    rc = rc ? rc : ensure(l->part_start, ((size_t)nci_cap * kMaxSearchParts + 1) * 4);
+    const size_t nreg = (size_t)nci_cap * kMaxSearchParts + 1;
+    rc = rc ? rc : ensure(l->part_count, nreg * 4);
+    rc = rc ? rc : ensure(l->part_start, nreg * 4);
+    rc = rc ? rc : ensure(l->part_istart, nreg * 4);
     rc = rc ? rc : ensure(l->totals, 16);
-    if (rc == NB_OK && l->cap_entries == 0) {
-        // first estimate: 4x the sphere's half pairs over the cluster size, plus slack
-        const double rho = (double)g->n / (g->box[0] * g->box[1] * g->box[2]);
-        const double half = 2.0 / 3.0 * M_PI * (double)rlist * rlist * rlist * rho * g->n;
-        const long ce = (long)(4.0 * half / (g->m * g->nn)) + 16L * nci_cap + 1024;
-        const long cit = ce / kItemEntries + nci_cap + 256;
-        rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
-        rc = rc ? rc : ensure(l->entries_canon, (size_t)ce * sizeof(nb_jentry));
-        rc = rc ? rc : ensure(l->keys, (size_t)ce * sizeof(float));
-        rc = rc ? rc : ensure(l->items, (size_t)cit * 16);
-        if (rc == NB_OK) {
-            l->cap_entries = ce;
-            l->cap_items = cit;
-        }
-    }
+    // entry and item capacities are set by the reserving (synchronous) build
     if (rc == NB_OK) {
         ScopedTimer tm(c, NB_TIMER_PAIRLIST);
         rc = launch_pairlist(l, excl_off, excl_idx, !(flags & NB_LIST_ASYNC), (flags & NB_LIST_BY_DISTANCE) != 0);
@@ -401,46 +386,55 @@ int nb_list_export_canonical(nb_list *l, nb_entry *out, long cap, long *count) {
     CHECK(nb_list_info(l, &ne, nullptr));
     if (count) *count = ne;
     const nb_grid *g = l->grid;
-    const int M = g->m, N = g->nn;
+    const int M = g->m, N = g->nn, P = l->resv_parts;
     int ns = 0;
     MXN_HIP(hipMemcpy(&ns, g->nslots.p, sizeof(int), hipMemcpyDeviceToHost));
     const int nci = ns / M;
-    int *starts = new (std::nothrow) int[nci + 1];
-    nb_jentry *ent = new (std::nothrow) nb_jentry[ne > 0 ? ne : 1];
-    if (!starts || !ent) {
-        delete[] starts;
-        delete[] ent;
+    const long nreg = (long)nci * P;
+    std::vector<int> start, cnt;
+    std::vector<nb_jentry> ent;
+    try {
+        start.resize(nreg + 1);
+        cnt.resize(nreg > 0 ? nreg : 1);
+        ent.resize(l->cap_entries > 0 ? l->cap_entries : 1);
+    } catch (...) {
         return fail(NB_ERR_OOM, "nb_list_export_canonical: host allocation");
     }
-    hipError_t e = hipMemcpy(starts, l->ci_start.p, (size_t)(nci + 1) * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && ne > 0) e = hipMemcpy(ent, l->entries.p, (size_t)ne * sizeof(nb_jentry), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-        delete[] starts;
-        delete[] ent;
-        return fail(NB_ERR_HIP, hipGetErrorString(e));
-    }
-    // entries may be stored by bounding-box distance: restore canonical order (shift, then j-cluster)
-    for (int ci = 0; ci < nci; ++ci)
-        std::sort(ent + starts[ci], ent + starts[ci + 1], [](const nb_jentry &x, const nb_jentry &y) {
+    hipError_t e = hipSuccess;
+    if (nreg > 0) e = hipMemcpy(start.data(), l->part_start.p, (size_t)(nreg + 1) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && nreg > 0) e = hipMemcpy(cnt.data(), l->part_count.p, (size_t)nreg * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && l->cap_entries > 0)
+        e = hipMemcpy(ent.data(), l->entries.p, (size_t)l->cap_entries * sizeof(nb_jentry), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(NB_ERR_HIP, hipGetErrorString(e));
+    long k = 0;
+    std::vector<nb_jentry> mine;
+    for (int ci = 0; ci < nci; ++ci) {
+        // the i-cluster's entries from all its regions, in canonical order (shift, then j-cluster)
+        mine.clear();
+        for (int p = 0; p < P; ++p) {
+            const long r = (long)ci * P + p;
+            const int n = std::min(cnt[r], start[r + 1] - start[r]);
+            mine.insert(mine.end(), ent.begin() + start[r], ent.begin() + start[r] + n);
+        }
+        std::sort(mine.begin(), mine.end(), [](const nb_jentry &x, const nb_jentry &y) {
             return x.shift != y.shift ? x.shift < y.shift : x.cj < y.cj;
         });
-    long k = 0;
-    for (int ci = 0; ci < nci; ++ci)
-        for (int j = starts[ci]; j < starts[ci + 1]; ++j, ++k) {
-            if (k >= cap) continue;
-            const uint64_t m = ((uint64_t)ent[j].mhi << 32) | ent[j].mlo;
-            uint64_t canon = 0;   // kernel order bit b*M + a -> canonical bit a*N + b
-            for (int b = 0; b < N; ++b)
-                for (int a = 0; a < M; ++a)
-                    if ((m >> (b * M + a)) & 1ull) canon |= 1ull << (a * N + b);
-            out[k].ci = ci;
-            out[k].shift = ent[j].shift;
-            out[k].cj = ent[j].cj;
-            out[k].pad = 0;
-            out[k].mask = canon;
+        for (const nb_jentry &en : mine) {
+            if (k < cap) {
+                const uint64_t m = ((uint64_t)en.mhi << 32) | en.mlo;
+                uint64_t canon = 0;   // kernel order bit b*M + a -> canonical bit a*N + b
+                for (int b = 0; b < N; ++b)
+                    for (int a = 0; a < M; ++a)
+                        if ((m >> (b * M + a)) & 1ull) canon |= 1ull << (a * N + b);
+                out[k].ci = ci;
+                out[k].shift = en.shift;
+                out[k].cj = en.cj;
+                out[k].pad = 0;
+                out[k].mask = canon;
+            }
+            ++k;
         }
-    delete[] starts;
-    delete[] ent;
+    }
     return NB_OK;
 }
 
@@ -601,6 +595,7 @@ int nb_batch_create(nb_ctx *c, int n_rep, nb_grid *const *grids, nb_list *const 
     b->nn = grids[0]->nn;
     b->grids.assign(grids, grids + n_rep);
     b->lists.assign(lists, lists + n_rep);
+    b->xyzq.assign(xyzq_now, xyzq_now + n_rep);
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 1;
     b->ncu = ncu;
@@ -620,7 +615,8 @@ void nb_batch_free(nb_batch *b) {
     if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
     if (b->graph) hipGraphDestroy(b->graph);
     if (b->capture_stream) hipStreamDestroy(b->capture_stream);
-    DevBuf *bufs[] = {&b->desc, &b->slot_off, &b->atom_off, &b->item_off, &b->partials};
+    DevBuf *bufs[] = {&b->desc, &b->slot_off, &b->atom_off, &b->item_off, &b->partials,
+                      &b->gjobs, &b->ljobs, &b->goff,     &b->loff,     &b->scans};
     for (DevBuf *d : bufs) release(*d);
     delete b;
 }
@@ -675,6 +671,7 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
     c->timing = false;
     hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? launch_batch(c, b, p, flags, energy, virial) : NB_ERR_HIP;
+    b->cycle = false;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
     c->stream = saved;
@@ -693,14 +690,152 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
     return NB_OK;
 }
 
+static int rebuild_refresh(nb_batch *b);
+
 int nb_batch_replay(nb_ctx *c, nb_batch *b) {
     if (!c || !b) return fail(NB_ERR_ARG, "nb_batch_replay: null argument");
     if (b->ctx != c) return fail(NB_ERR_STATE, "nb_batch_replay: batch belongs to another context");
     if (!b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_replay: nothing captured");
     MXN_HIP(hipSetDevice(c->device));
     CHECK(batch_refresh(b, nullptr, nullptr, false));
+    if (b->cycle) CHECK(rebuild_refresh(b));
     ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
     MXN_HIP(hipGraphLaunch(b->graph_exec, c->stream));
+    return NB_OK;
+}
+
+int nb_batch_bind_topology(nb_batch *b, const int *const *type, const int *const *excl_off,
+                           const int *const *excl_idx) {
+    if (!b || !type || !excl_off || !excl_idx) return fail(NB_ERR_ARG, "nb_batch_bind_topology: null argument");
+    for (int r = 0; r < b->n_rep; ++r)
+        if (!type[r] || !excl_off[r] || !excl_idx[r]) return fail(NB_ERR_ARG, "nb_batch_bind_topology: null replica");
+    if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_bind_topology: batch already captured");
+    b->type.assign(type, type + b->n_rep);
+    b->excl_off.assign(excl_off, excl_off + b->n_rep);
+    b->excl_idx.assign(excl_idx, excl_idx + b->n_rep);
+    b->topology = true;
+    return NB_OK;
+}
+
+// Job tables and per-stage workgroup offsets of the batched rebuild; uploaded
+// (synchronously) only when a replica's storage changed.
+static int rebuild_refresh(nb_batch *b) {
+    if (!b->topology) return fail(NB_ERR_STATE, "nb_batch_rebuild: bind the replicas' topology first");
+    const int n = b->n_rep;
+    const size_t gs = grid_job_size(), ls = list_job_size();
+    const int GS = grid_job_stages(), LS = list_job_stages();
+    std::vector<char> gj(gs * n), lj(ls * n);
+    std::vector<ScanJob> sj(n);
+    std::vector<int> goff(GS * (n + 1)), loff(LS * (n + 1)), gtot(GS, 0), ltot(LS, 0), gb(GS), lb(LS);
+    int max_ncol = 1;
+    for (int r = 0; r < n; ++r) {
+        nb_grid *g = b->grids[r];
+        nb_list *l = b->lists[r];
+        if (!grid_batchable(g)) return fail(NB_ERR_UNSUPPORTED, "nb_batch_rebuild: a replica's grid has too many columns");
+        if (l->resv_parts == 0 || l->resv_nci != g->slots_cap / g->m || l->grid != g)
+            return fail(NB_ERR_STATE, "nb_batch_rebuild: every replica's list needs a synchronous build on its grid");
+        fill_grid_job(gj.data() + gs * r, g, b->xyzq[r], b->type[r]);
+        fill_list_job(lj.data() + ls * r, l, b->excl_off[r], b->excl_idx[r], &sj[r]);
+        grid_job_blocks(g, gb.data());
+        list_job_blocks(l, lb.data());
+        for (int k = 0; k < GS; ++k) {
+            goff[k * (n + 1) + r] = gtot[k];
+            gtot[k] += gb[k];
+        }
+        for (int k = 0; k < LS; ++k) {
+            loff[k * (n + 1) + r] = ltot[k];
+            ltot[k] += lb[k];
+        }
+        max_ncol = std::max(max_ncol, g->ncol);
+    }
+    for (int k = 0; k < GS; ++k) goff[k * (n + 1) + n] = gtot[k];
+    for (int k = 0; k < LS; ++k) loff[k * (n + 1) + n] = ltot[k];
+    if (gj == b->gjobs_host && lj == b->ljobs_host && gtot == b->gtotal && ltot == b->ltotal) return NB_OK;
+    if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch: replica storage changed since capture: capture again");
+    CHECK(ensure(b->gjobs, gj.size()));
+    CHECK(ensure(b->ljobs, lj.size()));
+    CHECK(ensure(b->goff, goff.size() * sizeof(int)));
+    CHECK(ensure(b->loff, loff.size() * sizeof(int)));
+    CHECK(ensure(b->scans, sj.size() * sizeof(ScanJob)));
+    MXN_HIP(hipMemcpy(b->gjobs.p, gj.data(), gj.size(), hipMemcpyHostToDevice));
+    MXN_HIP(hipMemcpy(b->ljobs.p, lj.data(), lj.size(), hipMemcpyHostToDevice));
+    MXN_HIP(hipMemcpy(b->goff.p, goff.data(), goff.size() * sizeof(int), hipMemcpyHostToDevice));
+    MXN_HIP(hipMemcpy(b->loff.p, loff.data(), loff.size() * sizeof(int), hipMemcpyHostToDevice));
+    MXN_HIP(hipMemcpy(b->scans.p, sj.data(), sj.size() * sizeof(ScanJob), hipMemcpyHostToDevice));
+    b->gjobs_host = gj;
+    b->ljobs_host = lj;
+    b->gtotal = gtot;
+    b->ltotal = ltot;
+    b->max_ncol = max_ncol;
+    return NB_OK;
+}
+
+static int launch_rebuild(nb_ctx *c, nb_batch *b) {
+    {
+        ScopedTimer tm(c, NB_TIMER_GRID_SORT);
+        CHECK(launch_grid_sort_batch(c->stream, b->gjobs.p, (const int *)b->goff.p, b->n_rep, b->gtotal.data(),
+                                     b->max_ncol));
+    }
+    {
+        ScopedTimer tm(c, NB_TIMER_PAIRLIST);
+        CHECK(launch_pairlist_batch(c->stream, b->m, b->nn, b->ljobs.p, (const int *)b->loff.p, b->n_rep,
+                                    b->ltotal.data(), (const ScanJob *)b->scans.p));
+    }
+    for (int r = 0; r < b->n_rep; ++r) {   // every replica's grid and list are now one generation newer
+        ++b->grids[r]->generation;
+        b->lists[r]->grid_generation = b->grids[r]->generation;
+    }
+    return NB_OK;
+}
+
+int nb_batch_rebuild(nb_ctx *c, nb_batch *b) {
+    if (!c || !b) return fail(NB_ERR_ARG, "nb_batch_rebuild: null argument");
+    if (b->ctx != c) return fail(NB_ERR_STATE, "nb_batch_rebuild: batch belongs to another context");
+    MXN_HIP(hipSetDevice(c->device));
+    CHECK(rebuild_refresh(b));
+    return launch_rebuild(c, b);
+}
+
+int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *p, unsigned flags, double *energy,
+                           double *virial) {
+    if (nsteps < 0) return fail(NB_ERR_ARG, "nb_batch_capture_cycle: nsteps must be >= 0");
+    CHECK(batch_check(c, b, p, flags, energy, virial));
+    MXN_HIP(hipSetDevice(c->device));
+    if (b->graph_exec) {
+        hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    CHECK(rebuild_refresh(b));
+    CHECK(batch_refresh(b, nullptr, nullptr, false));
+    if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    MXN_HIP(hipStreamSynchronize(c->stream));
+    hipStream_t saved = c->stream;
+    const bool timing = c->timing;
+    c->stream = b->capture_stream;
+    c->timing = false;
+    hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? launch_rebuild(c, b) : NB_ERR_HIP;
+    b->cycle = true;
+    for (int k = 0; k < nsteps && rc == NB_OK; ++k) rc = launch_batch(c, b, p, flags, energy, virial);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+    c->stream = saved;
+    c->timing = timing;
+    if (e != hipSuccess || e2 != hipSuccess || rc != NB_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc != NB_OK ? rc : fail(NB_ERR_HIP, std::string("nb_batch_capture_cycle: ") +
+                                                       hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b->graph_exec = nullptr;
+        return fail(NB_ERR_HIP, std::string("nb_batch_capture_cycle: instantiate: ") + hipGetErrorString(e));
+    }
     return NB_OK;
 }
 

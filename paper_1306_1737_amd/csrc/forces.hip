@@ -20,6 +20,7 @@
 // FP64 (or FP32 for the precision study) and reduced deterministically.
 #include <type_traits>
 
+#include "devptr.h"
 #include "ewald_fit.h"
 #include "internal.h"
 
@@ -27,12 +28,10 @@ namespace {
 
 constexpr int kNAcc = 11;   // per work item: E_LJ, E_Coulomb, virial[9]
 
-// Per-system arrays a work item touches (one system, or one replica of a batch).
-// Pointers into global memory.  The view's arrays are typed so, because a
-// pointer read from a device table (batched replicas) is otherwise a generic
-// one: loads through it could not be scalar and atomics would go through flat
-// addressing.
-template <class T> using gptr = __attribute__((address_space(1))) T *;
+// Per-system arrays a work item touches (one system, or one replica of a batch),
+// as global pointers (see devptr.h).
+using mxn::gptr;
+using mxn::ld;
 
 struct SysView {
     gptr<const float4> xs_now;
@@ -44,22 +43,6 @@ struct SysView {
     gptr<double> partials;
     long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
 };
-
-// Vector loads through global pointers (component-wise, merged into one
-// 16-byte load by the compiler).
-__device__ inline float4 ld(gptr<const float4> p) {
-    const gptr<const float> q = (gptr<const float>)p;
-    return make_float4(q[0], q[1], q[2], q[3]);
-}
-__device__ inline int4 ld(gptr<const int4> p) {
-    const gptr<const int> q = (gptr<const int>)p;
-    return make_int4(q[0], q[1], q[2], q[3]);
-}
-
-__device__ inline nb_jentry ld(gptr<const nb_jentry> p) {
-    const int4 t = ld((gptr<const int4>)p);
-    return nb_jentry{t.x, t.y, (uint32_t)t.z, (uint32_t)t.w};
-}
 
 __device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fs, int slots_cap,
                                     const int4 *items, const nb_jentry *entries, double *partials, long pstride,

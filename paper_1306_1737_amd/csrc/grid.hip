@@ -6,6 +6,7 @@
 // column index and the bounding boxes are defined by separately rounded FP32
 // operations and must be bit-reproducible.
 #include <cmath>
+#include <cstring>
 
 #include "internal.h"
 
@@ -70,19 +71,26 @@ __device__ inline int wrap_column(const WrapArgs &a, int i) {
     return col;
 }
 
-__global__ __launch_bounds__(kHistThreads) void k_wrap_hist(WrapArgs a, int ncol, int nhb, int *hist) {
+// Kernel bodies take their workgroup index `blk` explicitly: the
+// single-system kernels pass blockIdx.x, the batched ones the index within
+// their replica's share of the grid.
+__device__ inline void wrap_hist_body(const WrapArgs &a, int ncol, int nhb, int *hist, int blk) {
     extern __shared__ int h[];
     for (int c = threadIdx.x; c < ncol; c += kHistThreads) h[c] = 0;
     __syncthreads();
-    const int b0 = blockIdx.x * mxn::kHistAtoms, b1 = min(a.n, b0 + mxn::kHistAtoms);
+    const int b0 = blk * mxn::kHistAtoms, b1 = min(a.n, b0 + mxn::kHistAtoms);
     for (int i = b0 + threadIdx.x; i < b1; i += kHistThreads) atomicAdd(&h[wrap_column(a, i)], 1);
     __syncthreads();
-    for (int c = threadIdx.x; c < ncol; c += kHistThreads) hist[(long)c * nhb + blockIdx.x] = h[c];
+    for (int c = threadIdx.x; c < ncol; c += kHistThreads) hist[(long)c * nhb + blk] = h[c];
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_wrap_hist(WrapArgs a, int ncol, int nhb, int *hist) {
+    wrap_hist_body(a, ncol, nhb, hist, blockIdx.x);
 }
 
 // per column: counts over blocks -> exclusive offsets per block, total count
-__global__ void k_col_prefix(int ncol, int nhb, int *hist, int *col_count) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void col_prefix_body(int ncol, int nhb, int *hist, int *col_count, int blk) {
+    const int c = blk * blockDim.x + threadIdx.x;
     if (c >= ncol) return;
     int *row = hist + (long)c * nhb;
     int s = 0;
@@ -94,13 +102,22 @@ __global__ void k_col_prefix(int ncol, int nhb, int *hist, int *col_count) {
     col_count[c] = s;
 }
 
+__global__ void k_col_prefix(int ncol, int nhb, int *hist, int *col_count) {
+    col_prefix_body(ncol, nhb, hist, col_count, blockIdx.x);
+}
+
+__device__ inline void bucket_hist_body(int n, int ncol, int nhb, const int *atom_col, const int *col_start,
+                                        const int *hist, int *bucket, int blk) {
+    extern __shared__ int off[];
+    for (int c = threadIdx.x; c < ncol; c += kHistThreads) off[c] = col_start[c] + hist[(long)c * nhb + blk];
+    __syncthreads();
+    const int b0 = blk * mxn::kHistAtoms, b1 = min(n, b0 + mxn::kHistAtoms);
+    for (int i = b0 + threadIdx.x; i < b1; i += kHistThreads) bucket[atomicAdd(&off[atom_col[i]], 1)] = i;
+}
+
 __global__ __launch_bounds__(kHistThreads) void k_bucket_hist(int n, int ncol, int nhb, const int *atom_col,
                                                              const int *col_start, const int *hist, int *bucket) {
-    extern __shared__ int off[];
-    for (int c = threadIdx.x; c < ncol; c += kHistThreads) off[c] = col_start[c] + hist[(long)c * nhb + blockIdx.x];
-    __syncthreads();
-    const int b0 = blockIdx.x * mxn::kHistAtoms, b1 = min(n, b0 + mxn::kHistAtoms);
-    for (int i = b0 + threadIdx.x; i < b1; i += kHistThreads) bucket[atomicAdd(&off[atom_col[i]], 1)] = i;
+    bucket_hist_body(n, ncol, nhb, atom_col, col_start, hist, bucket, blockIdx.x);
 }
 
 // per particle: periodic wrap, image count, column, column histogram by
@@ -133,10 +150,10 @@ struct SortArgs {
 constexpr int kSortThreads = 256;
 constexpr int kSortTile = 1024;
 
-__global__ __launch_bounds__(kSortThreads) void k_col_sort(SortArgs a) {
+__device__ inline void col_sort_body(const SortArgs &a, int c) {
     __shared__ unsigned long long tile[kSortTile];
     __shared__ float red[4][kSortThreads];
-    const int c = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int start = a.col_start[c], nc = a.col_count[c], end = a.col_start[c + 1];
     float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
     for (int mine = 0; mine < nc; mine += kSortThreads) {
@@ -196,9 +213,12 @@ __global__ __launch_bounds__(kSortThreads) void k_col_sort(SortArgs a) {
     if (tid == 0) a.colbb[c] = make_float4(red[0][0], red[1][0], red[2][0], red[3][0]);
 }
 
+__global__ __launch_bounds__(kSortThreads) void k_col_sort(SortArgs a) { col_sort_body(a, blockIdx.x); }
+
 // per cluster of `size` slots: min/max over real particles (inf/-inf if none)
-__global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi) {
-    int cl = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void bb_body(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi,
+                               int blk) {
+    int cl = blk * blockDim.x + threadIdx.x;
     if (cl >= *nslots / size) return;
     float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -212,22 +232,35 @@ __global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *p
     hi[cl] = h;
 }
 
+__global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi) {
+    bb_body(nslots, size, xs, perm, lo, hi, blockIdx.x);
+}
+
 // Exclusive scan on one workgroup of 1024 threads, each owning a contiguous
 // chunk; mode 0: values as is, 1: rounded up to a multiple of p, 2: ceil(v/p).
-__global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, int mode, int p, int *total) {
+// raw_total (optional) receives the sum of the untransformed values.
+__device__ inline void scan_body(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total) {
+    __shared__ int raws[1024];
     __shared__ int sums[1024];
     const int t = threadIdx.x;
     const int chunk = (n + 1023) / 1024;
     const int b = t * chunk, e = min(n, b + chunk);
     auto tr = [&](int v) { return mode == 0 ? v : (mode == 1 ? (v + p - 1) / p * p : (v + p - 1) / p); };
-    int s = 0;
-    for (int i = b; i < e; ++i) s += tr(in[i]);
+    int s = 0, r = 0;
+    for (int i = b; i < e; ++i) {
+        const int v = in[i];
+        s += tr(v);
+        r += v;
+    }
     sums[t] = s;
+    raws[t] = r;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         int v = t >= off ? sums[t - off] : 0;
+        int w = t >= off ? raws[t - off] : 0;
         __syncthreads();
         sums[t] += v;
+        raws[t] += w;
         __syncthreads();
     }
     int run = sums[t] - s;
@@ -238,7 +271,13 @@ __global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, i
     if (t == 1023) {
         out[n] = sums[1023];
         if (total) *total = sums[1023];
+        if (raw_total) *raw_total = raws[1023];
     }
+}
+
+__global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, int mode, int p, int *total,
+                                               int *raw_total) {
+    scan_body(in, out, n, mode, p, total, raw_total);
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -246,9 +285,83 @@ __global__ void k_fill_int(int *p, int n, int v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_shiftvec(float4 *sv, float Lx, float Ly, float Lz) {
+__device__ inline void shiftvec_body(float4 *sv, float Lx, float Ly, float Lz) {
     int s = threadIdx.x;
     if (s < 27) sv[s] = make_float4((float)(s / 9 - 1) * Lx, (float)((s / 3) % 3 - 1) * Ly, (float)(s % 3 - 1) * Lz, 0.0f);
+}
+
+__global__ void k_shiftvec(float4 *sv, float Lx, float Ly, float Lz) { shiftvec_body(sv, Lx, Ly, Lz); }
+
+// --------------------------------------------------------------------------
+// Batched grid sort: every stage is one launch over all replicas.  A stage's
+// workgroups are the concatenation of the replicas' shares; a workgroup finds
+// its replica by binary search in the stage's prefix of share sizes.
+
+struct GridJob {
+    WrapArgs w;
+    SortArgs s;
+    int ncol, nhb, cmax, m, nn, slots_cap;
+    int *col_hist, *col_start, *nslots;
+    float4 *bbi_lo, *bbi_hi, *bbj_lo, *bbj_hi, *shiftvec;
+};
+
+__device__ inline int job_of(const int *off, int n, int b) {
+    int lo = 0, hi = n - 1;   // last r with off[r] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// stage offsets: off + stage * (n + 1)
+enum { GS_HIST, GS_PREFIX, GS_SCAN, GS_COLSORT, GS_BBI, GS_BBJ, GS_NSTAGES };
+
+__global__ __launch_bounds__(kHistThreads) void kb_wrap_hist(const GridJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    const GridJob &j = J[r];
+    wrap_hist_body(j.w, j.ncol, j.nhb, j.col_hist, blockIdx.x - off[r]);
+}
+
+__global__ void kb_col_prefix(const GridJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    const GridJob &j = J[r];
+    col_prefix_body(j.ncol, j.nhb, j.col_hist, j.w.col_count, blockIdx.x - off[r]);
+}
+
+__global__ __launch_bounds__(1024) void kb_col_scan(const GridJob *J) {
+    const GridJob &j = J[blockIdx.x];
+    scan_body(j.w.col_count, j.col_start, j.ncol, 1, j.cmax, j.nslots, nullptr);
+}
+
+__global__ __launch_bounds__(kHistThreads) void kb_bucket_hist(const GridJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    const GridJob &j = J[r];
+    bucket_hist_body(j.w.n, j.ncol, j.nhb, j.w.atom_col, j.col_start, j.col_hist, const_cast<int *>(j.s.bucket),
+                     blockIdx.x - off[r]);
+}
+
+__global__ __launch_bounds__(kSortThreads) void kb_col_sort(const GridJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    col_sort_body(J[r].s, blockIdx.x - off[r]);
+}
+
+__global__ void kb_bb(const GridJob *J, const int *off, int n, int which) {
+    const int r = job_of(off, n, blockIdx.x);
+    const GridJob &j = J[r];
+    if (which == 0) bb_body(j.nslots, j.m, j.s.xs, j.s.perm, j.bbi_lo, j.bbi_hi, blockIdx.x - off[r]);
+    else bb_body(j.nslots, j.nn, j.s.xs, j.s.perm, j.bbj_lo, j.bbj_hi, blockIdx.x - off[r]);
+}
+
+__global__ __launch_bounds__(1024) void kb_scan(const mxn::ScanJob *J) {
+    const mxn::ScanJob &j = J[blockIdx.x];
+    scan_body(j.in, j.out, j.n, j.mode, j.p, j.total, j.raw_total);
+}
+
+__global__ void kb_shiftvec(const GridJob *J) {
+    const GridJob &j = J[blockIdx.x];
+    shiftvec_body(j.shiftvec, j.w.Lx, j.w.Ly, j.w.Lz);
 }
 
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
@@ -258,19 +371,89 @@ inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 namespace mxn {
 
 void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(in, out, n, 0, 1, total);
+    k_scan<<<1, 1024, 0, s>>>(in, out, n, 0, 1, total, nullptr);
 }
 
-void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(in, out, n, mode, p, total);
+void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total, hipStream_t s) {
+    k_scan<<<1, 1024, 0, s>>>(in, out, n, mode, p, total, raw_total);
 }
+
+static WrapArgs make_wrap(const nb_grid *g, const float *xyzq) {
+    return WrapArgs{(const float4 *)xyzq, g->n, g->Lf[0], g->Lf[1], g->Lf[2], g->invL[0], g->invL[1], g->invL[2],
+                    g->inv_x, g->inv_y, g->nx, g->ny, (int *)g->col_count.p, (int *)g->atom_col.p,
+                    (int *)g->atom_img.p, (float4 *)g->atom_xw.p, g->ctx->d_flags};
+}
+
+static SortArgs make_sort(const nb_grid *g, const int *type) {
+    return SortArgs{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
+                    (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
+                    (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p,
+                    (int *)g->slot_of.p};
+}
+
+size_t grid_job_size() { return sizeof(GridJob); }
+int grid_job_stages() { return GS_NSTAGES; }
+
+bool grid_batchable(const nb_grid *g) { return g->ncol <= kMaxHistColumns; }
+
+void fill_grid_job(void *out, const nb_grid *g, const float *xyzq, const int *type) {
+    GridJob j{};
+    j.w = make_wrap(g, xyzq);
+    j.s = make_sort(g, type);
+    j.ncol = g->ncol;
+    j.nhb = hist_blocks(g->n);
+    j.cmax = g->cmax;
+    j.m = g->m;
+    j.nn = g->nn;
+    j.slots_cap = g->slots_cap;
+    j.col_hist = (int *)g->col_hist.p;
+    j.col_start = (int *)g->col_start.p;
+    j.nslots = (int *)g->nslots.p;
+    j.bbi_lo = (float4 *)g->bbi_lo.p;
+    j.bbi_hi = (float4 *)g->bbi_hi.p;
+    j.bbj_lo = (float4 *)g->bbj_lo.p;
+    j.bbj_hi = (float4 *)g->bbj_hi.p;
+    j.shiftvec = (float4 *)g->shiftvec.p;
+    std::memcpy(out, &j, sizeof j);
+}
+
+// workgroups of one replica in each batched stage (the histogram stages share GS_HIST)
+void grid_job_blocks(const nb_grid *g, int *blocks_per_stage) {
+    blocks_per_stage[GS_HIST] = hist_blocks(g->n);
+    blocks_per_stage[GS_PREFIX] = blocks(g->ncol, 256);
+    blocks_per_stage[GS_SCAN] = 1;
+    blocks_per_stage[GS_COLSORT] = g->ncol;
+    blocks_per_stage[GS_BBI] = blocks(g->slots_cap / g->m, 256);
+    blocks_per_stage[GS_BBJ] = g->nn != g->m ? blocks(g->slots_cap / g->nn, 256) : 0;
+}
+
+// off: DEVICE int[GS_NSTAGES * (n_rep + 1)], each stage's exclusive prefix of the
+// replicas' workgroups; total: HOST int[GS_NSTAGES] workgroups per stage
+int launch_grid_sort_batch(hipStream_t st, const void *jobs, const int *off, int n_rep, const int *total,
+                           int max_ncol) {
+    const GridJob *J = (const GridJob *)jobs;
+    const int *o = off;
+    const int stride = n_rep + 1;
+    const size_t hb = (size_t)max_ncol * sizeof(int);
+    kb_wrap_hist<<<total[GS_HIST], kHistThreads, hb, st>>>(J, o + GS_HIST * stride, n_rep);
+    kb_col_prefix<<<total[GS_PREFIX], 256, 0, st>>>(J, o + GS_PREFIX * stride, n_rep);
+    kb_col_scan<<<n_rep, 1024, 0, st>>>(J);
+    kb_bucket_hist<<<total[GS_HIST], kHistThreads, hb, st>>>(J, o + GS_HIST * stride, n_rep);
+    kb_col_sort<<<total[GS_COLSORT], kSortThreads, 0, st>>>(J, o + GS_COLSORT * stride, n_rep);
+    kb_bb<<<total[GS_BBI], 256, 0, st>>>(J, o + GS_BBI * stride, n_rep, 0);
+    if (total[GS_BBJ] > 0) kb_bb<<<total[GS_BBJ], 256, 0, st>>>(J, o + GS_BBJ * stride, n_rep, 1);
+    kb_shiftvec<<<n_rep, 32, 0, st>>>(J);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+// one exclusive scan per job, one workgroup each
+void launch_scan_batch(const ScanJob *jobs, int n_jobs, hipStream_t st) { kb_scan<<<n_jobs, 1024, 0, st>>>(jobs); }
 
 int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
     hipStream_t st = g->ctx->stream;
     const int n = g->n, ncol = g->ncol;
-    WrapArgs w{(const float4 *)xyzq, n, g->Lf[0], g->Lf[1], g->Lf[2], g->invL[0], g->invL[1], g->invL[2],
-               g->inv_x, g->inv_y, g->nx, g->ny, (int *)g->col_count.p, (int *)g->atom_col.p,
-               (int *)g->atom_img.p, (float4 *)g->atom_xw.p, g->ctx->d_flags};
+    const WrapArgs w = make_wrap(g, xyzq);
     const bool lds_hist = ncol <= kMaxHistColumns;
     const int nhb = hist_blocks(n);
     const size_t hb = (size_t)ncol * sizeof(int);
@@ -282,7 +465,7 @@ int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
         k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
     }
     k_scan<<<1, 1024, 0, st>>>((const int *)g->col_count.p, (int *)g->col_start.p, ncol, 1, g->cmax,
-                               (int *)g->nslots.p);
+                               (int *)g->nslots.p, nullptr);
     if (lds_hist) {
         k_bucket_hist<<<nhb, kHistThreads, hb, st>>>(n, ncol, nhb, (const int *)g->atom_col.p,
                                                      (const int *)g->col_start.p, (const int *)g->col_hist.p,
@@ -292,9 +475,7 @@ int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
         k_bucket<<<blocks(n, 256), 256, 0, st>>>(n, (const int *)g->atom_col.p, (const int *)g->col_start.p,
                                                  (int *)g->col_fill.p, (int *)g->bucket.p);
     }
-    SortArgs s{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
-               (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
-               (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p, (int *)g->slot_of.p};
+    const SortArgs s = make_sort(g, type);
     k_col_sort<<<ncol, kSortThreads, 0, st>>>(s);
     k_bb<<<blocks(g->slots_cap / g->m, 256), 256, 0, st>>>((const int *)g->nslots.p, g->m, (const float4 *)g->xs.p,
                                                           (const int *)g->perm.p, (float4 *)g->bbi_lo.p,

@@ -98,11 +98,15 @@ struct nb_list {
     float rlist = 0, rbb = 0;
     long cap_entries = 0;
     long cap_items = 0;
-    int ci_cap = 0;
-    mxn::DevBuf entries, items;    // entries: per i-cluster, ordered by bounding-box distance
-    mxn::DevBuf entries_canon, keys;   // fill-pass output in canonical order, and its sort keys
-    mxn::DevBuf ci_count, ci_start, ci_istart, part_count, part_start;
-    mxn::DevBuf totals;        // int[4]: entries, items, overflow, pad
+    // Entries live in equal regions, one per (i-cluster, search part):
+    // part_start holds the region starts (sized by a synchronous build),
+    // part_count the entries found by the latest build.
+    mxn::DevBuf entries, items;        // entries: canonical order, or by bounding-box distance
+    mxn::DevBuf entries_canon, keys;   // fill-pass output before a distance sort, and its sort keys
+    mxn::DevBuf part_count, part_start, part_istart;
+    mxn::DevBuf totals;        // int[4]: entries, items, usable items (0 after an overflow), region overflow
+    int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
+    int resv_nci = 0;          // i-cluster capacity of the reserved layout
     long last_entries = 0;     // host copy after a synchronous build
     long grid_generation = -1;
 };
@@ -111,11 +115,20 @@ struct nb_batch {
     nb_ctx *ctx = nullptr;
     int n_rep = 0, m = 0, nn = 0, waves = 4, ncu = 1;
     long total_slots = 0, total_atoms = 0, pstride = 0;
-    std::vector<const nb_grid *> grids;
-    std::vector<const nb_list *> lists;
+    std::vector<nb_grid *> grids;
+    std::vector<nb_list *> lists;
     std::vector<long> generations;
     mxn::DevBuf desc, slot_off, atom_off, item_off, partials;
     std::vector<char> desc_host;   // the replica table as last copied to the device
+    // batched rebuild (grid sort + list fill of every replica)
+    std::vector<const float *> xyzq;
+    std::vector<const int *> type, excl_off, excl_idx;
+    bool topology = false;
+    bool cycle = false;   // the captured graph holds the rebuild too
+    mxn::DevBuf gjobs, ljobs, goff, loff, scans;
+    std::vector<char> gjobs_host, ljobs_host;   // job tables as last copied to the device
+    std::vector<int> gtotal, ltotal;
+    int max_ncol = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;
@@ -132,6 +145,26 @@ namespace mxn {
 constexpr int kMlpParams = 4801;
 int launch_batch(nb_ctx *ctx, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial);
 size_t rep_desc_size();
+// batched list rebuild (grid sort and pair search of many replicas, one launch per stage)
+struct ScanJob {
+    const int *in;
+    int *out;
+    int n, mode, p;
+    int *total, *raw_total;
+};
+void launch_scan_batch(const ScanJob *jobs, int n_jobs, hipStream_t st);
+size_t grid_job_size();
+int grid_job_stages();
+bool grid_batchable(const nb_grid *g);
+void fill_grid_job(void *out, const nb_grid *g, const float *xyzq, const int *type);
+void grid_job_blocks(const nb_grid *g, int *blocks_per_stage);
+int launch_grid_sort_batch(hipStream_t st, const void *jobs, const int *off, int n_rep, const int *total, int max_ncol);
+size_t list_job_size();
+int list_job_stages();
+void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan);
+void list_job_blocks(const nb_list *l, int *blocks_per_stage);
+int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
+                          const ScanJob *scans);
 void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *xyzq_now, float *f, long pbase);
 int launch_mlp_step(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float lr, float *loss,
                     float *grad_out);

@@ -10,32 +10,70 @@
 //
 // Compiled with -ffp-contract=off: the inclusion predicate and the
 // exclusion-in-image test are defined by separately rounded FP32 operations.
+#include <cstring>
+
+#include "devptr.h"
 #include "internal.h"
 
 namespace mxn {
-void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, hipStream_t s);
+void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total, hipStream_t s);
 }
 
 namespace {
 
-struct SearchArgs {
-    const int *nslots;
-    const float4 *xs;
-    const int *perm, *slot_of;
-    const float4 *bbi_lo, *bbi_hi, *bbj_lo, *bbj_hi, *colbb;
-    const int *col_start;
-    const int *excl_off, *excl_idx;
+using mxn::gptr;
+using mxn::ld;
+using mxn::plain;
+using mxn::st;
+
+// Search arguments with plain pointers (kernel arguments of the single-system
+// launch) or global ones (read from a device table by the batched launch).
+template <template <class> class P>
+struct SearchArgsT {
+    P<const int> nslots;
+    P<const float4> xs;
+    P<const int> perm, slot_of;
+    P<const float4> bbi_lo, bbi_hi, bbj_lo, bbj_hi, colbb;
+    P<const int> col_start;
+    P<const int> excl_off, excl_idx;
     float Lx, Ly, Lz, inv_x, inv_y;
     int nx, ny;
     float rlist, rl2, rb2;
-    int *part_count;                     // entries found by each (i-cluster, part)
-    const int *part_start, *ci_start, *ci_istart, *totals;
-    nb_jentry *entries;   // per i-cluster: part by part, each part in (shift, j-cluster) order
-    float *keys;          // bounding-box distance^2 of each entry
-    int4 *items;
-    long cap_entries, cap_items;
+    P<int> part_count;                   // entries found by each (i-cluster, part)
+    P<const int> part_start;             // region of each (i-cluster, part)
+    P<int> region_overflow;              // set when a region is too small
+    P<nb_jentry> entries;   // each region in (shift, j-cluster) order
+    P<float> keys;          // bounding-box distance^2 of each entry (or null)
     int nci_cap, parts;
 };
+using SearchArgs = SearchArgsT<plain>;
+using SearchArgsG = SearchArgsT<gptr>;
+
+__device__ inline SearchArgsG to_global(const SearchArgs &a) {
+    SearchArgsG g;
+    g.nslots = (gptr<const int>)a.nslots;
+    g.xs = (gptr<const float4>)a.xs;
+    g.perm = (gptr<const int>)a.perm;
+    g.slot_of = (gptr<const int>)a.slot_of;
+    g.bbi_lo = (gptr<const float4>)a.bbi_lo;
+    g.bbi_hi = (gptr<const float4>)a.bbi_hi;
+    g.bbj_lo = (gptr<const float4>)a.bbj_lo;
+    g.bbj_hi = (gptr<const float4>)a.bbj_hi;
+    g.colbb = (gptr<const float4>)a.colbb;
+    g.col_start = (gptr<const int>)a.col_start;
+    g.excl_off = (gptr<const int>)a.excl_off;
+    g.excl_idx = (gptr<const int>)a.excl_idx;
+    g.Lx = a.Lx; g.Ly = a.Ly; g.Lz = a.Lz; g.inv_x = a.inv_x; g.inv_y = a.inv_y;
+    g.nx = a.nx; g.ny = a.ny;
+    g.rlist = a.rlist; g.rl2 = a.rl2; g.rb2 = a.rb2;
+    g.part_count = (gptr<int>)a.part_count;
+    g.part_start = (gptr<const int>)a.part_start;
+    g.region_overflow = (gptr<int>)a.region_overflow;
+    g.entries = (gptr<nb_jentry>)a.entries;
+    g.keys = (gptr<float>)a.keys;
+    g.nci_cap = a.nci_cap; g.parts = a.parts;
+    return g;
+}
 
 __device__ inline float sq3(float x, float y, float z) { return (x * x + y * y) + z * z; }
 
@@ -66,36 +104,38 @@ __device__ inline int lower_bound(int lo, int hi, F key, float v) {
 // share of every image shift's candidate columns.
 constexpr int kExclStage = 64;   // staged exclusion partners per wavefront
 
-template <int M, int N, bool FILL>
-__global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+template <int M, int N, bool FILL, class A>
+__device__ inline void search_body(const A &a, int blk) {
     constexpr unsigned FULL = (1u << M) - 1u;
     __shared__ float4 xpos[4][kExclStage];
     __shared__ int xinfo[4][kExclStage];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gw = blockIdx.x * 4 + w;
+    const int gw = blk * 4 + w;
     const int P = a.parts, ci = gw / P, part = gw % P;
     if (ci >= a.nci_cap) return;
     const int nci = *a.nslots / M;
     if (ci >= nci) {   // beyond the padded slot count of this sort: contributes nothing to the scans
-        if (!FILL && lane == 0) a.part_count[gw] = 0;
+        if (lane == 0) a.part_count[gw] = 0;
         return;
     }
-    int wpos = 0;
+    int wpos = 0, resv = 0;   // fill pass: this part's reserved region
     if (FILL) {
-        if ((long)a.totals[0] > a.cap_entries || (long)a.totals[1] > a.cap_items) return;   // overflow: latched later
         wpos = a.part_start[gw];
+        resv = a.part_start[gw + 1] - wpos;
     }
-    const float4 lo = a.bbi_lo[ci], hi = a.bbi_hi[ci];
+    const float4 lo = ld(a.bbi_lo + ci), hi = ld(a.bbi_hi + ci);
     // the i-cluster (uniform across the wavefront)
     float ix[M], iy[M], iz[M];
     unsigned ireal = 0;
 #pragma unroll
     for (int ia = 0; ia < M; ++ia) {
-        const float4 p = a.xs[ci * M + ia];
+        const float4 p = ld(a.xs + ci * M + ia);
         ix[ia] = p.x; iy[ia] = p.y; iz[ia] = p.z;
         ireal |= (a.perm[ci * M + ia] >= 0 ? 1u : 0u) << ia;
     }
-    const float zmargin = 1e-3f;   // keeps the z window conservative against rounding
+    // keeps the z windows conservative against rounding: the FP32 squared distances
+    // carry a relative error below 1e-6, so sqrt of that error is below 1e-3 rlist
+    const float zmargin = 1e-3f + 2e-3f * a.rlist;
     const float pmargin = 1e-3f;   // keeps the particle-to-box prefilter conservative
     const float rp2 = (a.rlist + pmargin) * (a.rlist + pmargin);
     // exclusion partners of the i-particles: (slot * 8 + i-index, position), staged in LDS
@@ -121,7 +161,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             for (int e = e0; e < e1; ++e, ++q) {
                 const int ps = a.slot_of[a.excl_idx[e]];
                 xinfo[w][q] = ps * 8 + lane;
-                xpos[w][q] = a.xs[ps];
+                xpos[w][q] = ld(a.xs + ps);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -156,13 +196,16 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 const int cidx = cb + lane;
                 if (cidx < c_hi) {
                     const int c = (cx0 + cidx / ncy) * a.ny + cy0 + cidx % ncy;
-                    const float4 cbb = a.colbb[c];
+                    const float4 cbb = ld(a.colbb + c);
                     const float gx = axis_gap(cbb.x, cbb.z, slx, shx), gy = axis_gap(cbb.y, cbb.w, sly, shy);
-                    if (gx * gx + gy * gy < a.rl2) {
+                    const float g2 = gx * gx + gy * gy;
+                    if (g2 < a.rl2) {
+                        // a j-cluster in this column lies at least (gx, gy) away in x and y, so
+                        // only z gaps below sqrt(rlist^2 - g^2) can pass the box test
+                        const float zr = sqrtf(a.rl2 - g2) + zmargin;
                         const int j0 = a.col_start[c] / N, j1 = a.col_start[c + 1] / N;
-                        const float4 *blo = a.bbj_lo, *bhi = a.bbj_hi;
-                        k0 = lower_bound(j0, j1, [&](int k) { return bhi[k].z; }, slz - a.rlist - zmargin);
-                        const int k1 = lower_bound(k0, j1, [&](int k) { return blo[k].z; }, shz + a.rlist + zmargin);
+                        k0 = lower_bound(j0, j1, [&](int k) { return ld(a.bbj_hi + k).z; }, slz - zr);
+                        const int k1 = lower_bound(k0, j1, [&](int k) { return ld(a.bbj_lo + k).z; }, shz + zr);
                         kc = k1 - k0;
                     }
                 }
@@ -192,7 +235,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     if (ok && s == 13) ok = cj * N + N - 1 > ci * M;
                     float d2 = 0.0f;
                     if (ok) {
-                        const float4 jl = a.bbj_lo[cj], jh = a.bbj_hi[cj];
+                        const float4 jl = ld(a.bbj_lo + cj), jh = ld(a.bbj_hi + cj);
                         d2 = sq3(axis_gap(jl.x, jh.x, slx, shx), axis_gap(jl.y, jh.y, sly, shy),
                                  axis_gap(jl.z, jh.z, slz, shz));
                         ok = d2 < a.rl2;
@@ -203,7 +246,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                         bool hit = false;
                         for (int b = 0; b < N && !hit; ++b) {
                             const int sb = cj * N + b;
-                            const float4 pj = a.xs[sb];
+                            const float4 pj = ld(a.xs + sb);
                             if (a.perm[sb] < 0) continue;
                             const float g = sq3(axis_gap(pj.x, pj.x, slx, shx), axis_gap(pj.y, pj.y, sly, shy),
                                                 axis_gap(pj.z, pj.z, slz, shz));
@@ -246,53 +289,71 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                                         const int ps = a.slot_of[a.excl_idx[e]];
                                         const int b = ps - cj * N;
                                         if (b < 0 || b >= N) continue;
-                                        const float4 pj = a.xs[ps];
+                                        const float4 pj = ld(a.xs + ps);
                                         if (sq3(px[ia] - pj.x, py[ia] - pj.y, pz[ia] - pj.z) < a.rl2)
                                             mask &= ~(1ull << (b * M + ia));
                                     }
                                 }
                             }
-                            const int rank = __popcll(accepted & ((1ull << lane) - 1ull));
-                            nb_jentry en;
-                            en.cj = cj;
-                            en.shift = s;
-                            en.mlo = (uint32_t)mask;
-                            en.mhi = (uint32_t)(mask >> 32);
-                            a.entries[wpos + rank] = en;
-                            a.keys[wpos + rank] = d2;
+                            const int rank = cnt + __popcll(accepted & ((1ull << lane) - 1ull));
+                            if (rank < resv) {
+                                nb_jentry en;
+                                en.cj = cj;
+                                en.shift = s;
+                                en.mlo = (uint32_t)mask;
+                                en.mhi = (uint32_t)(mask >> 32);
+                                st(a.entries + wpos + rank, en);
+                                if (a.keys) a.keys[wpos + rank] = d2;
+                            }
                         }
-                        wpos += __popcll(accepted);
-                    } else {
-                        cnt += __popcll(accepted);
                     }
+                    cnt += __popcll(accepted);
                 }
             }
         }
     }
-    if (!FILL) {
-        if (lane == 0) a.part_count[gw] = cnt;
-    } else if (part == 0) {
-        const int start = a.ci_start[ci], end = a.ci_start[ci + 1], ipos = a.ci_istart[ci];
-        const int nit = (end - start + mxn::kItemEntries - 1) / mxn::kItemEntries;
-        for (int k = lane; k < nit; k += 64) {
-            const int js = start + k * mxn::kItemEntries;
-            const int je = js + mxn::kItemEntries < end ? js + mxn::kItemEntries : end;
-            a.items[ipos + k] = make_int4(ci, js, je, 0);
-        }
+    if (lane == 0) {
+        a.part_count[gw] = cnt;
+        if (FILL && cnt > resv) atomicOr((int *)a.region_overflow, 1);
     }
 }
 
-// Order the entries of each i-cluster by bounding-box distance (ties by
-// canonical position), so that the far entries, whose pairs mostly lie beyond
-// the cut-off, share force-kernel passes whose pair work can be skipped.
-// One wavefront per i-cluster, rank sort with the keys staged in LDS.
-__global__ __launch_bounds__(64) void k_sort_entries(const int *ci_start, const int *totals, long cap_entries,
-                                                     long cap_items, const nb_jentry *in, const float *keys,
-                                                     nb_jentry *out) {
+template <int M, int N, bool FILL>
+__global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+    search_body<M, N, FILL>(a, blockIdx.x);
+}
+
+// Work items: each (i-cluster, part) region cut into runs of at most
+// kItemEntries entries, at the offsets of a scan over the regions' counts.
+__device__ inline void items_body(int nparts_total, int parts, const int *part_count, const int *part_start,
+                                  const int *part_istart, long cap_items, int4 *items, int blk) {
+    const int g = blk * blockDim.x + threadIdx.x;
+    if (g >= nparts_total) return;
+    const int resv = part_start[g + 1] - part_start[g];
+    const int cnt = min(part_count[g], resv), start = part_start[g], ip = part_istart[g];
+    const int nit = (cnt + mxn::kItemEntries - 1) / mxn::kItemEntries;
+    for (int k = 0; k < nit; ++k) {
+        if ((long)ip + k >= cap_items) return;   // overflow: latched by k_finalize
+        const int js = start + k * mxn::kItemEntries;
+        const int je = min(js + mxn::kItemEntries, start + cnt);
+        items[ip + k] = make_int4(g / parts, js, je, 0);
+    }
+}
+
+__global__ void k_items(int nparts_total, int parts, const int *part_count, const int *part_start,
+                        const int *part_istart, long cap_items, int4 *items) {
+    items_body(nparts_total, parts, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
+}
+
+// Order the entries of each (i-cluster, part) region by bounding-box distance
+// (ties by canonical position), so that the far entries, whose pairs mostly
+// lie beyond the cut-off, share force-kernel passes whose pair work can be
+// skipped.  One wavefront per region, rank sort with the keys staged in LDS.
+__global__ __launch_bounds__(64) void k_sort_entries(const int *part_start, const int *part_count,
+                                                     const nb_jentry *in, const float *keys, nb_jentry *out) {
     __shared__ float sk[1024];
-    if ((long)totals[0] > cap_entries || (long)totals[1] > cap_items) return;
-    const int ci = blockIdx.x, lane = threadIdx.x;
-    const int b = ci_start[ci], n = ci_start[ci + 1] - b;
+    const int g = blockIdx.x, lane = threadIdx.x;
+    const int b = part_start[g], n = min(part_count[g], part_start[g + 1] - b);
     const bool staged = n <= 1024;
     if (staged)
         for (int i = lane; i < n; i += 64) sk[i] = keys[b + i];
@@ -308,22 +369,82 @@ __global__ __launch_bounds__(64) void k_sort_entries(const int *ci_start, const 
     }
 }
 
-// Per i-cluster entry counts and offsets from the per-part offsets.
-__global__ void k_ci_offsets(const int *part_start, int nci_cap, int parts, int *ci_count, int *ci_start) {
-    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci > nci_cap) return;
-    const int s = part_start[(long)ci * parts];
-    ci_start[ci] = s;
-    if (ci < nci_cap) ci_count[ci] = part_start[(long)(ci + 1) * parts] - s;
+// Largest entry count of any region (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_max_count(const int *in, int n, int *out) {
+    __shared__ int m[1024];
+    int v = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) v = max(v, in[i]);
+    m[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) m[threadIdx.x] = max(m[threadIdx.x], m[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = m[0];
 }
 
-// totals: [0] entries, [1] items (from the scans); writes [2] = usable item
-// count (0 on overflow) and latches the overflow flag
-__global__ void k_finalize(int *totals, long cap_entries, long cap_items, int *flags) {
+// Uniform regions: region g starts at g * size (g = 0 .. n).
+__global__ void k_region_starts(int n, int size, int *start) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= n) start[g] = g * size;
+}
+
+// totals: [0] entries, [1] items (from the scan), [3] region overflow; writes
+// [2] = usable item count (0 on overflow), latches the overflow flag and
+// clears [3] for the next build
+__device__ inline void finalize_body(int *totals, long cap_items, int *flags) {
     if (threadIdx.x != 0) return;
-    bool over = (long)totals[0] > cap_entries || (long)totals[1] > cap_items;
+    const bool over = totals[3] != 0 || (long)totals[1] > cap_items;
     totals[2] = over ? 0 : totals[1];
+    totals[3] = 0;
     if (over) atomicOr(flags, mxn::FLAG_OVERFLOW);
+}
+
+__global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_body(totals, cap_items, flags); }
+
+// --------------------------------------------------------------------------
+// Batched rebuild of many replicas' lists (the fill pass into the regions the
+// replicas' last synchronous builds sized), one launch per stage; a
+// workgroup finds its replica by binary search in the stage's prefix of
+// share sizes.
+
+struct ListJob {
+    SearchArgs a;
+    int nregions;
+    int *part_count, *part_start, *part_istart, *totals;
+    int4 *items;
+    long cap_items;
+    int *flags;
+};
+
+enum { LS_SEARCH, LS_ITEMS, LS_NSTAGES };
+
+__device__ inline int job_of(const int *off, int n, int b) {
+    int lo = 0, hi = n - 1;   // last r with off[r] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int M, int N>
+__global__ __launch_bounds__(256) void kb_search(const ListJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    search_body<M, N, true>(to_global(J[r].a), blockIdx.x - off[r]);
+}
+
+__global__ void kb_items(const ListJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    const ListJob &j = J[r];
+    items_body(j.nregions, j.a.parts, j.part_count, j.part_start, j.part_istart, j.cap_items, j.items,
+               blockIdx.x - off[r]);
+}
+
+__global__ void kb_finalize(const ListJob *J) {
+    const ListJob &j = J[blockIdx.x];
+    finalize_body(j.totals, j.cap_items, j.flags);
 }
 
 template <int M, int N>
@@ -338,11 +459,8 @@ void run(nb_list *l, SearchArgs &a, bool fill, int nblocks, hipStream_t st) {
 
 namespace mxn {
 
-int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync, bool by_distance) {
+static SearchArgs make_search(const nb_list *l, const int *excl_off, const int *excl_idx) {
     const nb_grid *g = l->grid;
-    nb_ctx *ctx = l->ctx;
-    hipStream_t st = ctx->stream;
-    const int nci_cap = g->slots_cap / g->m;
     SearchArgs a{};
     a.nslots = (const int *)g->nslots.p;
     a.xs = (const float4 *)g->xs.p;
@@ -364,63 +482,130 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     a.rl2 = rl2; a.rb2 = rb2;
     a.part_count = (int *)l->part_count.p;
     a.part_start = (const int *)l->part_start.p;
-    a.ci_start = (const int *)l->ci_start.p;
-    a.ci_istart = (const int *)l->ci_istart.p;
-    a.totals = (const int *)l->totals.p;
-    a.nci_cap = nci_cap;
-    // parts per i-cluster: the largest power of two up to 8 that keeps about 6000
-    // wavefronts or fewer (measured on MI355X: more parts only add per-part overhead
-    // once the GPU holds that many latency-bound wavefronts)
-    int parts = ctx->search_parts;
-    if (parts == 0) {
-        const long nci = std::max(1, g->n / g->m);
-        parts = 1;
-        while (parts < kMaxSearchParts && nci * parts * 2 <= 6000) parts *= 2;
+    a.region_overflow = (int *)l->totals.p + 3;
+    a.nci_cap = g->slots_cap / g->m;
+    return a;
+}
+
+size_t list_job_size() { return sizeof(ListJob); }
+int list_job_stages() { return LS_NSTAGES; }
+
+// The list must have been sized by a synchronous build for its grid's capacity.
+void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan) {
+    ListJob j{};
+    j.a = make_search(l, excl_off, excl_idx);
+    j.a.parts = l->resv_parts;
+    j.a.entries = (nb_jentry *)l->entries.p;
+    j.a.keys = nullptr;
+    j.nregions = l->resv_nci * l->resv_parts;
+    j.part_count = (int *)l->part_count.p;
+    j.part_start = (int *)l->part_start.p;
+    j.part_istart = (int *)l->part_istart.p;
+    j.totals = (int *)l->totals.p;
+    j.items = (int4 *)l->items.p;
+    j.cap_items = l->cap_items;
+    j.flags = l->ctx->d_flags;
+    std::memcpy(out, &j, sizeof j);
+    *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, kItemEntries, j.totals + 1, j.totals};
+}
+
+void list_job_blocks(const nb_list *l, int *blocks_per_stage) {
+    const long nreg = (long)l->resv_nci * l->resv_parts;
+    blocks_per_stage[LS_SEARCH] = (int)((nreg + 3) / 4);
+    blocks_per_stage[LS_ITEMS] = (int)((nreg + 255) / 256);
+}
+
+int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
+                          const ScanJob *scans) {
+    const ListJob *J = (const ListJob *)jobs;
+    const int stride = n_rep + 1;
+    if (m == 4 && nn == 4) kb_search<4, 4><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
+    else if (m == 4 && nn == 8) kb_search<4, 8><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
+    else kb_search<8, 8><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
+    launch_scan_batch(scans, n_rep, st);
+    kb_items<<<total[LS_ITEMS], 256, 0, st>>>(J, off + LS_ITEMS * stride, n_rep);
+    kb_finalize<<<n_rep, 64, 0, st>>>(J);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync, bool by_distance) {
+    const nb_grid *g = l->grid;
+    nb_ctx *ctx = l->ctx;
+    hipStream_t st = ctx->stream;
+    const int nci_cap = g->slots_cap / g->m;
+    SearchArgs a = make_search(l, excl_off, excl_idx);
+    // A synchronous build (also the first, and any after the grid's capacity
+    // changed) counts the entries and gives every (i-cluster, part) region the
+    // largest count plus a quarter plus 8 (uniform, because a re-sort re-forms
+    // the clusters, so a region's next occupant may have any count); later
+    // builds search once and fill the regions.
+    const bool reserve = sync || l->resv_parts == 0 || l->resv_nci != nci_cap;
+    int parts = l->resv_parts;
+    if (reserve) {
+        // parts per i-cluster: the largest power of two up to 8 that keeps about 6000
+        // wavefronts or fewer (measured on MI355X: more parts only add per-part overhead
+        // once the GPU holds that many latency-bound wavefronts)
+        parts = ctx->search_parts;
+        if (parts == 0) {
+            const long nci = std::max(1, g->n / g->m);
+            parts = 1;
+            while (parts < kMaxSearchParts && nci * parts * 2 <= 6000) parts *= 2;
+        }
     }
     a.parts = parts;
-    const int nblocks = (int)(((long)nci_cap * parts + 3) / 4);
-    // count pass
-    if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, false, nblocks, st);
-    else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, false, nblocks, st);
-    else run<8, 8>(l, a, false, nblocks, st);
-    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_start.p, nci_cap * parts, 0, 1,
-                     (int *)l->totals.p, st);
-    k_ci_offsets<<<(nci_cap + 256) / 256, 256, 0, st>>>((const int *)l->part_start.p, nci_cap, parts,
-                                                      (int *)l->ci_count.p, (int *)l->ci_start.p);
-    launch_scan_mode((const int *)l->ci_count.p, (int *)l->ci_istart.p, nci_cap, 2, kItemEntries,
-                     (int *)l->totals.p + 1, st);
-    if (sync) {
-        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    const int nregions = nci_cap * parts;
+    const int nblocks = (int)(((long)nregions + 3) / 4);
+    if (reserve) {
+        if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, false, nblocks, st);
+        else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, false, nblocks, st);
+        else run<8, 8>(l, a, false, nblocks, st);
+        k_max_count<<<1, 1024, 0, st>>>((const int *)l->part_count.p, nregions, (int *)l->totals.p);
+        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        MXN_HIP(hipMemsetAsync((int *)l->totals.p + 3, 0, sizeof(int), st));
         MXN_HIP(hipStreamSynchronize(st));
-        long ne = ctx->h_pinned[0], ni = ctx->h_pinned[1];
-        if (ne > l->cap_entries || ni > l->cap_items) {
-            long ce = ne + ne / 8 + 1024, cit = ni + ni / 8 + 256;
+        const long mx = ctx->h_pinned[0];
+        const long size = mx + mx / 4 + 8;
+        if (size * nregions > (1L << 31) - 1) return fail(NB_ERR_OOM, "nb_pairlist_build: list larger than 2^31 entries");
+        const long ce = size * nregions;
+        if (ce > l->cap_entries) {
             int rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
             if (rc) return rc;
-            rc = ensure(l->entries_canon, (size_t)ce * sizeof(nb_jentry));
-            if (rc) return rc;
-            rc = ensure(l->keys, (size_t)ce * sizeof(float));
-            if (rc) return rc;
-            rc = ensure(l->items, (size_t)cit * sizeof(int4));
-            if (rc) return rc;
             l->cap_entries = ce;
+        }
+        const long cit = ce / kItemEntries + nregions + 256;   // each region: at most count/32 + 1 items
+        if (cit > l->cap_items) {
+            int rc = ensure(l->items, (size_t)cit * sizeof(int4));
+            if (rc) return rc;
             l->cap_items = cit;
         }
-        l->last_entries = ne;
+        k_region_starts<<<(nregions + 256) / 256, 256, 0, st>>>(nregions, (int)size, (int *)l->part_start.p);
+        l->resv_parts = parts;
+        l->resv_nci = nci_cap;
+        l->last_entries = ce;
+    }
+    if (by_distance) {   // the fill pass writes canonical order and keys; the sort orders each region
+        int rc = ensure(l->entries_canon, (size_t)l->cap_entries * sizeof(nb_jentry));
+        if (rc) return rc;
+        rc = ensure(l->keys, (size_t)l->cap_entries * sizeof(float));
+        if (rc) return rc;
     }
     a.entries = (nb_jentry *)(by_distance ? l->entries_canon.p : l->entries.p);
-    a.keys = (float *)l->keys.p;
-    a.items = (int4 *)l->items.p;
-    a.cap_entries = l->cap_entries;
-    a.cap_items = l->cap_items;
+    a.keys = by_distance ? (float *)l->keys.p : nullptr;
     if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, true, nblocks, st);
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
+    // item offsets per region; totals[0] = entries found, totals[1] = items
+    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, kItemEntries,
+                     (int *)l->totals.p + 1, (int *)l->totals.p, st);
+    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, (const int *)l->part_count.p,
+                                                  (const int *)l->part_start.p, (const int *)l->part_istart.p,
+                                                  l->cap_items, (int4 *)l->items.p);
     if (by_distance)
-        k_sort_entries<<<nci_cap, 64, 0, st>>>((const int *)l->ci_start.p, (const int *)l->totals.p, l->cap_entries,
-                                           l->cap_items, (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
-                                           (nb_jentry *)l->entries.p);
-    k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_entries, l->cap_items, ctx->d_flags);
+        k_sort_entries<<<nregions, 64, 0, st>>>((const int *)l->part_start.p, (const int *)l->part_count.p,
+                                                (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
+                                                (nb_jentry *)l->entries.p);
+    k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, ctx->d_flags);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }

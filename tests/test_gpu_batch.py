@@ -108,3 +108,80 @@ def test_autotuner_choice_is_valid_and_cached(tmp_path):
         assert json.loads(cache.read_text())
     finally:
         mxn.nb_destroy(ctx)
+
+
+@pytest.mark.parametrize("shape", [(4, 8), (8, 8)])
+def test_batched_rebuild_and_cycle_graph(shape):
+    """After the particles move, one batched rebuild (grid sort + list of every replica, one launch per stage)
+    gives each replica the list its own build gives (bit-exact; two replicas also against the oracle); a graph
+    of rebuild + three force evaluations replays correctly with eager work between the replays."""
+    import torch
+    import paper_1306_1737_amd as mxn
+    dev = torch.device("cuda:0")
+    ctx = mxn.nb_create(0)
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(1.0, 3.12, F, lj)
+        reps = _replicas(torch, mxn, ctx, shape)
+        n = len(reps)
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        mxn.nb_batch_bind_topology(batch, [r["type"] for r in reps], [r["eo"] for r in reps], [r["ei"] for r in reps])
+        moved = []
+        for k, r in enumerate(reps):
+            b = r["box"]
+            x9 = synth.free_flight(b.xyz, synth.velocities(b.mass, 300.0, seed=70 + k), 0.002, 10)[9].astype(np.float32)
+            moved.append(x9)
+            r["xyzq"].copy_(torch.from_numpy(b.xyzq(x9)).to(dev))   # in place: the batch keeps the pointer
+        mxn.nb_batch_rebuild(ctx, batch)
+        mxn.nb_sync(ctx)
+        got = [mxn.nb_list_export_canonical(r["lst"]) for r in reps]
+        # each replica's own synchronous build on the moved positions
+        for k, r in enumerate(reps):
+            g = mxn.nb_grid_sort(ctx, r["box"].box, r["xyzq"], r["type"], shape)
+            lst = mxn.nb_pairlist_build(ctx, g, 1.1, -1.0, r["eo"], r["ei"])
+            ref = mxn.nb_list_export_canonical(lst)
+            assert len(ref) == len(got[k])
+            for key in ("ci", "shift", "cj", "mask"):
+                np.testing.assert_array_equal(got[k][key], ref[key], err_msg="replica %d %s" % (k, key))
+            mxn.nb_list_free(lst)
+            mxn.nb_grid_free(g)
+        for k in (0, 2):
+            b = reps[k]["box"]
+            og = oracle.grid_sort(moved[k], b.box, *shape)
+            rho = b.n / b.box.prod()
+            rbb = np.float32(max(0.0, 1.1 - 0.5 * (max(shape) / rho) ** (1 / 3)))
+            ref = oracle.pairlist(og, b.box, np.float32(1.1), rbb, b.excl_off, b.excl_idx)
+            assert len(ref) == len(got[k])
+            for key in ("ci", "shift", "cj", "mask"):
+                np.testing.assert_array_equal(got[k][key], ref[key], err_msg="oracle replica %d %s" % (k, key))
+        # forces after the batched rebuild, per replica, against the oracle
+        energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        mxn.nb_batch_forces(ctx, batch, p, mxn.NB_ENERGY, energy)
+        mxn.nb_sync(ctx)
+        ref_f = [r["f"].cpu().numpy().astype(np.float64) for r in reps]
+        ref_e = energy.cpu().numpy().reshape(n, 2).copy()
+        for k in (1, 3):
+            b = reps[k]["box"]
+            fr, er, _ = oracle.forces(moved[k], b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(), 1.0,
+                                      3.12, F)
+            assert rel_rms(ref_f[k], fr) <= 1e-5
+            np.testing.assert_allclose(ref_e[k], er, rtol=1e-5)
+        # one graph: rebuild + 3 force evaluations
+        mxn.nb_batch_capture_cycle(ctx, batch, 3, p, mxn.NB_ENERGY, energy)
+        for rep in range(3):
+            for r in reps:
+                r["f"].fill_(float("nan"))
+            energy.zero_()
+            torch.cuda.synchronize()
+            mxn.nb_batch_replay(ctx, batch)
+            mxn.nb_sync(ctx)
+            e = energy.cpu().numpy().reshape(n, 2)
+            for k, r in enumerate(reps):
+                assert rel_rms(r["f"].cpu().numpy().astype(np.float64), ref_f[k]) <= 1e-6
+                np.testing.assert_allclose(e[k], ref_e[k], rtol=1e-9)
+        mxn.nb_batch_free(batch)
+        for r in reps:
+            mxn.nb_list_free(r["lst"]); mxn.nb_grid_free(r["grid"])
+    finally:
+        mxn.nb_destroy(ctx)

@@ -94,6 +94,40 @@ def test_pairlist_bitexact(c1, shape, rlist):
 
 
 @pytest.mark.parametrize("shape", SHAPES)
+def test_async_rebuild_in_reserved_regions(c1, shape):
+    """An asynchronous rebuild (one search pass into the regions a synchronous build reserved) after the
+    particles moved equals the oracle's list for the new positions; a rebuild that outgrows the regions is
+    reported, and a synchronous build then re-reserves."""
+    rlist = 1.0
+    rbb = np.float32(default_rbb(c1, shape, rlist))
+    v = synth.velocities(c1.mass, 300.0, seed=11)
+    x9 = synth.free_flight(c1.xyz, v, 0.002, 10)[9].astype(np.float32)
+    s = GpuSystem(c1, shape, rlist, rbb=float(rbb))
+    try:
+        mxn, torch = s.mxn, s.torch
+        xq9 = torch.from_numpy(c1.xyzq(x9)).to(s.dev)
+        s.grid = mxn.nb_grid_sort(s.ctx, c1.box, xq9, s.type, shape, s.grid)
+        s.lst = mxn.nb_pairlist_build(s.ctx, s.grid, rlist, float(rbb), s.eo, s.ei, mxn.NB_LIST_ASYNC, s.lst)
+        mxn.nb_sync(s.ctx)
+        g = oracle.grid_sort(x9, c1.box, *shape)
+        _cmp_lists(mxn.nb_list_export_canonical(s.lst),
+                   oracle.pairlist(g, c1.box, np.float32(rlist), rbb, c1.excl_off, c1.excl_idx))
+        # a much larger radius cannot fit the regions reserved at rlist = 1.0
+        big = 1.45
+        rbb2 = np.float32(default_rbb(c1, shape, big))
+        s.lst = mxn.nb_pairlist_build(s.ctx, s.grid, big, float(rbb2), s.eo, s.ei, mxn.NB_LIST_ASYNC, s.lst)
+        with pytest.raises(mxn.NbError) as err:
+            mxn.nb_sync(s.ctx)
+        assert err.value.status == mxn.NB_ERR_OVERFLOW
+        s.lst = mxn.nb_pairlist_build(s.ctx, s.grid, big, float(rbb2), s.eo, s.ei, 0, s.lst)
+        mxn.nb_sync(s.ctx)
+        _cmp_lists(mxn.nb_list_export_canonical(s.lst),
+                   oracle.pairlist(g, c1.box, np.float32(big), rbb2, c1.excl_off, c1.excl_idx))
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
 def test_pairlist_same_for_every_search_split(c1, shape):
     """Wavefronts sharing one i-cluster's search (1, 2, 4, 8) change only the order of its entries."""
     rbb = np.float32(default_rbb(c1, shape, 1.0))
