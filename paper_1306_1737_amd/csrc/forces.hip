@@ -123,16 +123,35 @@ __device__ inline float wave_sum_dpp(float v) {
     return __int_as_float(x);
 }
 
+// Per-type-pair table in LDS: [ti*nt + tj] = (C6, C12, LJ shift at rc,
+// Coulomb shift at rc), and one all-zero row at nt*nt that pairs with a
+// clear mask bit (excluded or dummy) read instead, so the pair math needs no
+// per-term selects for them.
+__device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
+    for (int t = threadIdx.x; t <= a.nt * a.nt; t += blockDim.x) {
+        if (t == a.nt * a.nt) {
+            ljt[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            continue;
+        }
+        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
+        ljt[t] = make_float4(c6, c12, sh, a.shiftC);
+    }
+}
+
 // One pass of the direct kernel's inner loop: this lane's j-particle against
-// the M i-particles.  (A uniform mask-free copy of this loop for passes
-// without exclusions, dummies or self pairs measured slower on gfx950: the
-// duplicated body costs more than the mask selects it saves.)
+// the M i-particles.  Measured slower on gfx950, and therefore not used:
+// a uniform mask-free copy of this loop for passes without exclusions (the
+// duplicated body costs more than the selects it saves); a branch-free body
+// whose eight i-particle chains the compiler can interleave (132 registers,
+// occupancy 3: 240 us against 198 us on the 96k-atom box).
 template <int M, bool ENER>
 __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float (&xi)[M], const float (&yi)[M],
                                  const float (&zi)[M], const float (&qi)[M], const int (&ti)[M], float xj, float yj,
                                  float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l, float (&fix)[M],
                                  float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz, float &el,
                                  float &ec) {
+    const int znull = a.nt * a.nt;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
@@ -143,6 +162,7 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
             const float rinv2 = rinv * rinv;
             const float u = r2 * rinv * a.beta;
             const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+            // erfc(u) = exp(-u^2) P(u) / Q(u)
             const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
             const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u,
                                  1.0f);
@@ -151,8 +171,8 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
             const float vc = em * rinv;
             const float qq = qi[k] * qj;
             float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
-            const float4 lj = ljt[ti[k] + tj];
-            const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
+            const float4 lj = ljt[bit ? ti[k] + tj : znull];   // the zero row for a clear bit
+            const float c6 = lj.x, c12 = lj.y;
             const float rinv6 = rinv2 * rinv2 * rinv2;
             const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
             fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
@@ -163,8 +183,8 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
             fjy = fmaf(-fsc, dy, fjy);
             fjz = fmaf(-fsc, dz, fjz);
             if (ENER) {
-                el += t12 - t6 - (bit ? lj.z : 0.0f);
-                ec += qq * (vc - (bit ? a.shiftC : 0.0f));
+                el += t12 - t6 - lj.z;
+                ec += qq * (vc - lj.w);
             }
         }
     }
@@ -207,13 +227,15 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
 
     float xi[M], yi[M], zi[M], qi[M];
     int ti[M];
+    unsigned ireal = 0;   // i-slots holding particles (dummies have type -1)
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const float4 p = ld(v.xs_now + ci * M + k);
         xi[k] = p.x; yi[k] = p.y; zi[k] = p.z;
         qi[k] = p.w * a.coulomb_f;
         const int t = v.type_s[ci * M + k];
-        ti[k] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;   // types outside [0, ntypes) are clamped
+        ireal |= (t >= 0 ? 1u : 0u) << k;
+        ti[k] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;   // types beyond ntypes are clamped
     }
     float fix[M], fiy[M], fiz[M];
 #pragma unroll
@@ -230,18 +252,19 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         const nb_jentry en = ld(v.entries + (valid ? e : e0));
         const int jslot = en.cj * N + jb;
         const float4 pj = ld(v.xs_now + jslot);
-        const int tj = min(max(v.type_s[jslot], 0), a.nt - 1);
+        const int tjr = v.type_s[jslot];
+        const int tj = min(max(tjr, 0), a.nt - 1);
         const float4 sv = svec[en.shift];
         const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
         const float qj = pj.w;
         const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
         const unsigned mb = (unsigned)(m64 >> (jb * M)) & FULL;
-        unsigned act = FULL;
+        unsigned act = ireal;   // pairs of real particles only: dummies never interact
         if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
             const int t = jslot - ci * M;
-            act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
+            act &= t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
         }
-        if (!valid) act = 0u;
+        if (!valid || tjr < 0) act = 0u;
         float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
         const float rc2l = valid ? a.rc2 : -1.0f;
         pair_pass<M, ENER>(a, ljt, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, act, rc2l, fix, fiy, fiz, fjx, fjy, fjz,
@@ -299,11 +322,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     float4 *svec = smem;        // 27 image shift vectors
     float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
     for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
-    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
-        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
-        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
-        ljt[t] = make_float4(c6, c12, sh, 0.0f);
-    }
+    fill_ljt(a, ljt);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -430,16 +449,12 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
     float4 *svec = smem;
     float4 *ljt = smem + 32;
     for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
-    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
-        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
-        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
-        ljt[t] = make_float4(c6, c12, sh, 0.0f);
-    }
+    fill_ljt(a, ljt);
     __syncthreads();
 
     using acc_t = typename std::conditional<ACC64, double, float>::type;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    char *wb = reinterpret_cast<char *>(smem + 32 + a.nt * a.nt) + (size_t)wave * wave_lds_bytes<N>();
+    char *wb = reinterpret_cast<char *>(smem + 32 + a.nt * a.nt + 1) + (size_t)wave * wave_lds_bytes<N>();
     float4 *jd = reinterpret_cast<float4 *>(wb);
     int *jinfo = reinterpret_cast<int *>(wb + JMAX * 16);
     float *fjx = reinterpret_cast<float *>(wb + JMAX * 20);
@@ -461,22 +476,24 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         const nb_jentry en = a.entries[js + (valid ? jidx : 0) / N];
         const int jslot = en.cj * N + (jidx % N);
         const float4 pj = a.xs_now[jslot];
-        const int tj = min(max(a.type_s[jslot], 0), a.nt - 1);
+        const int tjr = a.type_s[jslot];
+        const int tj = min(max(tjr, 0), a.nt - 1);
         const float4 sv = svec[en.shift];
         const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
         const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
         const unsigned mb = (unsigned)(m64 >> ((jidx % N) * M)) & FULL;
-        unsigned act = FULL;
+        unsigned act = tjr < 0 ? 0u : FULL;   // dummies (type -1) never interact
         if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
             const int t = jslot - ci * M;
-            act = t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
+            act &= t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
         }
         unsigned inr = 0;
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const float4 pik = a.xs_now[ci * M + k];
             const float dx = pik.x - xj, dy = pik.y - yj, dz = pik.z - zj;
-            inr |= (unsigned)(dx * dx + dy * dy + dz * dz < a.rc2) << k;
+            const bool ireal = a.type_s[ci * M + k] >= 0;
+            inr |= (unsigned)(ireal && dx * dx + dy * dy + dz * dz < a.rc2) << k;
         }
         inr &= act;
         if (valid) {
@@ -728,11 +745,7 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     const long total = b.item_off[b.n_rep];
     if (xcd_block_first(total, b.waves) < 0) return;   // whole workgroup past the end
     extern __shared__ float4 ljt[];
-    for (int t = threadIdx.x; t < a.nt * a.nt; t += blockDim.x) {
-        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
-        const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
-        ljt[t] = make_float4(c6, c12, sh, 0.0f);
-    }
+    fill_ljt(a, ljt);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const long idx = xcd_item(total, b.waves, threadIdx.x >> 6);
@@ -897,7 +910,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     int nb = (int)((nwaves + 3) / 4);
     nb = (nb + 7) / 8 * 8;
     if (nb == 0) nb = 8;
-    const size_t lds = (32 + (size_t)p->ntypes * p->ntypes) * sizeof(float4);
+    const size_t lds = (32 + (size_t)p->ntypes * p->ntypes + 1) * sizeof(float4);
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
         const int var = ctx->force_variant;
@@ -947,7 +960,7 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
     b.flags = ctx->d_flags;
     k_batch_prefix<<<1, 1024, 0, st>>>(b);
     k_batch_gather<<<(int)((bt->total_slots + 255) / 256), 256, 0, st>>>(b);
-    const size_t lds = (size_t)p->ntypes * p->ntypes * sizeof(float4);
+    const size_t lds = ((size_t)p->ntypes * p->ntypes + 1) * sizeof(float4);
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
         if (bt->m == 4 && bt->nn == 4) launch_batch_shape<4, 4>(a, b, flags, bt->pstride, lds, st);

@@ -181,7 +181,7 @@ __device__ inline void col_sort_body(const SortArgs &a, int c) {
             float4 p = a.atom_xw[orig];
             a.xs[slot] = p;
             a.xs_now[slot] = p;
-            a.type_s[slot] = a.type[orig];
+            a.type_s[slot] = max(a.type[orig], 0);   // negative types clamp to 0; -1 marks dummies
             a.perm[slot] = orig;
             a.img_s[slot] = a.atom_img[orig];
             a.slot_of[orig] = slot;
@@ -189,13 +189,13 @@ __device__ inline void col_sort_body(const SortArgs &a, int c) {
             mxx = fmaxf(mxx, p.x); mxy = fmaxf(mxy, p.y);
         }
     }
-    // dummies: no charge, type 0 (never used: their mask bits are 0), distinct far positions
+    // dummies: no charge, type -1 (the kernels skip them), distinct far positions
     for (int slot = start + nc + tid; slot < end; slot += kSortThreads) {
         float4 d = make_float4(-1000.0f - 4.0f * (float)(slot & 1023), -1000.0f - 4.0f * (float)((slot >> 10) & 1023),
                                -1000.0f - 4.0f * (float)(slot >> 20), 0.0f);
         a.xs[slot] = d;
         a.xs_now[slot] = d;
-        a.type_s[slot] = 0;
+        a.type_s[slot] = -1;
         a.perm[slot] = -1;
         a.img_s[slot] = kImgBias | (kImgBias << 10) | (kImgBias << 20);
     }
