@@ -550,7 +550,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         if (parts == 0) {
             const long nci = std::max(1, g->n / g->m);
             parts = 1;
-            while (parts < kMaxSearchParts && nci * parts * 2 <= 6000) parts *= 2;
+            while (parts < kMaxSearchParts && nci * parts * 2 < 6000) parts *= 2;
         }
     }
     a.parts = parts;
