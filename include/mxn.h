@@ -272,6 +272,10 @@ int nb_batch_replay(nb_ctx *ctx, nb_batch *batch);
  * NB_ERR_OVERFLOW if a region overflows.  No host synchronisation.
  *   type, excl_off, excl_idx   HOST arrays of n_rep DEVICE pointers (each as
  *                              for nb_grid_sort / nb_pairlist_build)
+ * nb_batch_bind_topology re-sizes (synchronously) any replica list whose
+ * search is split over several wavefronts per i-cluster to one wavefront per
+ * i-cluster: in a batched launch the replicas fill the GPU, and unsplit
+ * regions give the force kernel full work items.
  * nb_batch_capture_cycle captures one rebuild followed by nsteps batched force
  * evaluations as a single graph, replayed with nb_batch_replay.
  */

@@ -713,6 +713,21 @@ int nb_batch_bind_topology(nb_batch *b, const int *const *type, const int *const
     b->type.assign(type, type + b->n_rep);
     b->excl_off.assign(excl_off, excl_off + b->n_rep);
     b->excl_idx.assign(excl_idx, excl_idx + b->n_rep);
+    // In one batched launch the replicas themselves fill the GPU: size every
+    // list for one search wavefront per i-cluster, so that its work items
+    // hold full runs of entries (several search parts would cut them short).
+    nb_ctx *c = b->ctx;
+    MXN_HIP(hipSetDevice(c->device));
+    const int saved = c->search_parts;
+    c->search_parts = 1;
+    int rc = NB_OK;
+    for (int r = 0; r < b->n_rep && rc == NB_OK; ++r) {
+        nb_list *l = b->lists[r];
+        if (l->resv_parts != 1 || l->resv_nci != b->grids[r]->slots_cap / b->grids[r]->m)
+            rc = launch_pairlist(l, excl_off[r], excl_idx[r], true, false);
+    }
+    c->search_parts = saved;
+    CHECK(rc);
     b->topology = true;
     return NB_OK;
 }
