@@ -19,7 +19,9 @@ VALU count of the built 8x8 force+energy kernel, FMA = 2) + 8 per listed pair
 beyond rc (distance and cut-off test), divided by the force kernel's average
 duration from HIP events on the library stream; peak = 157.3 TFLOP/s
 (MI355X FP32 vector, 256 CUs x 2.4 GHz, counting packed FP32; the non-packed
-ceiling this build can reach is half of it).
+ceiling this build can reach is half of it).  roofline.traffic = measured HBM
+bytes per force-kernel launch (scaled FETCH_SIZE + WRITE_SIZE counters, see
+FORCE_TRAFFIC), null once the kernel sources differ from the profiled ones.
 """
 import argparse
 import json
@@ -34,7 +36,30 @@ if ROOT not in sys.path:
 FLOPS_PER_PAIR = 69          # FP32 flops of one in-range pair evaluation (8x8 force+energy kernel)
 FLOPS_PER_DISTANCE = 8       # FP32 flops of the distance and cut-off test of a listed pair
 PEAK_FP32 = 157.3e12
+# HBM traffic of one force-kernel launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device-to-device copy
+# (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid only for the kernel sources the counters were taken on.
+FORCE_TRAFFIC = {"sources_sha1": "c4116c53be723f03cb7ae794c654f006d4c87e46", "fetch_kib": 11412.04,
+                 "write_kib": 126621.10, "fetch_scale": 2.0, "write_scale": 1.0}
+FORCE_SOURCES = ("paper_1306_1737_amd/csrc/forces.hip", "paper_1306_1737_amd/csrc/devptr.h",
+                 "paper_1306_1737_amd/csrc/ewald_fit.h")
 METRIC = "atom-pair interactions/s (FP32, ≤1e-5 rel force err) + % FP32 VALU peak"
+
+
+def force_traffic_bytes():
+    """Measured bytes per force-kernel launch, or None once the kernel sources changed since."""
+    import hashlib
+    h = hashlib.sha1()
+    try:
+        for f in FORCE_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    if h.hexdigest() != FORCE_TRAFFIC["sources_sha1"]:
+        return None
+    t = FORCE_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
 def cpu_baseline(box, w):
@@ -259,7 +284,7 @@ def main():
                    "rlist": w.rlist, "beta": w.beta, "nstlist": w.nstlist, "energies": "every step",
                    "force_calls_per_step": calls, "force_kernel": args.variant, "list_order": args.list_order},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None},
+                     "frac": achieved / PEAK_FP32, "traffic": force_traffic_bytes()},
         "effective_pairs_per_s": eff,
         "pct_fp32_valu_peak": 100.0 * achieved / PEAK_FP32,
         "pairs_per_force_call": {"listed": listed, "real": real, "within_rc": inr, "excluded_within_rc": exc,
