@@ -54,7 +54,8 @@ typedef struct nb_mlp nb_mlp;
 typedef struct nb_batch nb_batch;
 
 /* Cluster shape M x N: i-clusters of M particles against j-clusters of N
- * particles (Sec. 2.2 "The M x N algorithm").  Supported: 4x4, 4x8, 8x8. */
+ * particles (Sec. 2.2 "The M x N algorithm").  Supported: 4x4, 4x8, 8x4 (the
+ * paper's GPU shape: i-clusters are pairs of 4-clusters), 8x8. */
 typedef struct { int m, n; } nb_shape;
 
 /* Interaction parameters (Sec. 3.2 "Pair interaction functions", Eq. 1 and 2).
@@ -353,7 +354,8 @@ int nb_buffer_estimate(nb_ctx *ctx, const nb_buffer_query *q, int mode, double *
  * 8 features: temperature (K), mass-weighted displacement width
  * sqrt(kB T t^2 <1/m>) (nm, t = (nstlist-1) dt), list lifetime (steps), mass
  * density (g/cm^3), cut-off (nm), and the cluster shape one-hot
- * (4x4, 4x8, 8x8).  It is trained on labels from nb_recount (the paper's
+ * (4x4, 4x8, 8x8; other shapes take the analytic bound).  It is trained on
+ * labels from nb_recount (the paper's
  * drift criterion evaluated exactly, Sec. 5).  Architecture 8-64-64-1, tanh
  * hidden layers, softplus output, MSE loss, Adam (beta1 0.9, beta2 0.999,
  * eps 1e-8); features are normalised to [-1, 1] with the ranges lo/hi given

@@ -1,7 +1,7 @@
 """Autotuner for batched replicas: cluster shape x work items per workgroup.
 
 For a set of replica boxes it builds the grids and lists of every candidate
-cluster shape (4x4, 4x8, 8x8; the paper tunes M and N to the hardware,
+cluster shape (4x4, 4x8, 8x4, 8x8; the paper tunes M and N to the hardware,
 Sec. 2.2 and 3.1), binds them to one batch and times the batched force
 launch with 1, 2, 4 and 8 work items (wavefronts) per workgroup.  The fastest pair is
 cached in a JSON file keyed by device, number of replicas, total size
@@ -20,7 +20,7 @@ import numpy as np
 import synth
 import paper_1306_1737_amd as mxn
 
-SHAPES = [(4, 4), (4, 8), (8, 8)]
+SHAPES = [(4, 4), (4, 8), (8, 4), (8, 8)]
 GROUPS = [1, 2, 4, 8]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mxn_autotune.json")
 

@@ -148,7 +148,7 @@ int nb_sync(nb_ctx *c) {
 static void grid_release(nb_grid *g) {
     DevBuf *bufs[] = {&g->col_count, &g->col_start, &g->col_fill, &g->colbb, &g->col_hist, &g->atom_col, &g->atom_xw,
                       &g->atom_img, &g->bucket, &g->xs, &g->xs_now, &g->type_s, &g->perm, &g->img_s,
-                      &g->slot_of, &g->bbi_lo, &g->bbi_hi, &g->bbj_lo, &g->bbj_hi, &g->nslots, &g->fs,
+                      &g->slot_of, &g->bbi_lo, &g->bbi_hi, &g->bbj_lo, &g->bbj_hi, &g->nslots,
                       &g->shiftvec};
     for (DevBuf *b : bufs) release(*b);
 }
@@ -158,8 +158,8 @@ int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const
     if (!c || !box || !xyzq || !type || !grid) return fail(NB_ERR_ARG, "nb_grid_sort: null argument");
     if (n < 1) return fail(NB_ERR_ARG, "nb_grid_sort: n must be >= 1");
     const bool ok_shape = (shape.m == 4 && shape.n == 4) || (shape.m == 4 && shape.n == 8) ||
-                          (shape.m == 8 && shape.n == 8);
-    if (!ok_shape) return fail(NB_ERR_ARG, "nb_grid_sort: supported shapes are 4x4, 4x8, 8x8");
+                          (shape.m == 8 && shape.n == 4) || (shape.m == 8 && shape.n == 8);
+    if (!ok_shape) return fail(NB_ERR_ARG, "nb_grid_sort: supported shapes are 4x4, 4x8, 8x4, 8x8");
     for (int d = 0; d < 3; ++d)
         if (!(box[d] > 0.0) || !std::isfinite(box[d])) return fail(NB_ERR_ARG, "nb_grid_sort: bad box");
     MXN_HIP(hipSetDevice(c->device));
@@ -221,7 +221,6 @@ int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const
         rc = rc ? rc : ensure(g->bbj_hi, ns / g->nn * 16);
     }
     rc = rc ? rc : ensure(g->nslots, 16);
-    rc = rc ? rc : ensure(g->fs, ns * 3 * 4);
     rc = rc ? rc : ensure(g->shiftvec, 32 * 16);
     if (rc == NB_OK) {
         ScopedTimer tm(c, NB_TIMER_GRID_SORT);
@@ -309,8 +308,9 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 // ------------------------------------------------------------------- list
 
 static void list_release(nb_list *l) {
-    DevBuf *bufs[] = {&l->entries,    &l->entries_canon, &l->keys,        &l->items,
-                      &l->part_count, &l->part_start,    &l->part_istart, &l->totals};
+    DevBuf *bufs[] = {&l->entries,    &l->entries_canon, &l->keys,        &l->items,  &l->part_count,
+                      &l->part_start, &l->part_istart,   &l->totals,      &l->jcount, &l->jstart,
+                      &l->jtmp,       &l->jidx,          &l->fj,          &l->fi};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -740,7 +740,7 @@ static int rebuild_refresh(nb_batch *b) {
     const size_t gs = grid_job_size(), ls = list_job_size();
     const int GS = grid_job_stages(), LS = list_job_stages();
     std::vector<char> gj(gs * n), lj(ls * n);
-    std::vector<ScanJob> sj(n);
+    std::vector<ScanJob> sj(2 * n);   // item offsets, then j-cluster view offsets
     std::vector<int> goff(GS * (n + 1)), loff(LS * (n + 1)), gtot(GS, 0), ltot(LS, 0), gb(GS), lb(LS);
     int max_ncol = 1;
     for (int r = 0; r < n; ++r) {
@@ -750,7 +750,7 @@ static int rebuild_refresh(nb_batch *b) {
         if (l->resv_parts == 0 || l->resv_nci != g->slots_cap / g->m || l->grid != g)
             return fail(NB_ERR_STATE, "nb_batch_rebuild: every replica's list needs a synchronous build on its grid");
         fill_grid_job(gj.data() + gs * r, g, b->xyzq[r], b->type[r]);
-        fill_list_job(lj.data() + ls * r, l, b->excl_off[r], b->excl_idx[r], &sj[r]);
+        fill_list_job(lj.data() + ls * r, l, b->excl_off[r], b->excl_idx[r], &sj[r], &sj[n + r]);
         grid_job_blocks(g, gb.data());
         list_job_blocks(l, lb.data());
         for (int k = 0; k < GS; ++k) {

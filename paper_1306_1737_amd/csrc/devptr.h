@@ -31,6 +31,14 @@ __device__ inline nb_jentry ld(gptr<const nb_jentry> p) {
     const int4 t = ld((gptr<const int4>)p);
     return nb_jentry{t.x, t.y, (uint32_t)t.z, (uint32_t)t.w};
 }
+__device__ inline void st(float4 *p, const float4 &v) { *p = v; }
+__device__ inline void st(gptr<float4> p, const float4 &v) {
+    const gptr<float> q = (gptr<float>)p;
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+}
 __device__ inline void st(nb_jentry *p, const nb_jentry &v) { *p = v; }
 __device__ inline void st(gptr<nb_jentry> p, const nb_jentry &v) {
     const gptr<int> q = (gptr<int>)p;

@@ -8,10 +8,14 @@
 // one entry (64/N entries per pass) and loops over the M i-particles, so each
 // lane evaluates M pair interactions per pass with no cross-lane traffic:
 // j-forces stay in the lane and are added to memory once per entry with
-// coalesced atomics (the N lanes of an entry cover N consecutive slots);
-// i-forces stay in registers for the whole item and are reduced across the
-// wavefront once at its end.  The image shift is applied to the j-particle,
-// so entries of different shifts can share a pass.
+// one coalesced store per entry into a per-entry buffer (the N lanes of an
+// entry cover N consecutive float4); i-forces stay in registers for the whole
+// item, are reduced across the wavefront once at its end and stored per item.
+// A second kernel sums each cluster's stored j- and i-forces in a fixed order
+// and writes them in input order, so no force goes through an atomic and the
+// forces of a given list and positions are reproducible bit for bit.  The
+// image shift is applied to the j-particle, so entries of different shifts
+// can share a pass.
 //
 // Pair math (FP32): r^-1 from the hardware reciprocal square root;
 // exp(-beta^2 r^2) from the hardware exp2; erfc(beta r) = exp(-beta^2 r^2) *
@@ -36,18 +40,17 @@ using mxn::ld;
 struct SysView {
     gptr<const float4> xs_now;
     gptr<const int> type_s;
-    gptr<float> fs;
-    int slots_cap;
+    gptr<float4> fj, fi;   // j-forces per (entry, j-particle), i-forces per (item, i-particle)
     gptr<const int4> items;
     gptr<const nb_jentry> entries;
     gptr<double> partials;
     long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
 };
 
-__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fs, int slots_cap,
+__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float4 *fj, float4 *fi,
                                     const int4 *items, const nb_jentry *entries, double *partials, long pstride,
                                     long pbase) {
-    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float>)fs, slots_cap,
+    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float4>)fj, (gptr<float4>)fi,
                    (gptr<const int4>)items, (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
 }
 
@@ -55,8 +58,10 @@ struct ForceArgs {
     const int *nslots, *perm, *img_s, *slot_of, *type_s;
     const float4 *xyzq_now;
     float4 *xs_now;
-    float *fs;
-    int slots_cap, n;
+    float4 *fj, *fi;   // per-entry j-forces, per-item i-forces
+    const int *jstart, *jidx, *part_istart;   // j-cluster view; first item of each region
+    int parts;         // regions per i-cluster
+    int n;
     const int4 *items;
     const nb_jentry *entries;
     const int *totals;
@@ -85,22 +90,6 @@ __global__ void k_gather(ForceArgs a) {
         p.z -= (float)(((im >> 20) & 1023) - 512) * a.Lz;
         a.xs_now[s] = p;
     }
-    a.fs[s] = 0.0f;
-    a.fs[a.slots_cap + s] = 0.0f;
-    a.fs[2 * a.slots_cap + s] = 0.0f;
-}
-
-__global__ void k_scatter(ForceArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const int s = a.slot_of[i];
-    float fx = a.fs[s], fy = a.fs[a.slots_cap + s], fz = a.fs[2 * a.slots_cap + s];
-    if (a.accumulate) {
-        fx += a.f_out[3 * i]; fy += a.f_out[3 * i + 1]; fz += a.f_out[3 * i + 2];
-    }
-    a.f_out[3 * i] = fx;
-    a.f_out[3 * i + 1] = fy;
-    a.f_out[3 * i + 2] = fz;
 }
 
 template <class T>
@@ -273,11 +262,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
             elj += (acc_t)el;
             ec += (acc_t)ecl;
         }
-        if (valid) {
-            unsafeAtomicAdd((float *)(v.fs + jslot), fjx);
-            unsafeAtomicAdd((float *)(v.fs + v.slots_cap + jslot), fjy);
-            unsafeAtomicAdd((float *)(v.fs + 2 * v.slots_cap + jslot), fjz);
-        }
+        if (valid) mxn::st(v.fj + (long)e * N + jb, make_float4(fjx, fjy, fjz, 0.0f));
         if (VIR) {
             vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
             vir[3] += (acc_t)(yj * fjx); vir[4] += (acc_t)(yj * fjy); vir[5] += (acc_t)(yj * fjz);
@@ -292,10 +277,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
     for (int k = 0; k < M; ++k) {
         const float fx = wave_sum_dpp(fix[k]), fy = wave_sum_dpp(fiy[k]), fz = wave_sum_dpp(fiz[k]);
         if (lane == 63) {
-            const int s = ci * M + k;
-            unsafeAtomicAdd((float *)(v.fs + s), fx);
-            unsafeAtomicAdd((float *)(v.fs + v.slots_cap + s), fy);
-            unsafeAtomicAdd((float *)(v.fs + 2 * v.slots_cap + s), fz);
+            mxn::st(v.fi + (long)item * M + k, make_float4(fx, fy, fz, 0.0f));
             if (VIR) {
                 viri[0] += (acc_t)xi[k] * (acc_t)fx; viri[1] += (acc_t)xi[k] * (acc_t)fy; viri[2] += (acc_t)xi[k] * (acc_t)fz;
                 viri[3] += (acc_t)yi[k] * (acc_t)fx; viri[4] += (acc_t)yi[k] * (acc_t)fy; viri[5] += (acc_t)yi[k] * (acc_t)fz;
@@ -328,7 +310,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const long item = xcd_item(total, 4, threadIdx.x >> 6);
     if (item < 0) return;
-    const SysView v = make_view(a.xs_now, a.type_s, a.fs, a.slots_cap, a.items, a.entries, a.partials, a.pstride, 0);
+    const SysView v = make_view(a.xs_now, a.type_s, a.fj, a.fi, a.items, a.entries, a.partials, a.pstride, 0);
     force_item<M, N, ENER, VIR, ACC64>(a, v, ljt, svec, (int)item, lane);
 }
 
@@ -363,6 +345,82 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *partials, long ps
         if (k < 2) energy[k] = (double)red[0];
         else virial[k - 2] = (double)red[0];
     }
+}
+
+// Forces of one j-cluster's N slots: the j-forces its entries stored, taken
+// in the j-cluster view's order, plus the i-forces stored by the work items
+// of the i-cluster(s) holding these slots; written to the caller's array in
+// input order (or added to it).  One wavefront per j-cluster, lane = (group
+// g, j-particle b): the 64/N groups take every (64/N)-th entry and item,
+// four entries in flight per lane, and a fixed butterfly sums the groups.
+// After an overflowed build (no usable items) every force is zero.
+struct FoldView {
+    gptr<const int> nslots, perm, totals, jstart, jidx, part_istart;
+    gptr<const float4> fj, fi;
+    float *f_out;
+    int parts, accumulate;
+};
+
+template <int M, int N>
+__device__ inline void fold_body(const FoldView &v, int cj, int lane) {
+    constexpr int G = 64 / N;
+    cj = __builtin_amdgcn_readfirstlane(cj);   // wave-uniform: scalar loads of the run bounds
+    if (cj >= *v.nslots / N) return;
+    const int b = lane % N, g = lane / N, s = cj * N + b;
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    if (v.totals[2] > 0) {
+        const int k1 = v.jstart[cj + 1];
+        for (int k0 = v.jstart[cj] + g; k0 < k1; k0 += 4 * G) {
+            // all four loads issued before any is used: a run's tail re-reads
+            // position k0 (valid) and drops the value
+            int e[4];
+            float4 f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) e[u] = v.jidx[k0 + u * G < k1 ? k0 + u * G : k0];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) f[u] = ld(v.fj + (long)e[u] * N + b);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k0 + u * G < k1;
+                fx += ok ? f[u].x : 0.0f;
+                fy += ok ? f[u].y : 0.0f;
+                fz += ok ? f[u].z : 0.0f;
+            }
+        }
+        const int ci = s / M, o = s % M;
+        const int t1 = v.part_istart[(ci + 1) * v.parts];
+        for (int t = v.part_istart[ci * v.parts] + g; t < t1; t += G) {
+            const float4 f = ld(v.fi + (long)t * M + o);
+            fx += f.x; fy += f.y; fz += f.z;
+        }
+    }
+#pragma unroll
+    for (int o = N; o < 64; o <<= 1) {
+        fx += __shfl_xor(fx, o, 64);
+        fy += __shfl_xor(fy, o, 64);
+        fz += __shfl_xor(fz, o, 64);
+    }
+    if (g == 0) {
+        const int at = v.perm[s];
+        if (at >= 0) {
+            float *out = v.f_out + 3 * (long)at;
+            if (v.accumulate) {
+                fx += out[0]; fy += out[1]; fz += out[2];
+            }
+            out[0] = fx;
+            out[1] = fy;
+            out[2] = fz;
+        }
+    }
+}
+
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_fold(ForceArgs a) {
+    const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,        (gptr<const int>)a.totals,
+                     (gptr<const int>)a.jstart, (gptr<const int>)a.jidx,        (gptr<const int>)a.part_istart,
+                     (gptr<const float4>)a.fj,  (gptr<const float4>)a.fi,       a.f_out,
+                     a.parts,                   a.accumulate};
+    fold_body<M, N>(v, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // Pair statistics of a list at the current positions (the paper's effective
@@ -425,7 +483,7 @@ __device__ inline int lane_rank(unsigned long long bal) {
 
 template <int N>
 constexpr int wave_lds_bytes() {
-    return mxn::kItemEntries * N * 32 + 128 * 4;
+    return mxn::item_entries(N) * N * 32 + 128 * 4;
 }
 
 // Compacted variant (default).  A wavefront stages its work item's j-particles
@@ -435,13 +493,13 @@ constexpr int wave_lds_bytes() {
 // interactions only in full (or final partial) 64-lane passes: the i-force
 // stays in registers (one i-particle per pass), the j-forces go to per-slot
 // LDS accumulators that are conflict-free within a pass, and at the end each
-// j-slot adds its force to memory once with a coalesced atomic.  Compared with
+// j-slot stores its force into the per-entry buffer (coalesced).  Compared with
 // evaluating every listed pair in lock-step, this skips the pairs beyond rc
 // (about two thirds of an 8x8 list at rlist = rc + 0.1 nm) at the cost of LDS
 // staging.
 template <int M, int N, bool ENER, bool VIR, bool ACC64>
 __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
-    constexpr int JMAX = mxn::kItemEntries * N;
+    constexpr int JMAX = mxn::item_entries(N) * N;
     constexpr unsigned FULL = (1u << M) - 1u;
     const long total = a.totals[2];
     if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
@@ -577,10 +635,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         fy = wave_sum(fy);
         fz = wave_sum(fz);
         if (lane == 0) {
-            const int s = ci * M + k;
-            unsafeAtomicAdd(a.fs + s, fx);
-            unsafeAtomicAdd(a.fs + a.slots_cap + s, fy);
-            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + s, fz);
+            a.fi[item * M + k] = make_float4(fx, fy, fz, 0.0f);
             if (VIR) {
                 viri[0] += (acc_t)pik.x * (acc_t)fx; viri[1] += (acc_t)pik.x * (acc_t)fy; viri[2] += (acc_t)pik.x * (acc_t)fz;
                 viri[3] += (acc_t)pik.y * (acc_t)fx; viri[4] += (acc_t)pik.y * (acc_t)fy; viri[5] += (acc_t)pik.y * (acc_t)fz;
@@ -593,19 +648,15 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         }
     }
 
-    // j-forces: one coalesced atomic per slot that received any interaction
+    // j-forces: one coalesced store per slot (zero where nothing interacted)
     acc_t vir[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) vir[k] = 0;
     for (int base = 0; base < nslot; base += 64) {
         const int jidx = base + lane;
-        if (jidx < nslot && (jinfo[jidx] >> 16)) {
-            const nb_jentry en = a.entries[js + jidx / N];
-            const int jslot = en.cj * N + (jidx % N);
+        if (jidx < nslot) {
             const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
-            unsafeAtomicAdd(a.fs + jslot, gx);
-            unsafeAtomicAdd(a.fs + a.slots_cap + jslot, gy);
-            unsafeAtomicAdd(a.fs + 2 * a.slots_cap + jslot, gz);
+            a.fj[(long)js * N + jidx] = make_float4(gx, gy, gz, 0.0f);
             if (VIR) {
                 const float4 pj = jd[jidx];
                 vir[0] += (acc_t)(pj.x * gx); vir[1] += (acc_t)(pj.x * gy); vir[2] += (acc_t)(pj.x * gz);
@@ -658,8 +709,9 @@ struct RepDesc {
     float *f_out;
     float4 *xs_now;
     const int *type_s, *perm, *img_s, *slot_of, *nslots;
-    float *fs;
-    int slots_cap, n;
+    float4 *fj, *fi;
+    const int *jstart, *jidx, *part_istart;
+    int parts, n;
     const int4 *items;
     const nb_jentry *entries;
     const int *totals;
@@ -732,9 +784,6 @@ __global__ void k_batch_gather(BatchArgs b) {
         p.z -= (float)(((im >> 20) & 1023) - 512) * d.Lz;
         d.xs_now[s] = p;
     }
-    d.fs[s] = 0.0f;
-    d.fs[d.slots_cap + s] = 0.0f;
-    d.fs[2 * d.slots_cap + s] = 0.0f;
 }
 
 // One launch over the concatenated work items of all replicas, one
@@ -752,25 +801,23 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     if (idx < 0) return;
     const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
     const RepDesc &d = b.rep[r];
-    const SysView v = make_view(d.xs_now, d.type_s, d.fs, d.slots_cap, d.items, d.entries, b.partials, b.pstride,
-                                d.pbase);
+    const SysView v = make_view(d.xs_now, d.type_s, d.fj, d.fi, d.items, d.entries, b.partials, b.pstride, d.pbase);
     force_item<M, N, ENER, VIR, true>(a, v, ljt, d.shiftvec, (int)(idx - b.item_off[r]), lane);
 }
 
-__global__ void k_batch_scatter(BatchArgs b) {
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= b.atom_off[b.n_rep]) return;
-    const int r = find_rep(b.atom_off, b.n_rep, g);
+// one wavefront per j-cluster of every replica (the replicas' slot capacities
+// are multiples of N, so wavefront w covers global slots w*N .. w*N + N - 1)
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
+    const long g0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * N;
+    if (g0 >= b.slot_off[b.n_rep]) return;
+    const int r = find_rep(b.slot_off, b.n_rep, g0);
     const RepDesc &d = b.rep[r];
-    const int i = (int)(g - b.atom_off[r]);
-    const int s = d.slot_of[i];
-    float fx = d.fs[s], fy = d.fs[d.slots_cap + s], fz = d.fs[2 * d.slots_cap + s];
-    if (b.accumulate) {
-        fx += d.f_out[3 * i]; fy += d.f_out[3 * i + 1]; fz += d.f_out[3 * i + 2];
-    }
-    d.f_out[3 * i] = fx;
-    d.f_out[3 * i + 1] = fy;
-    d.f_out[3 * i + 2] = fz;
+    const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,        (gptr<const int>)d.totals,
+                     (gptr<const int>)d.jstart, (gptr<const int>)d.jidx,        (gptr<const int>)d.part_istart,
+                     (gptr<const float4>)d.fj,  (gptr<const float4>)d.fi,       d.f_out,
+                     d.parts,                   b.accumulate};
+    fold_body<M, N>(v, (int)((g0 - b.slot_off[r]) / N), threadIdx.x & 63);
 }
 
 // one workgroup per replica: its energies (and virial) from the per-item partials, in a fixed order
@@ -826,8 +873,6 @@ int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now) {
     a.img_s = (const int *)g->img_s.p;
     a.xyzq_now = (const float4 *)xyzq_now;
     a.xs_now = (float4 *)g->xs_now.p;
-    a.fs = (float *)g->fs.p;
-    a.slots_cap = g->slots_cap;
     a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
     a.flags = ctx->d_flags;
     k_gather<<<(g->slots_cap + 255) / 256, 256, 0, ctx->stream>>>(a);
@@ -846,8 +891,6 @@ int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *x
     a.type_s = (const int *)g->type_s.p;
     a.xyzq_now = (const float4 *)xyzq_now;
     a.xs_now = (float4 *)g->xs_now.p;
-    a.fs = (float *)g->fs.p;
-    a.slots_cap = g->slots_cap;
     a.n = g->n;
     a.items = (const int4 *)l->items.p;
     a.entries = (const nb_jentry *)l->entries.p;
@@ -860,6 +903,7 @@ int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *x
     const int nb = (int)((l->cap_items + 3) / 4) + 1;
     if (g->m == 4 && g->nn == 4) k_stats<4, 4><<<nb, 256, 0, st>>>(a, d_counts);
     else if (g->m == 4 && g->nn == 8) k_stats<4, 8><<<nb, 256, 0, st>>>(a, d_counts);
+    else if (g->m == 8 && g->nn == 4) k_stats<8, 4><<<nb, 256, 0, st>>>(a, d_counts);
     else k_stats<8, 8><<<nb, 256, 0, st>>>(a, d_counts);
     MXN_HIP(hipGetLastError());
     return NB_OK;
@@ -882,8 +926,12 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.type_s = (const int *)g->type_s.p;
     a.xyzq_now = (const float4 *)xyzq_now;
     a.xs_now = (float4 *)g->xs_now.p;
-    a.fs = (float *)g->fs.p;
-    a.slots_cap = g->slots_cap;
+    a.fj = (float4 *)l->fj.p;
+    a.fi = (float4 *)l->fi.p;
+    a.jstart = (const int *)l->jstart.p;
+    a.jidx = (const int *)l->jidx.p;
+    a.part_istart = (const int *)l->part_istart.p;
+    a.parts = l->resv_parts;
     a.n = g->n;
     a.items = (const int4 *)l->items.p;
     a.entries = (const nb_jentry *)l->entries.p;
@@ -916,9 +964,14 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         const int var = ctx->force_variant;
         if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, var, st);
         else if (g->m == 4 && g->nn == 8) launch_shape<4, 8>(a, flags, nb, lds, var, st);
+        else if (g->m == 8 && g->nn == 4) launch_shape<8, 4>(a, flags, nb, lds, var, st);
         else launch_shape<8, 8>(a, flags, nb, lds, var, st);
     }
-    k_scatter<<<(g->n + 255) / 256, 256, 0, st>>>(a);
+    const int nfold = (g->slots_cap / g->nn + 3) / 4;
+    if (g->m == 4 && g->nn == 4) k_fold<4, 4><<<nfold, 256, 0, st>>>(a);
+    else if (g->m == 4 && g->nn == 8) k_fold<4, 8><<<nfold, 256, 0, st>>>(a);
+    else if (g->m == 8 && g->nn == 4) k_fold<8, 4><<<nfold, 256, 0, st>>>(a);
+    else k_fold<8, 8><<<nfold, 256, 0, st>>>(a);
     if (need_acc) {
         if (flags & NB_ACC_FP32)
             k_reduce<false><<<kNAcc, 1024, 0, st>>>(a.partials, pstride, a.totals, energy, virial, flags & NB_ENERGY,
@@ -965,9 +1018,14 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
         if (bt->m == 4 && bt->nn == 4) launch_batch_shape<4, 4>(a, b, flags, bt->pstride, lds, st);
         else if (bt->m == 4 && bt->nn == 8) launch_batch_shape<4, 8>(a, b, flags, bt->pstride, lds, st);
+        else if (bt->m == 8 && bt->nn == 4) launch_batch_shape<8, 4>(a, b, flags, bt->pstride, lds, st);
         else launch_batch_shape<8, 8>(a, b, flags, bt->pstride, lds, st);
     }
-    k_batch_scatter<<<(int)((bt->total_atoms + 255) / 256), 256, 0, st>>>(b);
+    const int nfold = (int)((bt->total_slots / bt->nn + 3) / 4);
+    if (bt->m == 4 && bt->nn == 4) k_batch_fold<4, 4><<<nfold, 256, 0, st>>>(b);
+    else if (bt->m == 4 && bt->nn == 8) k_batch_fold<4, 8><<<nfold, 256, 0, st>>>(b);
+    else if (bt->m == 8 && bt->nn == 4) k_batch_fold<8, 4><<<nfold, 256, 0, st>>>(b);
+    else k_batch_fold<8, 8><<<nfold, 256, 0, st>>>(b);
     if (flags & (NB_ENERGY | NB_VIRIAL))
         k_batch_reduce<<<bt->n_rep, 256, 0, st>>>(b, (flags & NB_ENERGY) != 0, (flags & NB_VIRIAL) != 0);
     MXN_HIP(hipGetLastError());
@@ -986,8 +1044,12 @@ void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *x
     d.img_s = (const int *)g->img_s.p;
     d.slot_of = (const int *)g->slot_of.p;
     d.nslots = (const int *)g->nslots.p;
-    d.fs = (float *)g->fs.p;
-    d.slots_cap = g->slots_cap;
+    d.fj = (float4 *)l->fj.p;
+    d.fi = (float4 *)l->fi.p;
+    d.jstart = (const int *)l->jstart.p;
+    d.jidx = (const int *)l->jidx.p;
+    d.part_istart = (const int *)l->part_istart.p;
+    d.parts = l->resv_parts;
     d.n = g->n;
     d.items = (const int4 *)l->items.p;
     d.entries = (const nb_jentry *)l->entries.p;

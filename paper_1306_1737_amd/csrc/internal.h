@@ -29,7 +29,8 @@ int fail(int status, const std::string &msg);
 enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2 };
 
 // work items of the force kernel hold at most this many j-entries of one i-cluster
-constexpr int kItemEntries = 32;
+// Entries per force work item: four wavefront passes of 64/N entries each.
+constexpr int item_entries(int n) { return 256 / n; }
 constexpr int kHistAtoms = 4096;         // particles per workgroup in the column histogram
 constexpr int kMaxHistColumns = 16384;   // larger grids count columns with global atomics
 inline int hist_blocks(int n) { return n < 1 ? 1 : (n + kHistAtoms - 1) / kHistAtoms; }
@@ -87,7 +88,6 @@ struct nb_grid {
     mxn::DevBuf xs, xs_now, type_s, perm, img_s, slot_of;
     mxn::DevBuf bbi_lo, bbi_hi, bbj_lo, bbj_hi;
     mxn::DevBuf nslots;        // int on device
-    mxn::DevBuf fs;            // force accumulation, SoA [3][slots_cap]
     mxn::DevBuf shiftvec;      // 27 float4 image shift vectors
     long generation = 0;       // incremented by every sort; lists remember the one they were built on
 };
@@ -105,6 +105,13 @@ struct nb_list {
     mxn::DevBuf entries_canon, keys;   // fill-pass output before a distance sort, and its sort keys
     mxn::DevBuf part_count, part_start, part_istart;
     mxn::DevBuf totals;        // int[4]: entries, items, usable items (0 after an overflow), region overflow
+    // j-cluster view (per j-cluster: the positions of its entries, ascending),
+    // rebuilt with the list: counters (zero between builds), their exclusive
+    // scan, scatter output and the sorted runs
+    mxn::DevBuf jcount, jstart, jtmp, jidx;
+    // force-call buffers: float4 j-force per (entry position, j-particle) and
+    // i-force per (work item, i-particle), summed per cluster after the kernel
+    mxn::DevBuf fj, fi;
     int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
     int resv_nci = 0;          // i-cluster capacity of the reserved layout
     long last_entries = 0;     // host copy after a synchronous build
@@ -161,7 +168,8 @@ void grid_job_blocks(const nb_grid *g, int *blocks_per_stage);
 int launch_grid_sort_batch(hipStream_t st, const void *jobs, const int *off, int n_rep, const int *total, int max_ncol);
 size_t list_job_size();
 int list_job_stages();
-void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan);
+void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan,
+                   ScanJob *jscan);
 void list_job_blocks(const nb_list *l, int *blocks_per_stage);
 int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
                           const ScanJob *scans);

@@ -204,7 +204,13 @@ __device__ inline void search_body(const A &a, int blk) {
                         // only z gaps below sqrt(rlist^2 - g^2) can pass the box test
                         const float zr = sqrtf(a.rl2 - g2) + zmargin;
                         const int j0 = a.col_start[c] / N, j1 = a.col_start[c + 1] / N;
-                        k0 = lower_bound(j0, j1, [&](int k) { return ld(a.bbj_hi + k).z; }, slz - zr);
+                        // a j-cluster of padding only (a column's last one when N is below the
+                        // column granule) has an empty box, hi = -inf: it sorts as +inf, keeping
+                        // the key nondecreasing
+                        k0 = lower_bound(j0, j1, [&](int k) {
+                            const float4 h = ld(a.bbj_hi + k);
+                            return h.x == -INFINITY ? INFINITY : h.z;
+                        }, slz - zr);
                         const int k1 = lower_bound(k0, j1, [&](int k) { return ld(a.bbj_lo + k).z; }, shz + zr);
                         kc = k1 - k0;
                     }
@@ -324,25 +330,25 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
 }
 
 // Work items: each (i-cluster, part) region cut into runs of at most
-// kItemEntries entries, at the offsets of a scan over the regions' counts.
-__device__ inline void items_body(int nparts_total, int parts, const int *part_count, const int *part_start,
-                                  const int *part_istart, long cap_items, int4 *items, int blk) {
+// item_entries(N) entries, at the offsets of a scan over the regions' counts.
+__device__ inline void items_body(int nparts_total, int parts, int per_item, const int *part_count,
+                                  const int *part_start, const int *part_istart, long cap_items, int4 *items, int blk) {
     const int g = blk * blockDim.x + threadIdx.x;
     if (g >= nparts_total) return;
     const int resv = part_start[g + 1] - part_start[g];
     const int cnt = min(part_count[g], resv), start = part_start[g], ip = part_istart[g];
-    const int nit = (cnt + mxn::kItemEntries - 1) / mxn::kItemEntries;
+    const int nit = (cnt + per_item - 1) / per_item;
     for (int k = 0; k < nit; ++k) {
         if ((long)ip + k >= cap_items) return;   // overflow: latched by k_finalize
-        const int js = start + k * mxn::kItemEntries;
-        const int je = min(js + mxn::kItemEntries, start + cnt);
+        const int js = start + k * per_item;
+        const int je = min(js + per_item, start + cnt);
         items[ip + k] = make_int4(g / parts, js, je, 0);
     }
 }
 
-__global__ void k_items(int nparts_total, int parts, const int *part_count, const int *part_start,
+__global__ void k_items(int nparts_total, int parts, int per_item, const int *part_count, const int *part_start,
                         const int *part_istart, long cap_items, int4 *items) {
-    items_body(nparts_total, parts, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
+    items_body(nparts_total, parts, per_item, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
 }
 
 // Order the entries of each (i-cluster, part) region by bounding-box distance
@@ -403,6 +409,69 @@ __device__ inline void finalize_body(int *totals, long cap_items, int *flags) {
 __global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_body(totals, cap_items, flags); }
 
 // --------------------------------------------------------------------------
+// j-cluster view of a list: for every j-cluster, the positions of the entries
+// that name it, in increasing order.  The force kernels store each entry's
+// j-forces instead of adding them to memory with atomics; the reduction then
+// sums them per j-cluster in this fixed order.  Built after every list build:
+// a count per j-cluster over the usable items' entries, an exclusive scan, a
+// scatter that counts each j-cluster back down to zero (which leaves the
+// counters cleared for the next build), and a rank sort of each j-cluster's
+// run.
+struct JViewArgs {
+    const int *totals;   // [2]: usable items
+    const int4 *items;
+    const nb_jentry *entries;
+    int *jcount;         // j-cluster counters: zero between builds
+    const int *jstart;   // exclusive scan of the counts (njc + 1)
+    int *jtmp, *jidx;    // scatter output, and the sorted runs
+    int njc;             // j-clusters of the grid's capacity
+};
+
+constexpr int kJSortStage = 512;   // entries of a j-cluster's run sorted in LDS
+
+// one wavefront per work item, one lane per entry (items hold at most 64)
+__device__ inline void jcount_body(const JViewArgs &a, bool scatter, int blk) {
+    const int t = blk * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= a.totals[2]) return;
+    const int4 it = a.items[t];
+    const int e = it.y + lane;
+    if (e >= it.z) return;
+    const int cj = a.entries[e].cj;
+    if (!scatter) {
+        atomicAdd(a.jcount + cj, 1);
+    } else {
+        const int pos = atomicSub(a.jcount + cj, 1) - 1;
+        a.jtmp[a.jstart[cj] + pos] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_jcount(JViewArgs a, int scatter) { jcount_body(a, scatter != 0, blockIdx.x); }
+
+// one wavefront per j-cluster: rank sort of its run (the values are distinct)
+__device__ inline void jsort_body(const JViewArgs &a, int blk) {
+    __shared__ int sv[4][kJSortStage];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cj = blk * 4 + w;
+    if (cj >= a.njc) return;
+    if (lane == 0) a.jcount[cj] = 0;   // already zero after the scatter; kept clear regardless
+    const int b = a.jstart[cj], n = a.jstart[cj + 1] - b;
+    const bool staged = n <= kJSortStage;
+    if (staged)
+        for (int i = lane; i < n; i += 64) sv[w][i] = a.jtmp[b + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = lane; i < n; i += 64) {
+        const int v = staged ? sv[w][i] : a.jtmp[b + i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += (staged ? sv[w][j] : a.jtmp[b + j]) < v;
+        a.jidx[b + r] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_jsort(JViewArgs a) { jsort_body(a, blockIdx.x); }
+
+// --------------------------------------------------------------------------
 // Batched rebuild of many replicas' lists (the fill pass into the regions the
 // replicas' last synchronous builds sized), one launch per stage; a
 // workgroup finds its replica by binary search in the stage's prefix of
@@ -410,14 +479,15 @@ __global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_b
 
 struct ListJob {
     SearchArgs a;
-    int nregions;
+    JViewArgs jv;
+    int nregions, per_item;
     int *part_count, *part_start, *part_istart, *totals;
     int4 *items;
     long cap_items;
     int *flags;
 };
 
-enum { LS_SEARCH, LS_ITEMS, LS_NSTAGES };
+enum { LS_SEARCH, LS_ITEMS, LS_JITEMS, LS_JSORT, LS_NSTAGES };
 
 __device__ inline int job_of(const int *off, int n, int b) {
     int lo = 0, hi = n - 1;   // last r with off[r] <= b
@@ -438,13 +508,23 @@ __global__ __launch_bounds__(256) void kb_search(const ListJob *J, const int *of
 __global__ void kb_items(const ListJob *J, const int *off, int n) {
     const int r = job_of(off, n, blockIdx.x);
     const ListJob &j = J[r];
-    items_body(j.nregions, j.a.parts, j.part_count, j.part_start, j.part_istart, j.cap_items, j.items,
+    items_body(j.nregions, j.a.parts, j.per_item, j.part_count, j.part_start, j.part_istart, j.cap_items, j.items,
                blockIdx.x - off[r]);
 }
 
 __global__ void kb_finalize(const ListJob *J) {
     const ListJob &j = J[blockIdx.x];
     finalize_body(j.totals, j.cap_items, j.flags);
+}
+
+__global__ __launch_bounds__(256) void kb_jcount(const ListJob *J, const int *off, int n, int scatter) {
+    const int r = job_of(off, n, blockIdx.x);
+    jcount_body(J[r].jv, scatter != 0, blockIdx.x - off[r]);
+}
+
+__global__ __launch_bounds__(256) void kb_jsort(const ListJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    jsort_body(J[r].jv, blockIdx.x - off[r]);
 }
 
 template <int M, int N>
@@ -487,17 +567,33 @@ static SearchArgs make_search(const nb_list *l, const int *excl_off, const int *
     return a;
 }
 
+static JViewArgs make_jview(const nb_list *l) {
+    JViewArgs v{};
+    v.totals = (const int *)l->totals.p;
+    v.items = (const int4 *)l->items.p;
+    v.entries = (const nb_jentry *)l->entries.p;
+    v.jcount = (int *)l->jcount.p;
+    v.jstart = (const int *)l->jstart.p;
+    v.jtmp = (int *)l->jtmp.p;
+    v.jidx = (int *)l->jidx.p;
+    v.njc = l->grid->slots_cap / l->grid->nn;
+    return v;
+}
+
 size_t list_job_size() { return sizeof(ListJob); }
 int list_job_stages() { return LS_NSTAGES; }
 
 // The list must have been sized by a synchronous build for its grid's capacity.
-void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan) {
+void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_idx, ScanJob *scan,
+                   ScanJob *jscan) {
     ListJob j{};
     j.a = make_search(l, excl_off, excl_idx);
+    j.jv = make_jview(l);
     j.a.parts = l->resv_parts;
     j.a.entries = (nb_jentry *)l->entries.p;
     j.a.keys = nullptr;
     j.nregions = l->resv_nci * l->resv_parts;
+    j.per_item = item_entries(l->grid->nn);
     j.part_count = (int *)l->part_count.p;
     j.part_start = (int *)l->part_start.p;
     j.part_istart = (int *)l->part_istart.p;
@@ -506,13 +602,16 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.cap_items = l->cap_items;
     j.flags = l->ctx->d_flags;
     std::memcpy(out, &j, sizeof j);
-    *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, kItemEntries, j.totals + 1, j.totals};
+    *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, j.per_item, j.totals + 1, j.totals};
+    *jscan = ScanJob{j.jv.jcount, (int *)j.jv.jstart, j.jv.njc, 0, 1, nullptr, nullptr};
 }
 
 void list_job_blocks(const nb_list *l, int *blocks_per_stage) {
     const long nreg = (long)l->resv_nci * l->resv_parts;
     blocks_per_stage[LS_SEARCH] = (int)((nreg + 3) / 4);
     blocks_per_stage[LS_ITEMS] = (int)((nreg + 255) / 256);
+    blocks_per_stage[LS_JITEMS] = (int)((l->cap_items + 3) / 4);
+    blocks_per_stage[LS_JSORT] = (int)((l->grid->slots_cap / l->grid->nn + 3) / 4);
 }
 
 int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
@@ -521,10 +620,15 @@ int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const
     const int stride = n_rep + 1;
     if (m == 4 && nn == 4) kb_search<4, 4><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
     else if (m == 4 && nn == 8) kb_search<4, 8><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
+    else if (m == 8 && nn == 4) kb_search<8, 4><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
     else kb_search<8, 8><<<total[LS_SEARCH], 256, 0, st>>>(J, off + LS_SEARCH * stride, n_rep);
     launch_scan_batch(scans, n_rep, st);
     kb_items<<<total[LS_ITEMS], 256, 0, st>>>(J, off + LS_ITEMS * stride, n_rep);
     kb_finalize<<<n_rep, 64, 0, st>>>(J);
+    kb_jcount<<<total[LS_JITEMS], 256, 0, st>>>(J, off + LS_JITEMS * stride, n_rep, 0);
+    launch_scan_batch(scans + n_rep, n_rep, st);
+    kb_jcount<<<total[LS_JITEMS], 256, 0, st>>>(J, off + LS_JITEMS * stride, n_rep, 1);
+    kb_jsort<<<total[LS_JSORT], 256, 0, st>>>(J, off + LS_JSORT * stride, n_rep);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
@@ -559,6 +663,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     if (reserve) {
         if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, false, nblocks, st);
         else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, false, nblocks, st);
+        else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, false, nblocks, st);
         else run<8, 8>(l, a, false, nblocks, st);
         k_max_count<<<1, 1024, 0, st>>>((const int *)l->part_count.p, nregions, (int *)l->totals.p);
         MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -573,12 +678,22 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
             if (rc) return rc;
             l->cap_entries = ce;
         }
-        const long cit = ce / kItemEntries + nregions + 256;   // each region: at most count/32 + 1 items
+        const long cit = ce / item_entries(g->nn) + nregions + 256;   // each region: at most count/per-item + 1 items
         if (cit > l->cap_items) {
             int rc = ensure(l->items, (size_t)cit * sizeof(int4));
             if (rc) return rc;
             l->cap_items = cit;
         }
+        // j-cluster view and force-call buffers for this capacity; the counters start cleared
+        const long njc = g->slots_cap / g->nn;
+        int rc = ensure(l->jcount, (size_t)(njc + 1) * 4);
+        rc = rc ? rc : ensure(l->jstart, (size_t)(njc + 1) * 4);
+        rc = rc ? rc : ensure(l->jtmp, (size_t)l->cap_entries * 4);
+        rc = rc ? rc : ensure(l->jidx, (size_t)l->cap_entries * 4);
+        rc = rc ? rc : ensure(l->fj, (size_t)l->cap_entries * g->nn * 16);
+        rc = rc ? rc : ensure(l->fi, (size_t)l->cap_items * g->m * 16);
+        if (rc) return rc;
+        MXN_HIP(hipMemsetAsync(l->jcount.p, 0, (size_t)(njc + 1) * 4, st));
         k_region_starts<<<(nregions + 256) / 256, 256, 0, st>>>(nregions, (int)size, (int *)l->part_start.p);
         l->resv_parts = parts;
         l->resv_nci = nci_cap;
@@ -594,11 +709,12 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     a.keys = by_distance ? (float *)l->keys.p : nullptr;
     if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, true, nblocks, st);
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
+    else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
     // item offsets per region; totals[0] = entries found, totals[1] = items
-    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, kItemEntries,
+    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, item_entries(g->nn),
                      (int *)l->totals.p + 1, (int *)l->totals.p, st);
-    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, (const int *)l->part_count.p,
+    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, item_entries(g->nn), (const int *)l->part_count.p,
                                                   (const int *)l->part_start.p, (const int *)l->part_istart.p,
                                                   l->cap_items, (int4 *)l->items.p);
     if (by_distance)
@@ -606,6 +722,13 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
                                                 (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
                                                 (nb_jentry *)l->entries.p);
     k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, ctx->d_flags);
+    // the j-cluster view of the usable items' entries
+    const JViewArgs jv = make_jview(l);
+    const int nbi = (int)((l->cap_items + 3) / 4);
+    k_jcount<<<nbi, 256, 0, st>>>(jv, 0);
+    launch_scan(jv.jcount, (int *)jv.jstart, jv.njc, nullptr, st);
+    k_jcount<<<nbi, 256, 0, st>>>(jv, 1);
+    k_jsort<<<(jv.njc + 3) / 4, 256, 0, st>>>(jv);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }

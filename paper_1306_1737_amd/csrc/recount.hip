@@ -176,6 +176,7 @@ int launch_recount(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float 
     const size_t lds = (size_t)p->ntypes * p->ntypes * sizeof(float4);
     if (g->m == 4 && g->nn == 4) k_recount<4, 4><<<nb, 256, lds, st>>>(a);
     else if (g->m == 4 && g->nn == 8) k_recount<4, 8><<<nb, 256, lds, st>>>(a);
+    else if (g->m == 8 && g->nn == 4) k_recount<8, 4><<<nb, 256, lds, st>>>(a);
     else k_recount<8, 8><<<nb, 256, lds, st>>>(a);
     MXN_HIP(hipGetLastError());
     return NB_OK;

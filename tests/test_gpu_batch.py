@@ -110,7 +110,7 @@ def test_autotuner_choice_is_valid_and_cached(tmp_path):
         mxn.nb_destroy(ctx)
 
 
-@pytest.mark.parametrize("shape", [(4, 8), (8, 8)])
+@pytest.mark.parametrize("shape", [(4, 8), (8, 4), (8, 8)])
 def test_batched_rebuild_and_cycle_graph(shape):
     """After the particles move, one batched rebuild (grid sort + list of every replica, one launch per stage)
     gives each replica the list its own build gives (bit-exact; two replicas also against the oracle); a graph

@@ -17,7 +17,7 @@ def _announce(request):
     yield
 
 
-@pytest.mark.parametrize("shape", [(4, 4), (4, 8), (8, 8)])
+@pytest.mark.parametrize("shape", [(4, 4), (4, 8), (8, 4), (8, 8)])
 def test_recount_matches_oracle(shape):
     import torch
     import paper_1306_1737_amd as mxn

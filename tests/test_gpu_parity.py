@@ -15,7 +15,7 @@ from tests._nb import F, GpuSystem, default_rbb, rel_rms
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(4, 4), (4, 8), (8, 8)]
+SHAPES = [(4, 4), (4, 8), (8, 4), (8, 8)]
 
 
 @pytest.fixture(autouse=True)
@@ -79,8 +79,8 @@ def _cmp_lists(gpu, ref):
         np.testing.assert_array_equal(gpu[k], ref[k], err_msg=k)
 
 
-@pytest.mark.parametrize("shape,rlist", [((4, 4), 0.9), ((4, 8), 0.9), ((8, 8), 0.9), ((4, 4), 1.1), ((8, 8), 1.1),
-                                         ((4, 8), 1.2)])
+@pytest.mark.parametrize("shape,rlist", [((4, 4), 0.9), ((4, 8), 0.9), ((8, 4), 0.9), ((8, 8), 0.9), ((4, 4), 1.1),
+                                         ((8, 4), 1.1), ((8, 8), 1.1), ((4, 8), 1.2)])
 def test_pairlist_bitexact(c1, shape, rlist):
     rbb = np.float32(default_rbb(c1, shape, rlist))
     s = GpuSystem(c1, shape, rlist, rbb=float(rbb))

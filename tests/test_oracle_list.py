@@ -36,7 +36,7 @@ def _shift_vec(s, Lf):
 
 
 def test_grid_sort_invariants(c1):
-    for m, n in ((4, 4), (4, 8), (8, 8)):
+    for m, n in ((4, 4), (4, 8), (8, 4), (8, 8)):
         g = oracle.grid_sort(c1.xyz, c1.box, m, n)
         cmax = max(m, n)
         nx, ny = g["nx"], g["ny"]
@@ -110,7 +110,7 @@ def _expand(entries, m, n, perm, excluded_pairs):
     return full, corr
 
 
-@pytest.mark.parametrize("shape,rlist", [((4, 4), 0.9), ((4, 8), 1.0), ((8, 8), 1.1), ((8, 8), 0.9)])
+@pytest.mark.parametrize("shape,rlist", [((4, 4), 0.9), ((4, 8), 1.0), ((8, 4), 1.0), ((8, 8), 1.1), ((8, 8), 0.9)])
 def test_list_coverage(shape, rlist):
     # a smaller box keeps the brute-force pair enumeration quick; L = 2.47 nm > 2 rlist
     b = synth.water_box(500, 2.47, seed=11)
