@@ -310,7 +310,7 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 static void list_release(nb_list *l) {
     DevBuf *bufs[] = {&l->entries,    &l->entries_canon, &l->keys,        &l->items,  &l->part_count,
                       &l->part_start, &l->part_istart,   &l->totals,      &l->jcount, &l->jstart,
-                      &l->jtmp,       &l->jidx,          &l->fj,          &l->fi};
+                      &l->jrank,      &l->jrank_canon,   &l->fj,          &l->fi};
     for (DevBuf *b : bufs) release(*b);
 }
 

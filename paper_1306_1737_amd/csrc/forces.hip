@@ -8,14 +8,14 @@
 // one entry (64/N entries per pass) and loops over the M i-particles, so each
 // lane evaluates M pair interactions per pass with no cross-lane traffic:
 // j-forces stay in the lane and are added to memory once per entry with
-// one coalesced store per entry into a per-entry buffer (the N lanes of an
-// entry cover N consecutive float4); i-forces stay in registers for the whole
-// item, are reduced across the wavefront once at its end and stored per item.
-// A second kernel sums each cluster's stored j- and i-forces in a fixed order
-// and writes them in input order, so no force goes through an atomic and the
-// forces of a given list and positions are reproducible bit for bit.  The
-// image shift is applied to the j-particle, so entries of different shifts
-// can share a pass.
+// one store per entry into the entry's row of a buffer whose rows are grouped
+// by j-cluster (the N lanes of an entry write one 16N-byte row); i-forces stay
+// in registers for the whole item, are reduced across the wavefront once at
+// its end and stored per item.  A second kernel sums each cluster's stored j-
+// and i-forces in 64-bit fixed point (order-independent) and writes them in
+// input order, so no force goes through an atomic and the forces of a given
+// list and positions are reproducible bit for bit.  The image shift is
+// applied to the j-particle, so entries of different shifts can share a pass.
 //
 // Pair math (FP32): r^-1 from the hardware reciprocal square root;
 // exp(-beta^2 r^2) from the hardware exp2; erfc(beta r) = exp(-beta^2 r^2) *
@@ -40,26 +40,28 @@ using mxn::ld;
 struct SysView {
     gptr<const float4> xs_now;
     gptr<const int> type_s;
-    gptr<float4> fj, fi;   // j-forces per (entry, j-particle), i-forces per (item, i-particle)
+    gptr<float4> fj, fi;   // j-forces per (row, j-particle), i-forces per (item, i-particle)
+    gptr<const int> jpos;  // row of each entry position
     gptr<const int4> items;
     gptr<const nb_jentry> entries;
     gptr<double> partials;
     long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
 };
 
-__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float4 *fj, float4 *fi,
+__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float4 *fj, float4 *fi, const int *jpos,
                                     const int4 *items, const nb_jentry *entries, double *partials, long pstride,
                                     long pbase) {
-    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float4>)fj, (gptr<float4>)fi,
-                   (gptr<const int4>)items, (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
+    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float4>)fj,
+                   (gptr<float4>)fi,           (gptr<const int>)jpos,   (gptr<const int4>)items,
+                   (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
 }
 
 struct ForceArgs {
     const int *nslots, *perm, *img_s, *slot_of, *type_s;
     const float4 *xyzq_now;
     float4 *xs_now;
-    float4 *fj, *fi;   // per-entry j-forces, per-item i-forces
-    const int *jstart, *jidx, *part_istart;   // j-cluster view; first item of each region
+    float4 *fj, *fi;   // j-forces per (row, j-particle), i-forces per (item, i-particle)
+    const int *jstart, *jpos, *part_istart;   // first row of each j-cluster, row of each entry; first item of each region
     int parts;         // regions per i-cluster
     int n;
     const int4 *items;
@@ -239,6 +241,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         const int e = e0 + eo;
         const bool valid = e < je;
         const nb_jentry en = ld(v.entries + (valid ? e : e0));
+        const int row = v.jpos[valid ? e : e0];
         const int jslot = en.cj * N + jb;
         const float4 pj = ld(v.xs_now + jslot);
         const int tjr = v.type_s[jslot];
@@ -262,7 +265,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
             elj += (acc_t)el;
             ec += (acc_t)ecl;
         }
-        if (valid) mxn::st(v.fj + (long)e * N + jb, make_float4(fjx, fjy, fjz, 0.0f));
+        if (valid) mxn::st(v.fj + (long)row * N + jb, make_float4(fjx, fjy, fjz, 0.0f));
         if (VIR) {
             vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
             vir[3] += (acc_t)(yj * fjx); vir[4] += (acc_t)(yj * fjy); vir[5] += (acc_t)(yj * fjz);
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const long item = xcd_item(total, 4, threadIdx.x >> 6);
     if (item < 0) return;
-    const SysView v = make_view(a.xs_now, a.type_s, a.fj, a.fi, a.items, a.entries, a.partials, a.pstride, 0);
+    const SysView v = make_view(a.xs_now, a.type_s, a.fj, a.fi, a.jpos, a.items, a.entries, a.partials, a.pstride, 0);
     force_item<M, N, ENER, VIR, ACC64>(a, v, ljt, svec, (int)item, lane);
 }
 
@@ -347,62 +350,88 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *partials, long ps
     }
 }
 
-// Forces of one j-cluster's N slots: the j-forces its entries stored, taken
-// in the j-cluster view's order, plus the i-forces stored by the work items
-// of the i-cluster(s) holding these slots; written to the caller's array in
-// input order (or added to it).  One wavefront per j-cluster, lane = (group
-// g, j-particle b): the 64/N groups take every (64/N)-th entry and item,
-// four entries in flight per lane, and a fixed butterfly sums the groups.
+// Forces of one j-cluster's N slots: the j-forces in the j-cluster's rows
+// plus the i-forces stored by the work items of the i-cluster(s) holding
+// these slots; written to the caller's array in input order (or added to it).
+// One wavefront per j-cluster, lane = (group g, j-particle b): the 64/N
+// groups take every (64/N)-th row and item (four rows in flight per lane;
+// each step reads 64/N consecutive rows), and a butterfly sums the groups.
+// The sums are taken in 64-bit fixed point (2^-26 units: a range beyond
+// 1e11 and a resolution far below FP32 rounding of the forces), so they do
+// not depend on the order of the rows; a non-finite term (or one beyond the
+// fixed-point range) makes the force NaN.
 // After an overflowed build (no usable items) every force is zero.
 struct FoldView {
-    gptr<const int> nslots, perm, totals, jstart, jidx, part_istart;
+    gptr<const int> nslots, perm, totals, jstart, part_istart;
     gptr<const float4> fj, fi;
     float *f_out;
     int parts, accumulate;
 };
 
+constexpr float kFixScale = 67108864.0f;           // 2^26
+constexpr double kFixInv = 1.0 / 67108864.0;
+
+// x in 2^-26 units (rounded); 0 with bad set for NaN, infinities and values
+// beyond the int64 range
+__device__ inline long long to_fix(float x, bool &bad) {
+    const float y = x * kFixScale;
+    const bool ok = fabsf(y) < 9.0e18f;
+    bad |= !ok;
+    return ok ? (long long)rintf(y) : 0ll;
+}
+
 template <int M, int N>
 __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
     constexpr int G = 64 / N;
-    cj = __builtin_amdgcn_readfirstlane(cj);   // wave-uniform: scalar loads of the run bounds
+    cj = __builtin_amdgcn_readfirstlane(cj);   // wave-uniform: scalar loads of the row bounds
     if (cj >= *v.nslots / N) return;
     const int b = lane % N, g = lane / N, s = cj * N + b;
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    long long sx = 0, sy = 0, sz = 0;
+    bool bad = false;
     if (v.totals[2] > 0) {
         const int k1 = v.jstart[cj + 1];
         for (int k0 = v.jstart[cj] + g; k0 < k1; k0 += 4 * G) {
-            // all four loads issued before any is used: a run's tail re-reads
-            // position k0 (valid) and drops the value
-            int e[4];
+            // all four loads issued before any is used: past the last row a
+            // lane re-reads row k0 (valid) and drops the value
             float4 f[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) e[u] = v.jidx[k0 + u * G < k1 ? k0 + u * G : k0];
+            for (int u = 0; u < 4; ++u) f[u] = ld(v.fj + (long)(k0 + u * G < k1 ? k0 + u * G : k0) * N + b);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) f[u] = ld(v.fj + (long)e[u] * N + b);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) {   // branch-free: the loads above stay in flight together
                 const bool ok = k0 + u * G < k1;
-                fx += ok ? f[u].x : 0.0f;
-                fy += ok ? f[u].y : 0.0f;
-                fz += ok ? f[u].z : 0.0f;
+                bool b3 = false;
+                const long long qx = to_fix(f[u].x, b3), qy = to_fix(f[u].y, b3), qz = to_fix(f[u].z, b3);
+                sx += ok ? qx : 0ll;
+                sy += ok ? qy : 0ll;
+                sz += ok ? qz : 0ll;
+                bad |= ok && b3;
             }
         }
         const int ci = s / M, o = s % M;
         const int t1 = v.part_istart[(ci + 1) * v.parts];
         for (int t = v.part_istart[ci * v.parts] + g; t < t1; t += G) {
             const float4 f = ld(v.fi + (long)t * M + o);
-            fx += f.x; fy += f.y; fz += f.z;
+            sx += to_fix(f.x, bad);
+            sy += to_fix(f.y, bad);
+            sz += to_fix(f.z, bad);
         }
     }
 #pragma unroll
     for (int o = N; o < 64; o <<= 1) {
-        fx += __shfl_xor(fx, o, 64);
-        fy += __shfl_xor(fy, o, 64);
-        fz += __shfl_xor(fz, o, 64);
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sz += __shfl_xor(sz, o, 64);
     }
+    const unsigned long long badm = __ballot(bad);
     if (g == 0) {
         const int at = v.perm[s];
         if (at >= 0) {
+            bool nonfinite = false;
+#pragma unroll
+            for (int q = 0; q < G; ++q) nonfinite |= (badm >> (q * N + b)) & 1ull;
+            float fx = (float)((double)sx * kFixInv), fy = (float)((double)sy * kFixInv),
+                  fz = (float)((double)sz * kFixInv);
+            if (nonfinite) fx = fy = fz = __builtin_nanf("");
             float *out = v.f_out + 3 * (long)at;
             if (v.accumulate) {
                 fx += out[0]; fy += out[1]; fz += out[2];
@@ -416,9 +445,9 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
 
 template <int M, int N>
 __global__ __launch_bounds__(256) void k_fold(ForceArgs a) {
-    const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,        (gptr<const int>)a.totals,
-                     (gptr<const int>)a.jstart, (gptr<const int>)a.jidx,        (gptr<const int>)a.part_istart,
-                     (gptr<const float4>)a.fj,  (gptr<const float4>)a.fi,       a.f_out,
+    const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,   (gptr<const int>)a.totals,
+                     (gptr<const int>)a.jstart, (gptr<const int>)a.part_istart,
+                     (gptr<const float4>)a.fj,  (gptr<const float4>)a.fi,  a.f_out,
                      a.parts,                   a.accumulate};
     fold_body<M, N>(v, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
@@ -656,7 +685,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         const int jidx = base + lane;
         if (jidx < nslot) {
             const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
-            a.fj[(long)js * N + jidx] = make_float4(gx, gy, gz, 0.0f);
+            a.fj[(long)a.jpos[js + jidx / N] * N + jidx % N] = make_float4(gx, gy, gz, 0.0f);
             if (VIR) {
                 const float4 pj = jd[jidx];
                 vir[0] += (acc_t)(pj.x * gx); vir[1] += (acc_t)(pj.x * gy); vir[2] += (acc_t)(pj.x * gz);
@@ -710,7 +739,7 @@ struct RepDesc {
     float4 *xs_now;
     const int *type_s, *perm, *img_s, *slot_of, *nslots;
     float4 *fj, *fi;
-    const int *jstart, *jidx, *part_istart;
+    const int *jstart, *jpos, *part_istart;
     int parts, n;
     const int4 *items;
     const nb_jentry *entries;
@@ -801,7 +830,8 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     if (idx < 0) return;
     const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
     const RepDesc &d = b.rep[r];
-    const SysView v = make_view(d.xs_now, d.type_s, d.fj, d.fi, d.items, d.entries, b.partials, b.pstride, d.pbase);
+    const SysView v =
+        make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
     force_item<M, N, ENER, VIR, true>(a, v, ljt, d.shiftvec, (int)(idx - b.item_off[r]), lane);
 }
 
@@ -813,9 +843,9 @@ __global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
     if (g0 >= b.slot_off[b.n_rep]) return;
     const int r = find_rep(b.slot_off, b.n_rep, g0);
     const RepDesc &d = b.rep[r];
-    const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,        (gptr<const int>)d.totals,
-                     (gptr<const int>)d.jstart, (gptr<const int>)d.jidx,        (gptr<const int>)d.part_istart,
-                     (gptr<const float4>)d.fj,  (gptr<const float4>)d.fi,       d.f_out,
+    const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,   (gptr<const int>)d.totals,
+                     (gptr<const int>)d.jstart, (gptr<const int>)d.part_istart,
+                     (gptr<const float4>)d.fj,  (gptr<const float4>)d.fi,  d.f_out,
                      d.parts,                   b.accumulate};
     fold_body<M, N>(v, (int)((g0 - b.slot_off[r]) / N), threadIdx.x & 63);
 }
@@ -929,7 +959,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.fj = (float4 *)l->fj.p;
     a.fi = (float4 *)l->fi.p;
     a.jstart = (const int *)l->jstart.p;
-    a.jidx = (const int *)l->jidx.p;
+    a.jpos = (const int *)l->jrank.p;
     a.part_istart = (const int *)l->part_istart.p;
     a.parts = l->resv_parts;
     a.n = g->n;
@@ -1047,7 +1077,7 @@ void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *x
     d.fj = (float4 *)l->fj.p;
     d.fi = (float4 *)l->fi.p;
     d.jstart = (const int *)l->jstart.p;
-    d.jidx = (const int *)l->jidx.p;
+    d.jpos = (const int *)l->jrank.p;
     d.part_istart = (const int *)l->part_istart.p;
     d.parts = l->resv_parts;
     d.n = g->n;

@@ -238,8 +238,10 @@ __global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *p
 
 // Exclusive scan on one workgroup of 1024 threads, each owning a contiguous
 // chunk; mode 0: values as is, 1: rounded up to a multiple of p, 2: ceil(v/p).
-// raw_total (optional) receives the sum of the untransformed values.
-__device__ inline void scan_body(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total) {
+// raw_total (optional) receives the sum of the untransformed values; clear
+// (optional, the input array itself) is zeroed once read.
+__device__ inline void scan_body(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total,
+                                 int *clear = nullptr) {
     __shared__ int raws[1024];
     __shared__ int sums[1024];
     const int t = threadIdx.x;
@@ -265,8 +267,10 @@ __device__ inline void scan_body(const int *in, int *out, int n, int mode, int p
     }
     int run = sums[t] - s;
     for (int i = b; i < e; ++i) {
+        const int v = in[i];
         out[i] = run;
-        run += tr(in[i]);
+        run += tr(v);
+        if (clear) clear[i] = 0;
     }
     if (t == 1023) {
         out[n] = sums[1023];
@@ -279,6 +283,8 @@ __global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, i
                                                int *raw_total) {
     scan_body(in, out, n, mode, p, total, raw_total);
 }
+
+__global__ __launch_bounds__(1024) void k_scan_clear(int *in, int *out, int n) { scan_body(in, out, n, 0, 1, nullptr, nullptr, in); }
 
 __global__ void k_fill_int(int *p, int n, int v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,7 +362,7 @@ __global__ void kb_bb(const GridJob *J, const int *off, int n, int which) {
 
 __global__ __launch_bounds__(1024) void kb_scan(const mxn::ScanJob *J) {
     const mxn::ScanJob &j = J[blockIdx.x];
-    scan_body(j.in, j.out, j.n, j.mode, j.p, j.total, j.raw_total);
+    scan_body(j.in, j.out, j.n, j.mode, j.p, j.total, j.raw_total, j.clear);
 }
 
 __global__ void kb_shiftvec(const GridJob *J) {
@@ -373,6 +379,8 @@ namespace mxn {
 void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s) {
     k_scan<<<1, 1024, 0, s>>>(in, out, n, 0, 1, total, nullptr);
 }
+
+void launch_scan_clear(int *in, int *out, int n, hipStream_t s) { k_scan_clear<<<1, 1024, 0, s>>>(in, out, n); }
 
 void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total, hipStream_t s) {
     k_scan<<<1, 1024, 0, s>>>(in, out, n, mode, p, total, raw_total);

@@ -105,12 +105,15 @@ struct nb_list {
     mxn::DevBuf entries_canon, keys;   // fill-pass output before a distance sort, and its sort keys
     mxn::DevBuf part_count, part_start, part_istart;
     mxn::DevBuf totals;        // int[4]: entries, items, usable items (0 after an overflow), region overflow
-    // j-cluster view (per j-cluster: the positions of its entries, ascending),
-    // rebuilt with the list: counters (zero between builds), their exclusive
-    // scan, scatter output and the sorted runs
-    mxn::DevBuf jcount, jstart, jtmp, jidx;
-    // force-call buffers: float4 j-force per (entry position, j-particle) and
-    // i-force per (work item, i-particle), summed per cluster after the kernel
+    // j-cluster view, rebuilt with the list: entries per j-cluster (counters,
+    // zero between builds), their exclusive scan (first row of each j-cluster),
+    // and for each entry position its row: the j-cluster's first row plus the
+    // entry's rank among the j-cluster's entries (jrank_canon: the fill pass's
+    // ranks before a distance sort)
+    mxn::DevBuf jcount, jstart, jrank, jrank_canon;
+    // force-call buffers: float4 j-force per (row, j-particle), rows grouped by
+    // j-cluster, and i-force per (work item, i-particle); summed per cluster
+    // after the force kernel
     mxn::DevBuf fj, fi;
     int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
     int resv_nci = 0;          // i-cluster capacity of the reserved layout
@@ -158,6 +161,7 @@ struct ScanJob {
     int *out;
     int n, mode, p;
     int *total, *raw_total;
+    int *clear;   // the input, zeroed once read (or null)
 };
 void launch_scan_batch(const ScanJob *jobs, int n_jobs, hipStream_t st);
 size_t grid_job_size();
@@ -197,5 +201,7 @@ int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *x
                  unsigned long long *d_counts);
 // exclusive scan of n ints on one workgroup; writes out[0..n] (out[n] = total) and *total
 void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
+// exclusive scan of in[0..n) into out[0..n] that leaves in[] zeroed
+void launch_scan_clear(int *in, int *out, int n, hipStream_t s);
 
 }  // namespace mxn

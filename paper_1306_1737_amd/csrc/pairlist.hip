@@ -44,6 +44,8 @@ struct SearchArgsT {
     P<int> region_overflow;              // set when a region is too small
     P<nb_jentry> entries;   // each region in (shift, j-cluster) order
     P<float> keys;          // bounding-box distance^2 of each entry (or null)
+    P<int> jcount;          // entries per j-cluster (fill pass; zero before it)
+    P<int> jrank;           // each written entry's rank among its j-cluster's entries
     int nci_cap, parts;
 };
 using SearchArgs = SearchArgsT<plain>;
@@ -71,6 +73,8 @@ __device__ inline SearchArgsG to_global(const SearchArgs &a) {
     g.region_overflow = (gptr<int>)a.region_overflow;
     g.entries = (gptr<nb_jentry>)a.entries;
     g.keys = (gptr<float>)a.keys;
+    g.jcount = (gptr<int>)a.jcount;
+    g.jrank = (gptr<int>)a.jrank;
     g.nci_cap = a.nci_cap; g.parts = a.parts;
     return g;
 }
@@ -310,6 +314,7 @@ __device__ inline void search_body(const A &a, int blk) {
                                 en.mhi = (uint32_t)(mask >> 32);
                                 st(a.entries + wpos + rank, en);
                                 if (a.keys) a.keys[wpos + rank] = d2;
+                                a.jrank[wpos + rank] = atomicAdd((int *)a.jcount + cj, 1);
                             }
                         }
                     }
@@ -356,7 +361,8 @@ __global__ void k_items(int nparts_total, int parts, int per_item, const int *pa
 // lie beyond the cut-off, share force-kernel passes whose pair work can be
 // skipped.  One wavefront per region, rank sort with the keys staged in LDS.
 __global__ __launch_bounds__(64) void k_sort_entries(const int *part_start, const int *part_count,
-                                                     const nb_jentry *in, const float *keys, nb_jentry *out) {
+                                                     const nb_jentry *in, const float *keys, nb_jentry *out,
+                                                     const int *rank_in, int *rank_out) {
     __shared__ float sk[1024];
     const int g = blockIdx.x, lane = threadIdx.x;
     const int b = part_start[g], n = min(part_count[g], part_start[g + 1] - b);
@@ -372,6 +378,7 @@ __global__ __launch_bounds__(64) void k_sort_entries(const int *part_start, cons
             r += (kj < ki) || (kj == ki && j < i);
         }
         out[b + r] = in[b + i];
+        rank_out[b + r] = rank_in[b + i];
     }
 }
 
@@ -409,67 +416,33 @@ __device__ inline void finalize_body(int *totals, long cap_items, int *flags) {
 __global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_body(totals, cap_items, flags); }
 
 // --------------------------------------------------------------------------
-// j-cluster view of a list: for every j-cluster, the positions of the entries
-// that name it, in increasing order.  The force kernels store each entry's
-// j-forces instead of adding them to memory with atomics; the reduction then
-// sums them per j-cluster in this fixed order.  Built after every list build:
-// a count per j-cluster over the usable items' entries, an exclusive scan, a
-// scatter that counts each j-cluster back down to zero (which leaves the
-// counters cleared for the next build), and a rank sort of each j-cluster's
-// run.
-struct JViewArgs {
+// j-cluster view of a list.  The force kernels store each entry's j-forces
+// (instead of adding them to memory with atomics) in a row of a buffer whose
+// rows are grouped by j-cluster, so that the reduction reads each j-cluster's
+// rows contiguously.  The fill pass takes each written entry's rank among its
+// j-cluster's entries from a counter per j-cluster; after the build an
+// exclusive scan of the counters (which clears them for the next build)
+// gives each j-cluster's first row, and this pass turns every usable entry's
+// rank into its row.  The row order within a j-cluster depends on timing; the
+// reduction sums in fixed point, so the forces do not.
+struct JPosArgs {
     const int *totals;   // [2]: usable items
     const int4 *items;
     const nb_jentry *entries;
-    int *jcount;         // j-cluster counters: zero between builds
-    const int *jstart;   // exclusive scan of the counts (njc + 1)
-    int *jtmp, *jidx;    // scatter output, and the sorted runs
-    int njc;             // j-clusters of the grid's capacity
+    const int *jstart;   // first row of each j-cluster
+    int *jrank;          // rank in, row out
 };
 
-constexpr int kJSortStage = 512;   // entries of a j-cluster's run sorted in LDS
-
 // one wavefront per work item, one lane per entry (items hold at most 64)
-__device__ inline void jcount_body(const JViewArgs &a, bool scatter, int blk) {
+__device__ inline void jpos_body(const JPosArgs &a, int blk) {
     const int t = blk * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= a.totals[2]) return;
     const int4 it = a.items[t];
     const int e = it.y + lane;
-    if (e >= it.z) return;
-    const int cj = a.entries[e].cj;
-    if (!scatter) {
-        atomicAdd(a.jcount + cj, 1);
-    } else {
-        const int pos = atomicSub(a.jcount + cj, 1) - 1;
-        a.jtmp[a.jstart[cj] + pos] = e;
-    }
+    if (e < it.z) a.jrank[e] += a.jstart[a.entries[e].cj];
 }
 
-__global__ __launch_bounds__(256) void k_jcount(JViewArgs a, int scatter) { jcount_body(a, scatter != 0, blockIdx.x); }
-
-// one wavefront per j-cluster: rank sort of its run (the values are distinct)
-__device__ inline void jsort_body(const JViewArgs &a, int blk) {
-    __shared__ int sv[4][kJSortStage];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cj = blk * 4 + w;
-    if (cj >= a.njc) return;
-    if (lane == 0) a.jcount[cj] = 0;   // already zero after the scatter; kept clear regardless
-    const int b = a.jstart[cj], n = a.jstart[cj + 1] - b;
-    const bool staged = n <= kJSortStage;
-    if (staged)
-        for (int i = lane; i < n; i += 64) sv[w][i] = a.jtmp[b + i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int i = lane; i < n; i += 64) {
-        const int v = staged ? sv[w][i] : a.jtmp[b + i];
-        int r = 0;
-        for (int j = 0; j < n; ++j) r += (staged ? sv[w][j] : a.jtmp[b + j]) < v;
-        a.jidx[b + r] = v;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_jsort(JViewArgs a) { jsort_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x); }
 
 // --------------------------------------------------------------------------
 // Batched rebuild of many replicas' lists (the fill pass into the regions the
@@ -479,7 +452,7 @@ __global__ __launch_bounds__(256) void k_jsort(JViewArgs a) { jsort_body(a, bloc
 
 struct ListJob {
     SearchArgs a;
-    JViewArgs jv;
+    JPosArgs jp;
     int nregions, per_item;
     int *part_count, *part_start, *part_istart, *totals;
     int4 *items;
@@ -487,7 +460,7 @@ struct ListJob {
     int *flags;
 };
 
-enum { LS_SEARCH, LS_ITEMS, LS_JITEMS, LS_JSORT, LS_NSTAGES };
+enum { LS_SEARCH, LS_ITEMS, LS_JPOS, LS_NSTAGES };
 
 __device__ inline int job_of(const int *off, int n, int b) {
     int lo = 0, hi = n - 1;   // last r with off[r] <= b
@@ -517,14 +490,9 @@ __global__ void kb_finalize(const ListJob *J) {
     finalize_body(j.totals, j.cap_items, j.flags);
 }
 
-__global__ __launch_bounds__(256) void kb_jcount(const ListJob *J, const int *off, int n, int scatter) {
+__global__ __launch_bounds__(256) void kb_jpos(const ListJob *J, const int *off, int n) {
     const int r = job_of(off, n, blockIdx.x);
-    jcount_body(J[r].jv, scatter != 0, blockIdx.x - off[r]);
-}
-
-__global__ __launch_bounds__(256) void kb_jsort(const ListJob *J, const int *off, int n) {
-    const int r = job_of(off, n, blockIdx.x);
-    jsort_body(J[r].jv, blockIdx.x - off[r]);
+    jpos_body(J[r].jp, blockIdx.x - off[r]);
 }
 
 template <int M, int N>
@@ -567,16 +535,13 @@ static SearchArgs make_search(const nb_list *l, const int *excl_off, const int *
     return a;
 }
 
-static JViewArgs make_jview(const nb_list *l) {
-    JViewArgs v{};
+static JPosArgs make_jpos(const nb_list *l) {
+    JPosArgs v{};
     v.totals = (const int *)l->totals.p;
     v.items = (const int4 *)l->items.p;
     v.entries = (const nb_jentry *)l->entries.p;
-    v.jcount = (int *)l->jcount.p;
     v.jstart = (const int *)l->jstart.p;
-    v.jtmp = (int *)l->jtmp.p;
-    v.jidx = (int *)l->jidx.p;
-    v.njc = l->grid->slots_cap / l->grid->nn;
+    v.jrank = (int *)l->jrank.p;
     return v;
 }
 
@@ -588,7 +553,9 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
                    ScanJob *jscan) {
     ListJob j{};
     j.a = make_search(l, excl_off, excl_idx);
-    j.jv = make_jview(l);
+    j.a.jcount = (int *)l->jcount.p;
+    j.a.jrank = (int *)l->jrank.p;
+    j.jp = make_jpos(l);
     j.a.parts = l->resv_parts;
     j.a.entries = (nb_jentry *)l->entries.p;
     j.a.keys = nullptr;
@@ -603,15 +570,15 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.flags = l->ctx->d_flags;
     std::memcpy(out, &j, sizeof j);
     *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, j.per_item, j.totals + 1, j.totals};
-    *jscan = ScanJob{j.jv.jcount, (int *)j.jv.jstart, j.jv.njc, 0, 1, nullptr, nullptr};
+    int *jc = (int *)l->jcount.p;
+    *jscan = ScanJob{jc, (int *)l->jstart.p, l->grid->slots_cap / l->grid->nn, 0, 1, nullptr, nullptr, jc};
 }
 
 void list_job_blocks(const nb_list *l, int *blocks_per_stage) {
     const long nreg = (long)l->resv_nci * l->resv_parts;
     blocks_per_stage[LS_SEARCH] = (int)((nreg + 3) / 4);
     blocks_per_stage[LS_ITEMS] = (int)((nreg + 255) / 256);
-    blocks_per_stage[LS_JITEMS] = (int)((l->cap_items + 3) / 4);
-    blocks_per_stage[LS_JSORT] = (int)((l->grid->slots_cap / l->grid->nn + 3) / 4);
+    blocks_per_stage[LS_JPOS] = (int)((l->cap_items + 3) / 4);
 }
 
 int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
@@ -625,10 +592,8 @@ int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const
     launch_scan_batch(scans, n_rep, st);
     kb_items<<<total[LS_ITEMS], 256, 0, st>>>(J, off + LS_ITEMS * stride, n_rep);
     kb_finalize<<<n_rep, 64, 0, st>>>(J);
-    kb_jcount<<<total[LS_JITEMS], 256, 0, st>>>(J, off + LS_JITEMS * stride, n_rep, 0);
     launch_scan_batch(scans + n_rep, n_rep, st);
-    kb_jcount<<<total[LS_JITEMS], 256, 0, st>>>(J, off + LS_JITEMS * stride, n_rep, 1);
-    kb_jsort<<<total[LS_JSORT], 256, 0, st>>>(J, off + LS_JSORT * stride, n_rep);
+    kb_jpos<<<total[LS_JPOS], 256, 0, st>>>(J, off + LS_JPOS * stride, n_rep);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
@@ -688,8 +653,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         const long njc = g->slots_cap / g->nn;
         int rc = ensure(l->jcount, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->jstart, (size_t)(njc + 1) * 4);
-        rc = rc ? rc : ensure(l->jtmp, (size_t)l->cap_entries * 4);
-        rc = rc ? rc : ensure(l->jidx, (size_t)l->cap_entries * 4);
+        rc = rc ? rc : ensure(l->jrank, (size_t)l->cap_entries * 4);
         rc = rc ? rc : ensure(l->fj, (size_t)l->cap_entries * g->nn * 16);
         rc = rc ? rc : ensure(l->fi, (size_t)l->cap_items * g->m * 16);
         if (rc) return rc;
@@ -704,9 +668,16 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         if (rc) return rc;
         rc = ensure(l->keys, (size_t)l->cap_entries * sizeof(float));
         if (rc) return rc;
+        rc = ensure(l->jrank_canon, (size_t)l->cap_entries * 4);
+        if (rc) return rc;
     }
     a.entries = (nb_jentry *)(by_distance ? l->entries_canon.p : l->entries.p);
     a.keys = by_distance ? (float *)l->keys.p : nullptr;
+    // the j-cluster counters and ranks (allocated by a reserving build)
+    a.jcount = (int *)l->jcount.p;
+    a.jrank = (int *)(by_distance ? l->jrank_canon.p : l->jrank.p);
+    if (!a.jcount || !a.jrank || !l->jstart.p || !l->fj.p || !l->fi.p)
+        return fail(NB_ERR_STATE, "nb_pairlist_build: j-cluster view buffers missing");
     if (g->m == 4 && g->nn == 4) run<4, 4>(l, a, true, nblocks, st);
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, true, nblocks, st);
@@ -720,15 +691,12 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     if (by_distance)
         k_sort_entries<<<nregions, 64, 0, st>>>((const int *)l->part_start.p, (const int *)l->part_count.p,
                                                 (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
-                                                (nb_jentry *)l->entries.p);
+                                                (nb_jentry *)l->entries.p, (const int *)l->jrank_canon.p,
+                                                (int *)l->jrank.p);
     k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, ctx->d_flags);
-    // the j-cluster view of the usable items' entries
-    const JViewArgs jv = make_jview(l);
-    const int nbi = (int)((l->cap_items + 3) / 4);
-    k_jcount<<<nbi, 256, 0, st>>>(jv, 0);
-    launch_scan(jv.jcount, (int *)jv.jstart, jv.njc, nullptr, st);
-    k_jcount<<<nbi, 256, 0, st>>>(jv, 1);
-    k_jsort<<<(jv.njc + 3) / 4, 256, 0, st>>>(jv);
+    // rows of the j-cluster view
+    launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
+    k_jpos<<<(int)((l->cap_items + 3) / 4), 256, 0, st>>>(make_jpos(l));
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }

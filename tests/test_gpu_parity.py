@@ -241,6 +241,34 @@ def test_accumulate_flag(c1):
 
 
 @pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("shape", [(4, 8), (8, 4), (8, 8)])
+def test_forces_reproducible_across_rebuilds(c1, shape, variant):
+    """The j-forces of a j-cluster are summed in fixed point, so the forces do not depend on the order in
+    which the list build placed that j-cluster's rows (set by atomics): forces from two separate builds of
+    the same list, and from two calls on one build, are bit-identical; the list itself is identical."""
+    s = GpuSystem(c1, shape, 1.1, variant=variant)
+    try:
+        mxn = s.mxn
+        fl = mxn.NB_ENERGY | mxn.NB_VIRIAL
+        f1, e1, v1 = s.forces(1.0, 3.12, fl)
+        f1b, e1b, _ = s.forces(1.0, 3.12, fl)
+        ref = mxn.nb_list_export_canonical(s.lst)
+        for flags in (0, mxn.NB_LIST_ASYNC):
+            s.lst = mxn.nb_pairlist_build(s.ctx, s.grid, 1.1, -1.0, s.eo, s.ei, flags, s.lst)
+            _cmp_lists(mxn.nb_list_export_canonical(s.lst), ref)
+            f2, e2, v2 = s.forces(1.0, 3.12, fl)
+            np.testing.assert_array_equal(f2.view(np.uint64), f1.view(np.uint64))
+            np.testing.assert_array_equal(e2, e1)
+            np.testing.assert_array_equal(v2, v1)
+        np.testing.assert_array_equal(f1b.view(np.uint64), f1.view(np.uint64))
+        np.testing.assert_array_equal(e1b, e1)
+        fr, er, _ = _oracle_forces(c1, 1.0, 3.12)
+        assert rel_rms(f1, fr) <= 1e-5
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
 def test_tiny_and_ragged(ragged, variant):
     """One water in a box; and a ragged 291-atom box, all shapes."""
     one = synth.water_box(1, 2.5, seed=1)
