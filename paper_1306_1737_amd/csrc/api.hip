@@ -120,6 +120,7 @@ void nb_destroy(nb_ctx *c) {
         }
     for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
     release(c->partials);
+    release(c->blockpart);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->h_pinned) hipHostFree(c->h_pinned);
     delete c;

@@ -40,7 +40,8 @@ using mxn::ld;
 struct SysView {
     gptr<const float4> xs_now;
     gptr<const int> type_s;
-    gptr<float4> fj, fi;   // j-forces per (row, j-particle), i-forces per (item, i-particle)
+    gptr<float> fj;        // j-force (x, y, z) per (row, j-particle)
+    gptr<float4> fi;       // i-force per (item, i-particle)
     gptr<const int> jpos;  // row of each entry position
     gptr<const int4> items;
     gptr<const nb_jentry> entries;
@@ -48,10 +49,10 @@ struct SysView {
     long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
 };
 
-__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float4 *fj, float4 *fi, const int *jpos,
+__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fj, float4 *fi, const int *jpos,
                                     const int4 *items, const nb_jentry *entries, double *partials, long pstride,
                                     long pbase) {
-    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float4>)fj,
+    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float>)fj,
                    (gptr<float4>)fi,           (gptr<const int>)jpos,   (gptr<const int4>)items,
                    (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
 }
@@ -60,8 +61,12 @@ struct ForceArgs {
     const int *nslots, *perm, *img_s, *slot_of, *type_s;
     const float4 *xyzq_now;
     float4 *xs_now;
-    float4 *fj, *fi;   // j-forces per (row, j-particle), i-forces per (item, i-particle)
+    float *fj;         // j-force (x, y, z) per (row, j-particle)
+    float4 *fi;        // i-force per (item, i-particle)
     const int *jstart, *jpos, *part_istart;   // first row of each j-cluster, row of each entry; first item of each region
+    double *blockpart;   // energy reduction: per-share sums [kNAcc][kReduceParts]
+    double *energy, *virial;
+    int ener, vir;
     int parts;         // regions per i-cluster
     int n;
     const int4 *items;
@@ -265,7 +270,12 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
             elj += (acc_t)el;
             ec += (acc_t)ecl;
         }
-        if (valid) mxn::st(v.fj + (long)row * N + jb, make_float4(fjx, fjy, fjz, 0.0f));
+        if (valid) {
+            const gptr<float> o = v.fj + ((long)row * N + jb) * 3;
+            o[0] = fjx;
+            o[1] = fjy;
+            o[2] = fjz;
+        }
         if (VIR) {
             vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
             vir[3] += (acc_t)(yj * fjx); vir[4] += (acc_t)(yj * fjy); vir[5] += (acc_t)(yj * fjz);
@@ -317,39 +327,6 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     force_item<M, N, ENER, VIR, ACC64>(a, v, ljt, svec, (int)item, lane);
 }
 
-// Deterministic reduction of the per-item partials: one workgroup per value,
-// a fixed assignment of items to threads (coalesced, four independent
-// accumulators per thread) and a fixed tree.  FP64 or (precision study) FP32.
-template <bool ACC64>
-__global__ __launch_bounds__(1024) void k_reduce(const double *partials, long pstride, const int *totals,
-                                                 double *energy, double *virial, int ener, int vir) {
-    using acc_t = typename std::conditional<ACC64, double, float>::type;
-    __shared__ acc_t red[1024];
-    const int t = threadIdx.x, k = blockIdx.x;
-    if ((k < 2 && !ener) || (k >= 2 && !vir)) return;
-    const int n = totals[2];
-    const double *p = partials + (size_t)k * pstride;
-    acc_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    int i = t;
-    for (; i + 3 * 1024 < n; i += 4 * 1024) {
-        s0 += (acc_t)p[i];
-        s1 += (acc_t)p[i + 1024];
-        s2 += (acc_t)p[i + 2048];
-        s3 += (acc_t)p[i + 3072];
-    }
-    for (; i < n; i += 1024) s0 += (acc_t)p[i];
-    red[t] = (s0 + s1) + (s2 + s3);
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) {
-        if (k < 2) energy[k] = (double)red[0];
-        else virial[k - 2] = (double)red[0];
-    }
-}
-
 // Forces of one j-cluster's N slots: the j-forces in the j-cluster's rows
 // plus the i-forces stored by the work items of the i-cluster(s) holding
 // these slots; written to the caller's array in input order (or added to it).
@@ -359,11 +336,12 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *partials, long ps
 // The sums are taken in 64-bit fixed point (2^-26 units: a range beyond
 // 1e11 and a resolution far below FP32 rounding of the forces), so they do
 // not depend on the order of the rows; a non-finite term (or one beyond the
-// fixed-point range) makes the force NaN.
-// After an overflowed build (no usable items) every force is zero.
+// fixed-point range) makes the force NaN.  After an overflowed build (no
+// usable items) every force is zero.
 struct FoldView {
     gptr<const int> nslots, perm, totals, jstart, part_istart;
-    gptr<const float4> fj, fi;
+    gptr<const float> fj;
+    gptr<const float4> fi;
     float *f_out;
     int parts, accumulate;
 };
@@ -393,14 +371,19 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
         for (int k0 = v.jstart[cj] + g; k0 < k1; k0 += 4 * G) {
             // all four loads issued before any is used: past the last row a
             // lane re-reads row k0 (valid) and drops the value
-            float4 f[4];
+            float f[4][3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) f[u] = ld(v.fj + (long)(k0 + u * G < k1 ? k0 + u * G : k0) * N + b);
+            for (int u = 0; u < 4; ++u) {
+                const gptr<const float> p = v.fj + ((long)(k0 + u * G < k1 ? k0 + u * G : k0) * N + b) * 3;
+                f[u][0] = p[0];
+                f[u][1] = p[1];
+                f[u][2] = p[2];
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {   // branch-free: the loads above stay in flight together
                 const bool ok = k0 + u * G < k1;
                 bool b3 = false;
-                const long long qx = to_fix(f[u].x, b3), qy = to_fix(f[u].y, b3), qz = to_fix(f[u].z, b3);
+                const long long qx = to_fix(f[u][0], b3), qy = to_fix(f[u][1], b3), qz = to_fix(f[u][2], b3);
                 sx += ok ? qx : 0ll;
                 sy += ok ? qy : 0ll;
                 sz += ok ? qz : 0ll;
@@ -443,13 +426,69 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
     }
 }
 
-template <int M, int N>
+// Energy and virial from the per-item partials, deterministic and in two
+// stages: the first kReduceParts fold workgroups each sum a contiguous share
+// of the items (fixed thread assignment and tree) into one value per
+// quantity, then one workgroup sums those values in order.  (A single
+// launch with a last-workgroup ticket needs a device-scope release per
+// workgroup, which writes back the L2 of every XCD: measured far slower.)
+// FP64, or FP32 throughout for the precision study.
+constexpr int kReduceParts = 256;
+
+template <bool ACC64>
+__device__ inline void fold_energy(const ForceArgs &a) {
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    __shared__ acc_t red[256];
+    const int t = threadIdx.x, w = blockIdx.x;
+    const int R = min((int)gridDim.x, kReduceParts);
+    if (w >= R) return;
+    const long nit = a.totals[2];
+    const long per = (nit + R - 1) / R, i0 = w * per, i1 = min(nit, i0 + per);
+    for (int k = 0; k < kNAcc; ++k) {
+        if ((k < 2 && !a.ener) || (k >= 2 && !a.vir)) continue;
+        acc_t s = 0;
+        for (long i = i0 + t; i < i1; i += 256) s += (acc_t)a.partials[(size_t)k * a.pstride + i];
+        red[t] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) a.blockpart[(size_t)k * kReduceParts + w] = (double)red[0];
+    }
+}
+
+template <bool ACC64>
+__global__ __launch_bounds__(256) void k_reduce_parts(const double *blockpart, int R, double *energy, double *virial,
+                                                      int ener, int vir) {
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    __shared__ acc_t red[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < kNAcc; ++k) {
+        if ((k < 2 && !ener) || (k >= 2 && !vir)) continue;
+        red[t] = t < R ? (acc_t)blockpart[(size_t)k * kReduceParts + t] : (acc_t)0;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) {
+            if (k < 2) energy[k] = (double)red[0];
+            else virial[k - 2] = (double)red[0];
+        }
+        __syncthreads();
+    }
+}
+
+template <int M, int N, int ACC>   // ACC: 0 no energy/virial, 1 FP32, 2 FP64 sums
 __global__ __launch_bounds__(256) void k_fold(ForceArgs a) {
     const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,   (gptr<const int>)a.totals,
                      (gptr<const int>)a.jstart, (gptr<const int>)a.part_istart,
-                     (gptr<const float4>)a.fj,  (gptr<const float4>)a.fi,  a.f_out,
+                     (gptr<const float>)a.fj,   (gptr<const float4>)a.fi,  a.f_out,
                      a.parts,                   a.accumulate};
     fold_body<M, N>(v, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+    if (ACC == 1) fold_energy<false>(a);
+    if (ACC == 2) fold_energy<true>(a);
 }
 
 // Pair statistics of a list at the current positions (the paper's effective
@@ -685,7 +724,10 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         const int jidx = base + lane;
         if (jidx < nslot) {
             const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
-            a.fj[(long)a.jpos[js + jidx / N] * N + jidx % N] = make_float4(gx, gy, gz, 0.0f);
+            float *o = a.fj + ((long)a.jpos[js + jidx / N] * N + jidx % N) * 3;
+            o[0] = gx;
+            o[1] = gy;
+            o[2] = gz;
             if (VIR) {
                 const float4 pj = jd[jidx];
                 vir[0] += (acc_t)(pj.x * gx); vir[1] += (acc_t)(pj.x * gy); vir[2] += (acc_t)(pj.x * gz);
@@ -702,6 +744,20 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
         if (lane == 0)
             for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
+    }
+}
+
+template <int M, int N>
+void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
+    const int R = std::min(nb, kReduceParts);
+    if (acc == 0) {
+        k_fold<M, N, 0><<<nb, 256, 0, st>>>(a);
+    } else if (acc == 1) {
+        k_fold<M, N, 1><<<nb, 256, 0, st>>>(a);
+        k_reduce_parts<false><<<1, 256, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
+    } else {
+        k_fold<M, N, 2><<<nb, 256, 0, st>>>(a);
+        k_reduce_parts<true><<<1, 256, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
     }
 }
 
@@ -738,7 +794,8 @@ struct RepDesc {
     float *f_out;
     float4 *xs_now;
     const int *type_s, *perm, *img_s, *slot_of, *nslots;
-    float4 *fj, *fi;
+    float *fj;
+    float4 *fi;
     const int *jstart, *jpos, *part_istart;
     int parts, n;
     const int4 *items;
@@ -845,7 +902,7 @@ __global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
     const RepDesc &d = b.rep[r];
     const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,   (gptr<const int>)d.totals,
                      (gptr<const int>)d.jstart, (gptr<const int>)d.part_istart,
-                     (gptr<const float4>)d.fj,  (gptr<const float4>)d.fi,  d.f_out,
+                     (gptr<const float>)d.fj,   (gptr<const float4>)d.fi,  d.f_out,
                      d.parts,                   b.accumulate};
     fold_body<M, N>(v, (int)((g0 - b.slot_off[r]) / N), threadIdx.x & 63);
 }
@@ -956,7 +1013,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.type_s = (const int *)g->type_s.p;
     a.xyzq_now = (const float4 *)xyzq_now;
     a.xs_now = (float4 *)g->xs_now.p;
-    a.fj = (float4 *)l->fj.p;
+    a.fj = (float *)l->fj.p;
     a.fi = (float4 *)l->fi.p;
     a.jstart = (const int *)l->jstart.p;
     a.jpos = (const int *)l->jrank.p;
@@ -983,6 +1040,17 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.f_out = f;
     a.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
     a.flags = ctx->d_flags;
+    // fold launch: one wavefront per j-cluster; with energies it also reduces the partials
+    const int nfold = (g->slots_cap / g->nn + 3) / 4;
+    if (need_acc) {
+        int rc = ensure(ctx->blockpart, (size_t)kReduceParts * kNAcc * sizeof(double));
+        if (rc) return rc;
+        a.blockpart = (double *)ctx->blockpart.p;
+        a.energy = energy;
+        a.virial = virial;
+        a.ener = (flags & NB_ENERGY) ? 1 : 0;
+        a.vir = (flags & NB_VIRIAL) ? 1 : 0;
+    }
     k_gather<<<(g->slots_cap + 255) / 256, 256, 0, st>>>(a);
     const long nwaves = l->cap_items;
     int nb = (int)((nwaves + 3) / 4);
@@ -997,19 +1065,11 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         else if (g->m == 8 && g->nn == 4) launch_shape<8, 4>(a, flags, nb, lds, var, st);
         else launch_shape<8, 8>(a, flags, nb, lds, var, st);
     }
-    const int nfold = (g->slots_cap / g->nn + 3) / 4;
-    if (g->m == 4 && g->nn == 4) k_fold<4, 4><<<nfold, 256, 0, st>>>(a);
-    else if (g->m == 4 && g->nn == 8) k_fold<4, 8><<<nfold, 256, 0, st>>>(a);
-    else if (g->m == 8 && g->nn == 4) k_fold<8, 4><<<nfold, 256, 0, st>>>(a);
-    else k_fold<8, 8><<<nfold, 256, 0, st>>>(a);
-    if (need_acc) {
-        if (flags & NB_ACC_FP32)
-            k_reduce<false><<<kNAcc, 1024, 0, st>>>(a.partials, pstride, a.totals, energy, virial, flags & NB_ENERGY,
-                                                    flags & NB_VIRIAL);
-        else
-            k_reduce<true><<<kNAcc, 1024, 0, st>>>(a.partials, pstride, a.totals, energy, virial, flags & NB_ENERGY,
-                                                   flags & NB_VIRIAL);
-    }
+    const int acc = !need_acc ? 0 : ((flags & NB_ACC_FP32) ? 1 : 2);
+    if (g->m == 4 && g->nn == 4) launch_fold<4, 4>(a, acc, nfold, st);
+    else if (g->m == 4 && g->nn == 8) launch_fold<4, 8>(a, acc, nfold, st);
+    else if (g->m == 8 && g->nn == 4) launch_fold<8, 4>(a, acc, nfold, st);
+    else launch_fold<8, 8>(a, acc, nfold, st);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
@@ -1074,7 +1134,7 @@ void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *x
     d.img_s = (const int *)g->img_s.p;
     d.slot_of = (const int *)g->slot_of.p;
     d.nslots = (const int *)g->nslots.p;
-    d.fj = (float4 *)l->fj.p;
+    d.fj = (float *)l->fj.p;
     d.fi = (float4 *)l->fi.p;
     d.jstart = (const int *)l->jstart.p;
     d.jpos = (const int *)l->jrank.p;

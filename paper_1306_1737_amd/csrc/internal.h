@@ -62,6 +62,7 @@ struct nb_ctx {
     int *d_flags = nullptr;     // latched kernel errors
     int *h_pinned = nullptr;    // pinned host scratch (16 ints)
     mxn::DevBuf partials;       // per-work-item energy/virial partials
+    mxn::DevBuf blockpart;      // sums of the partials over contiguous shares of the work items
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
     int search_parts = 0;   // 0: chosen from the number of i-clusters
@@ -111,9 +112,9 @@ struct nb_list {
     // entry's rank among the j-cluster's entries (jrank_canon: the fill pass's
     // ranks before a distance sort)
     mxn::DevBuf jcount, jstart, jrank, jrank_canon;
-    // force-call buffers: float4 j-force per (row, j-particle), rows grouped by
-    // j-cluster, and i-force per (work item, i-particle); summed per cluster
-    // after the force kernel
+    // force-call buffers: j-force (x, y, z) per (row, j-particle), rows grouped
+    // by j-cluster, and float4 i-force per (work item, i-particle); summed per
+    // cluster after the force kernel
     mxn::DevBuf fj, fi;
     int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
     int resv_nci = 0;          // i-cluster capacity of the reserved layout

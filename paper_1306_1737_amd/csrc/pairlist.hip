@@ -654,7 +654,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         int rc = ensure(l->jcount, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->jstart, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->jrank, (size_t)l->cap_entries * 4);
-        rc = rc ? rc : ensure(l->fj, (size_t)l->cap_entries * g->nn * 16);
+        rc = rc ? rc : ensure(l->fj, (size_t)l->cap_entries * g->nn * 12);
         rc = rc ? rc : ensure(l->fi, (size_t)l->cap_items * g->m * 16);
         if (rc) return rc;
         MXN_HIP(hipMemsetAsync(l->jcount.p, 0, (size_t)(njc + 1) * 4, st));
