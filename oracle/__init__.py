@@ -9,6 +9,8 @@ no code with it; the only common module is `synth` (seeded input generation).
   exclusions with the correction still applied, Sec. 2.4 and 3.2).
 * `grid_dims`, `grid_sort`, `pairlist`: FP32 canonical clustering and
   cluster-pair list (Sec. 2.3, cluster-pair search pseudocode; Sec. 2.4 masks).
+* `gather`, `prune`: the second stage of a two-stage list (Sec. 2.3: box-only
+  search, then a particle-distance prune), at positions of a later time.
 * `recount`: exact missed-pair energy after displacements (Sec. 5, appendix).
 * `drift` (module): the appendix's analytic drift bound (with its V'' term
   corrected) and its numerical quadrature.
@@ -54,6 +56,7 @@ def _lib():
         _h = ctypes.CDLL(_LIB)
         _h.oracle_pairlist.restype = ctypes.c_long
         _h.oracle_recount.restype = ctypes.c_long
+        _h.oracle_prune.restype = ctypes.c_long
     return _h
 
 
@@ -149,6 +152,27 @@ def pairlist(grid, box, rlist, rbb, excl_off, excl_idx, ci_begin=0, ci_end=None)
         if tot <= cap:
             return out[:tot]
         cap = int(tot)
+
+
+def gather(grid, xyz_now, box):
+    """Slot positions (n_slots x 3, FP32) at new coordinates, each atom in its build-time image."""
+    xyz = _c(xyz_now, np.float32); box = _c(box, np.float64)
+    img = _c(grid["img"], np.int32); slot_of = _c(grid["slot_of"], np.int32)
+    xs = np.zeros((grid["n_slots"], 3), np.float32)
+    _lib().oracle_gather(ctypes.c_int(xyz.shape[0]), _p(xyz, ctypes.c_float), _p(img, ctypes.c_int),
+                         _p(slot_of, ctypes.c_int), _p(box, ctypes.c_double), _p(xs, ctypes.c_float))
+    return xs
+
+
+def prune(grid, xs_now, box, entries, r):
+    """Entries of a list with some real particle pair within r at slot positions xs_now (Sec. 2.3 prune)."""
+    xs = _c(xs_now, np.float32); perm = _c(grid["perm"], np.int32); box = _c(box, np.float64)
+    ent = np.ascontiguousarray(entries, dtype=ENTRY_DTYPE)
+    out = np.zeros(max(len(ent), 1), ENTRY_DTYPE)
+    k = _lib().oracle_prune(ctypes.c_int(grid["m"]), ctypes.c_int(grid["n"]), _p(xs, ctypes.c_float),
+                            _p(perm, ctypes.c_int), _p(box, ctypes.c_double), ent.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.c_long(len(ent)), ctypes.c_float(r), out.ctypes.data_as(ctypes.c_void_p))
+    return out[:k]
 
 
 def recount(xyz0, xyzt, q, typ, box, excl_off, excl_idx, c6c12, rc, beta, coulomb_f, m, n_, rl, c_bb, db, nb):

@@ -426,6 +426,64 @@ long oracle_pairlist(int n_slots, int M, int N, const float *xs, const int *perm
 }
 
 /* ------------------------------------------------------------------------- */
+/* 3b. Two-stage list: prune of a cluster-pair list at given positions       */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Sec. 2.3: the list can be built from bounding boxes alone (rbb >= rlist in
+ * oracle_pairlist), and the cluster pairs whose particles are all beyond a
+ * radius are then removed with a particle-distance test.  Positions at a
+ * later time keep the atoms' build-time images (the pair list's shifts are
+ * fixed for its lifetime): slot position = x - (float)k * L in FP32, k the
+ * image of oracle_grid_sort.
+ */
+void oracle_gather(int n, const float *xyz, const int *img, const int *slot_of, const double box[3], float *xs_now) {
+    float Lf[3] = {(float)box[0], (float)box[1], (float)box[2]};
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            volatile float kl = (float)img[3 * i + a] * Lf[a];
+            volatile float x = xyz[3 * i + a] - kl;
+            xs_now[3 * slot_of[i] + a] = x;
+        }
+}
+
+/*
+ * Keep an entry (ci, s, cj) iff some real particle a of ci and real b of cj
+ * have r2 < r^2, with r2 formed exactly as in the search's particle test
+ * (i moved by the shift, separately rounded FP32 operations); exclusions
+ * and the half-list triangle do not enter, as in that test.  Entries keep
+ * their order and masks.  Returns the number kept.
+ */
+long oracle_prune(int M, int N, const float *xs, const int *perm, const double box[3], const oracle_entry *in,
+                  long n_in, float r, oracle_entry *out) {
+    float Lf[3] = {(float)box[0], (float)box[1], (float)box[2]};
+    volatile float r2v = r * r;
+    float r2 = r2v;
+    long kept = 0;
+    for (long e = 0; e < n_in; ++e) {
+        int ci = in[e].ci, cj = in[e].cj, s = in[e].shift;
+        int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
+        float sv[3];
+        for (int a = 0; a < 3; ++a) sv[a] = (float)sh[a] * Lf[a];
+        int keep = 0;
+        for (int a = 0; a < M && !keep; ++a) {
+            int sa = ci * M + a;
+            if (perm[sa] < 0) continue;
+            float xa[3];
+            for (int k = 0; k < 3; ++k) { volatile float t = xs[3 * sa + k] + sv[k]; xa[k] = t; }
+            for (int b = 0; b < N && !keep; ++b) {
+                int sb = cj * N + b;
+                if (perm[sb] < 0) continue;
+                volatile float dx = xa[0] - xs[3 * sb], dy = xa[1] - xs[3 * sb + 1], dz = xa[2] - xs[3 * sb + 2];
+                if (sq_sum3(dx, dy, dz) < r2) keep = 1;
+            }
+        }
+        if (keep) out[kept++] = in[e];
+    }
+    return kept;
+}
+
+/* ------------------------------------------------------------------------- */
 /* 4. Exact missed-pair recount (Verlet-buffer study, Sec. 5 and appendix)   */
 /* ------------------------------------------------------------------------- */
 
