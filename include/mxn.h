@@ -172,6 +172,31 @@ int nb_pairlist_build(nb_ctx *ctx, const nb_grid *grid, float rlist, float rbb, 
                       const int *excl_idx, int flags, nb_list **list);
 void nb_list_free(nb_list *list);
 
+/*
+ * Second stage of a two-stage list (Sec. 2.3: a list built from bounding
+ * boxes, then cluster pairs whose particles are all beyond a radius removed
+ * with a particle-distance test, done on the GPU).  `*inner` receives the
+ * entries of `outer` that hold a pair of real particles closer than r at the
+ * positions xyzq_now, the i-particle moved by the entry's image shift; the
+ * test is the search's own FP32 particle test (exclusions and the half-list
+ * triangle do not enter it), so a list built with rbb = rlist and pruned at
+ * rlist at its build positions equals the one-stage list built with rbb = 0.
+ * Kept entries keep their order, masks and regions; `*inner` is a complete
+ * list for nb_forces on outer's grid (same lifetime rules as outer).  With r
+ * at least rc plus the distance any pair can close in until the next prune,
+ * forces on the pruned list equal those on the outer one; a rolling prune
+ * every few steps lets the outer list (and its search) live longer.
+ *
+ *   outer     a list built on the current sort of its grid; not modified
+ *   xyzq_now  DEVICE float4[n], caller's order, the same array nb_forces takes
+ *   r         prune radius (nm), > 0
+ *   inner     in/out: NULL creates, otherwise reused; must not be outer
+ * Asynchronous (no host synchronisation, capturable in a graph).  An outer
+ * list that overflowed gives an inner list that reports NB_ERR_OVERFLOW at
+ * nb_sync.  Non-finite positions are reported as by nb_forces.
+ */
+int nb_pairlist_prune(nb_ctx *ctx, const nb_list *outer, const float *xyzq_now, float r, nb_list **inner);
+
 /* Synchronous.  Number of cluster-pair entries and force work items. */
 int nb_list_info(nb_list *list, long *n_entries, long *n_items);
 

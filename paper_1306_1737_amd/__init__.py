@@ -28,7 +28,7 @@ NB_BUFFER_ANALYTIC, NB_BUFFER_MLP, NB_BUFFER_AUTO = 0, 1, 2
 EXPORTS = [
     "nb_create", "nb_destroy", "nb_set_stream", "nb_sync", "nb_last_error",
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
-    "nb_pairlist_build", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
+    "nb_pairlist_build", "nb_pairlist_prune", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
     "nb_list_stats", "nb_set_force_variant", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
@@ -96,6 +96,7 @@ def lib():
             "nb_grid_info": ([vp, ctypes.POINTER(nb_grid_info_t)], i),
             "nb_grid_export": ([vp, vp, vp, vp, vp, vp], i),
             "nb_pairlist_build": ([vp, vp, f, f, vp, vp, i, pvp], i), "nb_list_free": ([vp], None),
+            "nb_pairlist_prune": ([vp, vp, vp, f, pvp], i),
             "nb_list_info": ([vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)], i),
             "nb_list_export_canonical": ([vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_long)], i),
             "nb_forces": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), u, vp, vp, vp], i),
@@ -227,6 +228,13 @@ def nb_pairlist_build(ctx, grid, rlist, rbb, excl_off, excl_idx, flags=0, lst=No
     h = lst if lst is not None else ctypes.c_void_p()
     _check(lib().nb_pairlist_build(ctx, grid, float(rlist), float(rbb), _ptr(excl_off), _ptr(excl_idx), int(flags),
                                    ctypes.byref(h)))
+    return h
+
+
+def nb_pairlist_prune(ctx, outer, xyzq_now, r, inner=None):
+    """Second stage of a two-stage list: the entries of `outer` with a particle pair within r at xyzq_now."""
+    h = inner if inner is not None else ctypes.c_void_p()
+    _check(lib().nb_pairlist_prune(ctx, outer, _ptr(xyzq_now), float(r), ctypes.byref(h)))
     return h
 
 

@@ -361,6 +361,42 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     return NB_OK;
 }
 
+int nb_pairlist_prune(nb_ctx *c, const nb_list *outer, const float *xyzq_now, float r, nb_list **inner) {
+    if (!c || !outer || !xyzq_now || !inner) return fail(NB_ERR_ARG, "nb_pairlist_prune: null argument");
+    if (outer->ctx != c) return fail(NB_ERR_STATE, "nb_pairlist_prune: list belongs to another context");
+    if (*inner == outer) return fail(NB_ERR_ARG, "nb_pairlist_prune: the pruned list must be another handle");
+    if (*inner && (*inner)->ctx != c) return fail(NB_ERR_STATE, "nb_pairlist_prune: list belongs to another context");
+    if (!(r > 0.0f) || !std::isfinite(r)) return fail(NB_ERR_ARG, "nb_pairlist_prune: r must be > 0");
+    const nb_grid *g = outer->grid;
+    if (!g || outer->resv_parts == 0) return fail(NB_ERR_STATE, "nb_pairlist_prune: the outer list was never built");
+    if (outer->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, "nb_pairlist_prune: the outer list was built before its grid's last sort");
+    MXN_HIP(hipSetDevice(c->device));
+    nb_list *l = *inner;
+    bool fresh = false;
+    if (!l) {
+        l = new (std::nothrow) nb_list();
+        if (!l) return fail(NB_ERR_OOM, "nb_pairlist_prune: host allocation");
+        l->ctx = c;
+        fresh = true;
+    }
+    int rc;
+    {
+        ScopedTimer tm(c, NB_TIMER_PAIRLIST);
+        rc = launch_gather(c, g, xyzq_now);
+        rc = rc ? rc : launch_prune(l, outer, r);
+    }
+    if (rc != NB_OK) {
+        if (fresh) {
+            list_release(l);
+            delete l;
+        }
+        return rc;
+    }
+    *inner = l;
+    return NB_OK;
+}
+
 void nb_list_free(nb_list *l) {
     if (!l) return;
     hipSetDevice(l->ctx->device);

@@ -202,6 +202,10 @@ int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *x
                  unsigned long long *d_counts);
 // exclusive scan of n ints on one workgroup; writes out[0..n] (out[n] = total) and *total
 void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
+// second stage of a two-stage list: `in` gets outer's entries with a pair within r
+// at the grid's gathered positions (xs_now)
+int launch_prune(nb_list *in, const nb_list *outer, float r);
+int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now);
 // exclusive scan of in[0..n) into out[0..n] that leaves in[] zeroed
 void launch_scan_clear(int *in, int *out, int n, hipStream_t s);
 

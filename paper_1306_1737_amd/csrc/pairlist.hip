@@ -445,6 +445,89 @@ __device__ inline void jpos_body(const JPosArgs &a, int blk) {
 __global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x); }
 
 // --------------------------------------------------------------------------
+// Second stage of a two-stage list (Sec. 2.3: the list built from bounding
+// boxes, then cluster pairs whose particles are all beyond a radius removed
+// by a particle-distance test on the GPU).  One wavefront per region of the
+// outer list, one lane per entry: an entry is kept iff a real particle of
+// the i-cluster, moved by the entry's image shift, and a real particle of
+// the j-cluster are closer than r, formed with the search's own separately
+// rounded FP32 operations, at the gathered positions of the call.  Kept
+// entries keep their order, masks and region; like the fill pass, each takes
+// its rank within its j-cluster.
+struct PruneArgs {
+    const int *nslots;
+    const float4 *xs_now;
+    const int *perm;
+    const int *part_start;      // the regions (the outer list's layout)
+    const int *part_count_in;   // entries of the outer list per region
+    const int *totals_in;       // the outer list's totals: [1] items, [2] usable items
+    const nb_jentry *in;
+    int *part_count;            // kept entries per region
+    nb_jentry *out;
+    int *jcount, *jrank;
+    int *region_overflow;
+    float Lx, Ly, Lz, r2;
+    int nregions, parts;
+};
+
+template <int M, int N>
+__global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
+    const int lane = threadIdx.x & 63, g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= a.nregions) return;
+    // an overflowed outer list (items counted, none usable) is incomplete, and so is its prune
+    if (a.totals_in[2] == 0 && a.totals_in[1] > 0) {
+        if (lane == 0) {
+            a.part_count[g] = 0;
+            if (g == 0) atomicOr(a.region_overflow, 1);
+        }
+        return;
+    }
+    const int ci = g / a.parts;
+    if (ci >= *a.nslots / M) {
+        if (lane == 0) a.part_count[g] = 0;
+        return;
+    }
+    const int start = a.part_start[g];
+    const int n_in = min(a.part_count_in[g], a.part_start[g + 1] - start);
+    float ix[M], iy[M], iz[M];
+    unsigned ireal = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const float4 p = a.xs_now[ci * M + k];
+        ix[k] = p.x; iy[k] = p.y; iz[k] = p.z;
+        ireal |= (a.perm[ci * M + k] >= 0 ? 1u : 0u) << k;
+    }
+    int cnt = 0;
+    for (int e0 = 0; e0 < n_in; e0 += 64) {
+        const int e = e0 + lane;
+        const bool valid = e < n_in;
+        const nb_jentry en = a.in[start + (valid ? e : 0)];
+        const int s = en.shift;
+        const float sx = (float)(s / 9 - 1) * a.Lx, sy = (float)((s / 3) % 3 - 1) * a.Ly,
+                    sz = (float)(s % 3 - 1) * a.Lz;
+        bool keep = false;
+        for (int b = 0; valid && b < N && !keep; ++b) {
+            const int sb = en.cj * N + b;
+            if (a.perm[sb] < 0) continue;
+            const float4 pj = a.xs_now[sb];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const float px = ix[k] + sx, py = iy[k] + sy, pz = iz[k] + sz;
+                keep |= ((ireal >> k) & 1u) && sq3(px - pj.x, py - pj.y, pz - pj.z) < a.r2;
+            }
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (keep) {
+            const int pos = start + cnt + __popcll(bal & ((1ull << lane) - 1ull));
+            a.out[pos] = en;
+            a.jrank[pos] = atomicAdd(a.jcount + en.cj, 1);
+        }
+        cnt += __popcll(bal);
+    }
+    if (lane == 0) a.part_count[g] = cnt;
+}
+
+// --------------------------------------------------------------------------
 // Batched rebuild of many replicas' lists (the fill pass into the regions the
 // replicas' last synchronous builds sized), one launch per stage; a
 // workgroup finds its replica by binary search in the stage's prefix of
@@ -543,6 +626,24 @@ static JPosArgs make_jpos(const nb_list *l) {
     v.jstart = (const int *)l->jstart.p;
     v.jrank = (int *)l->jrank.p;
     return v;
+}
+
+// item offsets per region (totals[0] = entries, totals[1] = items) and the work items
+static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
+    const int pe = item_entries(l->grid->nn);
+    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, pe, (int *)l->totals.p + 1,
+                     (int *)l->totals.p, st);
+    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, pe, (const int *)l->part_count.p,
+                                                  (const int *)l->part_start.p, (const int *)l->part_istart.p,
+                                                  l->cap_items, (int4 *)l->items.p);
+}
+
+// usable item count (overflow check) and the rows of the j-cluster view
+static void finish_view(nb_list *l, hipStream_t st) {
+    const nb_grid *g = l->grid;
+    k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, l->ctx->d_flags);
+    launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
+    k_jpos<<<(int)((l->cap_items + 3) / 4), 256, 0, st>>>(make_jpos(l));
 }
 
 size_t list_job_size() { return sizeof(ListJob); }
@@ -682,21 +783,77 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
-    // item offsets per region; totals[0] = entries found, totals[1] = items
-    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, item_entries(g->nn),
-                     (int *)l->totals.p + 1, (int *)l->totals.p, st);
-    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, item_entries(g->nn), (const int *)l->part_count.p,
-                                                  (const int *)l->part_start.p, (const int *)l->part_istart.p,
-                                                  l->cap_items, (int4 *)l->items.p);
+    finish_items(l, nregions, parts, st);
     if (by_distance)
         k_sort_entries<<<nregions, 64, 0, st>>>((const int *)l->part_start.p, (const int *)l->part_count.p,
                                                 (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
                                                 (nb_jentry *)l->entries.p, (const int *)l->jrank_canon.p,
                                                 (int *)l->jrank.p);
-    k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, ctx->d_flags);
-    // rows of the j-cluster view
-    launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
-    k_jpos<<<(int)((l->cap_items + 3) / 4), 256, 0, st>>>(make_jpos(l));
+    finish_view(l, st);
+    MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+int launch_prune(nb_list *in, const nb_list *outer, float r) {
+    const nb_grid *g = outer->grid;
+    nb_ctx *ctx = in->ctx;
+    hipStream_t st = ctx->stream;
+    const int nregions = outer->resv_nci * outer->resv_parts;
+    // the outer list's layout, with buffers of its capacity; new counters start cleared
+    const long njc = g->slots_cap / g->nn;
+    const size_t nreg = (size_t)outer->resv_nci * kMaxSearchParts + 1;
+    void *old_jc = in->jcount.p, *old_tot = in->totals.p;
+    int rc = ensure(in->part_count, nreg * 4);
+    rc = rc ? rc : ensure(in->part_start, nreg * 4);
+    rc = rc ? rc : ensure(in->part_istart, nreg * 4);
+    rc = rc ? rc : ensure(in->totals, 16);
+    rc = rc ? rc : ensure(in->entries, (size_t)outer->cap_entries * sizeof(nb_jentry));
+    rc = rc ? rc : ensure(in->items, (size_t)outer->cap_items * sizeof(int4));
+    rc = rc ? rc : ensure(in->jcount, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(in->jstart, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(in->jrank, (size_t)outer->cap_entries * 4);
+    rc = rc ? rc : ensure(in->fj, (size_t)outer->cap_entries * g->nn * 12);
+    rc = rc ? rc : ensure(in->fi, (size_t)outer->cap_items * g->m * 16);
+    if (rc) return rc;
+    if (in->jcount.p != old_jc || in->resv_nci != outer->resv_nci)
+        MXN_HIP(hipMemsetAsync(in->jcount.p, 0, (size_t)(njc + 1) * 4, st));
+    if (in->totals.p != old_tot) MXN_HIP(hipMemsetAsync(in->totals.p, 0, 16, st));
+    in->grid = g;
+    in->grid_generation = outer->grid_generation;
+    in->rlist = r;
+    in->rbb = outer->rbb;
+    in->cap_entries = outer->cap_entries;
+    in->cap_items = outer->cap_items;
+    in->resv_parts = outer->resv_parts;
+    in->resv_nci = outer->resv_nci;
+    in->last_entries = outer->last_entries;
+    MXN_HIP(hipMemcpyAsync(in->part_start.p, outer->part_start.p, (size_t)(nregions + 1) * 4, hipMemcpyDeviceToDevice,
+                           st));
+    PruneArgs a{};
+    a.nslots = (const int *)g->nslots.p;
+    a.xs_now = (const float4 *)g->xs_now.p;
+    a.perm = (const int *)g->perm.p;
+    a.part_start = (const int *)outer->part_start.p;
+    a.part_count_in = (const int *)outer->part_count.p;
+    a.totals_in = (const int *)outer->totals.p;
+    a.in = (const nb_jentry *)outer->entries.p;
+    a.part_count = (int *)in->part_count.p;
+    a.out = (nb_jentry *)in->entries.p;
+    a.jcount = (int *)in->jcount.p;
+    a.jrank = (int *)in->jrank.p;
+    a.region_overflow = (int *)in->totals.p + 3;
+    a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
+    volatile float r2 = r * r;
+    a.r2 = r2;
+    a.nregions = nregions;
+    a.parts = outer->resv_parts;
+    const int nb = (nregions + 3) / 4;
+    if (g->m == 4 && g->nn == 4) k_prune<4, 4><<<nb, 256, 0, st>>>(a);
+    else if (g->m == 4 && g->nn == 8) k_prune<4, 8><<<nb, 256, 0, st>>>(a);
+    else if (g->m == 8 && g->nn == 4) k_prune<8, 4><<<nb, 256, 0, st>>>(a);
+    else k_prune<8, 8><<<nb, 256, 0, st>>>(a);
+    finish_items(in, nregions, outer->resv_parts, st);
+    finish_view(in, st);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
