@@ -183,7 +183,13 @@ def main():
     ap.add_argument("--variant", default="direct", choices=["direct", "compact"])
     ap.add_argument("--list-order", default="canonical", choices=["canonical", "distance"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="production", choices=["production", "batched"])
+    ap.add_argument("--workload", default="production", choices=["production", "batched", "twostage"])
+    ap.add_argument("--outer-rlist", type=float, default=0.0, metavar="NM",
+                    help="twostage: radius of the box-only outer list (default: the workload's rlist)")
+    ap.add_argument("--outer-nstlist", type=int, default=0, metavar="STEPS",
+                    help="twostage: lifetime of the outer list (default: the workload's nstlist)")
+    ap.add_argument("--prune-every", type=int, default=2, metavar="STEPS", help="twostage: rolling prune interval")
+    ap.add_argument("--r-inner", type=float, default=1.05, metavar="NM", help="twostage: rolling prune radius")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates memory-traffic counters) and exit")
     args = ap.parse_args()
@@ -205,6 +211,8 @@ def main():
         if args.shape == "8x8":
             args.shape = "auto"
         return bench_batched(args)
+    if args.workload == "twostage":
+        return bench_twostage(args)
 
     import numpy as np
     import torch
@@ -301,6 +309,106 @@ def main():
         result["cpu_baseline"] = cpu_baseline(box, w)
     mxn.nb_list_free(state["lst"])
     mxn.nb_grid_free(state["grid"])
+    mxn.nb_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+def bench_twostage(args):
+    """Two-stage list on the production box (Sec. 2.3's box-only search plus GPU prune): time per force step of
+    (one-stage) the production cycle, (two-stage) a box-only search pruned at rlist once per build, and
+    (rolling) a box-only outer list of its own radius and lifetime pruned every few steps at an inner radius.
+    Every variant runs the same ballistic trajectory; the pairs within rc that each one finds per step are
+    counted (nb_list_stats), so a variant that loses pairs shows it."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1737_amd as mxn
+
+    w = synth.PRODUCTION
+    m, n = (int(v) for v in args.shape.split("x"))
+    r_out = args.outer_rlist or w.rlist
+    n_out = args.outer_nstlist or w.nstlist
+    P = max(1, args.prune_every)
+    print("[bench] generating %d waters" % w.n_mol, file=sys.stderr, flush=True)
+    box = synth.water_box(w.n_mol, w.L, seed=1306)
+    vel = synth.velocities(box.mass, w.T, seed=1306)
+    xs = synth.free_flight(box.xyz, vel, w.dt, max(w.nstlist, n_out))
+    dev = torch.device("cuda:0")
+    xq = [torch.from_numpy(box.xyzq(x)).to(dev) for x in xs]
+    typ = torch.from_numpy(box.type).to(dev)
+    eo = torch.from_numpy(box.excl_off).to(dev)
+    ei = torch.from_numpy(box.excl_idx).to(dev)
+    lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+    f = torch.zeros((box.n, 3), dtype=torch.float32, device=dev)
+    e = torch.zeros(2, dtype=torch.float64, device=dev)
+    ctx = mxn.nb_create(0)
+    params = mxn.make_params(w.rc, w.beta, synth.COULOMB_F, lj)
+    st = {"grid": None, "lst": None, "inner": None}
+
+    def cycle(kind, list_flags, stats=None):
+        st["grid"] = mxn.nb_grid_sort(ctx, box.box, xq[0], typ, (m, n), st["grid"])
+        if kind == "one-stage":
+            st["lst"] = mxn.nb_pairlist_build(ctx, st["grid"], w.rlist, -1.0, eo, ei, list_flags, st["lst"])
+            steps, use = w.nstlist, (lambda k: st["lst"])
+        elif kind == "two-stage":
+            st["lst"] = mxn.nb_pairlist_build(ctx, st["grid"], w.rlist, w.rlist, eo, ei, list_flags, st["lst"])
+            st["inner"] = mxn.nb_pairlist_prune(ctx, st["lst"], xq[0], w.rlist, st["inner"])
+            steps, use = w.nstlist, (lambda k: st["inner"])
+        else:
+            st["lst"] = mxn.nb_pairlist_build(ctx, st["grid"], r_out, r_out, eo, ei, list_flags, st["lst"])
+            steps, use = n_out, (lambda k: st["inner"])
+        for k in range(steps):
+            if kind == "rolling" and k % P == 0:
+                st["inner"] = mxn.nb_pairlist_prune(ctx, st["lst"], xq[k], args.r_inner, st["inner"])
+            mxn.nb_forces(ctx, st["grid"], use(k), xq[k], params, mxn.NB_ENERGY, f, e)
+            if stats is not None:
+                c = mxn.nb_list_stats(ctx, st["grid"], use(k), xq[k], w.rc)
+                stats.append((c[0], c[2] + c[3]))
+        return steps
+
+    out = {}
+    for kind in ("one-stage", "two-stage", "rolling"):
+        print("[bench] %s" % kind, file=sys.stderr, flush=True)
+        cycle(kind, 0)                      # sizes the list storage (one synchronisation)
+        mxn.nb_sync(ctx)
+        stats = []
+        cycle(kind, mxn.NB_LIST_ASYNC, stats)
+        for _ in range(max(0, args.warmup - 1)):
+            cycle(kind, mxn.NB_LIST_ASYNC)
+        mxn.nb_sync(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        calls = 0
+        for _ in range(args.steps):
+            calls += cycle(kind, mxn.NB_LIST_ASYNC)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mxn.nb_sync(ctx)
+        out[kind] = {"ms_per_force_step": (t1 - t0) * 1e3 / calls, "force_steps": calls,
+                     "listed_pairs_per_step": float(np.mean([s[0] for s in stats])),
+                     "pairs_within_rc": [int(s[1]) for s in stats]}
+        for h in ("inner", "lst"):
+            if st[h] is not None:
+                mxn.nb_list_free(st[h])
+                st[h] = None
+        mxn.nb_grid_free(st["grid"])
+        st["grid"] = None
+    base = out["one-stage"]
+    for kind, r in out.items():   # pairs within rc each variant finds, against the one-stage list, per step
+        k = min(len(r["pairs_within_rc"]), len(base["pairs_within_rc"]))
+        r["pairs_within_rc_minus_one_stage"] = [a - b for a, b in zip(r["pairs_within_rc"][:k],
+                                                                        base["pairs_within_rc"][:k])]
+    ms = out["rolling"]["ms_per_force_step"]
+    inr = float(np.mean(out["rolling"]["pairs_within_rc"]))
+    result = {
+        "metric": "atom-pair interactions/s within rc, two-stage list", "value": inr / (ms * 1e-3),
+        "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name + "-twostage", "shape": "%dx%d" % (m, n), "rc": w.rc, "rlist": w.rlist,
+                   "outer_rlist": r_out, "outer_nstlist": n_out, "prune_every": P, "r_inner": args.r_inner},
+        "variants": out,
+    }
     mxn.nb_destroy(ctx)
     print(json.dumps(result), flush=True)
 

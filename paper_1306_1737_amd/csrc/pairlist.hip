@@ -419,30 +419,12 @@ __global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_b
 // j-cluster view of a list.  The force kernels store each entry's j-forces
 // (instead of adding them to memory with atomics) in a row of a buffer whose
 // rows are grouped by j-cluster, so that the reduction reads each j-cluster's
-// rows contiguously.  The fill pass takes each written entry's rank among its
-// j-cluster's entries from a counter per j-cluster; after the build an
-// exclusive scan of the counters (which clears them for the next build)
-// gives each j-cluster's first row, and this pass turns every usable entry's
-// rank into its row.  The row order within a j-cluster depends on timing; the
+// rows contiguously.  The fill pass (and the prune) take each written entry's
+// rank among its j-cluster's entries from a counter per j-cluster; after the
+// build an exclusive scan of the counters (which clears them for the next
+// build) gives each j-cluster's first row, and an entry's row is that plus
+// its rank.  The row order within a j-cluster depends on timing; the
 // reduction sums in fixed point, so the forces do not.
-struct JPosArgs {
-    const int *totals;   // [2]: usable items
-    const int4 *items;
-    const nb_jentry *entries;
-    const int *jstart;   // first row of each j-cluster
-    int *jrank;          // rank in, row out
-};
-
-// one wavefront per work item, one lane per entry (items hold at most 64)
-__device__ inline void jpos_body(const JPosArgs &a, int blk) {
-    const int t = blk * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (t >= a.totals[2]) return;
-    const int4 it = a.items[t];
-    const int e = it.y + lane;
-    if (e < it.z) a.jrank[e] += a.jstart[a.entries[e].cj];
-}
-
-__global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x); }
 
 // --------------------------------------------------------------------------
 // Second stage of a two-stage list (Sec. 2.3: the list built from bounding
@@ -505,17 +487,25 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         const int s = en.shift;
         const float sx = (float)(s / 9 - 1) * a.Lx, sy = (float)((s / 3) % 3 - 1) * a.Ly,
                     sz = (float)(s % 3 - 1) * a.Lz;
-        bool keep = false;
-        for (int b = 0; valid && b < N && !keep; ++b) {
+        // the entry's N j-particles loaded together, then all M x N tests (no early exit: the
+        // wavefront waits for its slowest lane anyway)
+        float4 pj[N];
+        bool jreal[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
             const int sb = en.cj * N + b;
-            if (a.perm[sb] < 0) continue;
-            const float4 pj = a.xs_now[sb];
+            pj[b] = a.xs_now[sb];
+            jreal[b] = a.perm[sb] >= 0;
+        }
+        bool keep = false;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 const float px = ix[k] + sx, py = iy[k] + sy, pz = iz[k] + sz;
-                keep |= ((ireal >> k) & 1u) && sq3(px - pj.x, py - pj.y, pz - pj.z) < a.r2;
+                keep |= jreal[b] && ((ireal >> k) & 1u) && sq3(px - pj[b].x, py - pj[b].y, pz - pj[b].z) < a.r2;
             }
-        }
+        keep &= valid;
         const unsigned long long bal = __ballot(keep);
         if (keep) {
             const int pos = start + cnt + __popcll(bal & ((1ull << lane) - 1ull));
@@ -535,7 +525,6 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
 
 struct ListJob {
     SearchArgs a;
-    JPosArgs jp;
     int nregions, per_item;
     int *part_count, *part_start, *part_istart, *totals;
     int4 *items;
@@ -543,7 +532,7 @@ struct ListJob {
     int *flags;
 };
 
-enum { LS_SEARCH, LS_ITEMS, LS_JPOS, LS_NSTAGES };
+enum { LS_SEARCH, LS_ITEMS, LS_NSTAGES };
 
 __device__ inline int job_of(const int *off, int n, int b) {
     int lo = 0, hi = n - 1;   // last r with off[r] <= b
@@ -573,10 +562,6 @@ __global__ void kb_finalize(const ListJob *J) {
     finalize_body(j.totals, j.cap_items, j.flags);
 }
 
-__global__ __launch_bounds__(256) void kb_jpos(const ListJob *J, const int *off, int n) {
-    const int r = job_of(off, n, blockIdx.x);
-    jpos_body(J[r].jp, blockIdx.x - off[r]);
-}
 
 template <int M, int N>
 void run(nb_list *l, SearchArgs &a, bool fill, int nblocks, hipStream_t st) {
@@ -618,15 +603,6 @@ static SearchArgs make_search(const nb_list *l, const int *excl_off, const int *
     return a;
 }
 
-static JPosArgs make_jpos(const nb_list *l) {
-    JPosArgs v{};
-    v.totals = (const int *)l->totals.p;
-    v.items = (const int4 *)l->items.p;
-    v.entries = (const nb_jentry *)l->entries.p;
-    v.jstart = (const int *)l->jstart.p;
-    v.jrank = (int *)l->jrank.p;
-    return v;
-}
 
 // item offsets per region (totals[0] = entries, totals[1] = items) and the work items
 static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
@@ -638,12 +614,11 @@ static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
                                                   l->cap_items, (int4 *)l->items.p);
 }
 
-// usable item count (overflow check) and the rows of the j-cluster view
+// usable item count (overflow check) and the first row of each j-cluster
 static void finish_view(nb_list *l, hipStream_t st) {
     const nb_grid *g = l->grid;
     k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, l->ctx->d_flags);
     launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
-    k_jpos<<<(int)((l->cap_items + 3) / 4), 256, 0, st>>>(make_jpos(l));
 }
 
 size_t list_job_size() { return sizeof(ListJob); }
@@ -656,7 +631,6 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.a = make_search(l, excl_off, excl_idx);
     j.a.jcount = (int *)l->jcount.p;
     j.a.jrank = (int *)l->jrank.p;
-    j.jp = make_jpos(l);
     j.a.parts = l->resv_parts;
     j.a.entries = (nb_jentry *)l->entries.p;
     j.a.keys = nullptr;
@@ -679,7 +653,6 @@ void list_job_blocks(const nb_list *l, int *blocks_per_stage) {
     const long nreg = (long)l->resv_nci * l->resv_parts;
     blocks_per_stage[LS_SEARCH] = (int)((nreg + 3) / 4);
     blocks_per_stage[LS_ITEMS] = (int)((nreg + 255) / 256);
-    blocks_per_stage[LS_JPOS] = (int)((l->cap_items + 3) / 4);
 }
 
 int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
@@ -694,7 +667,6 @@ int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const
     kb_items<<<total[LS_ITEMS], 256, 0, st>>>(J, off + LS_ITEMS * stride, n_rep);
     kb_finalize<<<n_rep, 64, 0, st>>>(J);
     launch_scan_batch(scans + n_rep, n_rep, st);
-    kb_jpos<<<total[LS_JPOS], 256, 0, st>>>(J, off + LS_JPOS * stride, n_rep);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
