@@ -7,6 +7,7 @@ no code with it; the only common module is `synth` (seeded input generation).
 * `forces`, `forces_subset`: FP64 pair sums by definition (Eq. 1 LJ, Eq. 2
   Coulomb with the Ewald real-space correction g(r) = d/dr[erf(beta r)/r],
   exclusions with the correction still applied, Sec. 2.4 and 3.2).
+* `forces_rf`: the same with the reaction-field correction g(r) = -2 k r.
 * `grid_dims`, `grid_sort`, `pairlist`: FP32 canonical clustering and
   cluster-pair list (Sec. 2.3, cluster-pair search pseudocode; Sec. 2.4 masks).
 * `gather`, `prune`: the second stage of a two-stage list (Sec. 2.3: box-only
@@ -85,6 +86,24 @@ def forces(xyz, q, typ, box, excl_off, excl_idx, c6c12, rc, beta, coulomb_f, shi
                                  _p(f, ctypes.c_double), _p(e, ctypes.c_double), _p(v, ctypes.c_double))
     if rcode != 0:
         raise MemoryError("oracle_forces failed")
+    return f, e, v.reshape(3, 3)
+
+
+def forces_rf(xyz, q, typ, box, excl_off, excl_idx, c6c12, rc, eps_rf, coulomb_f, shift=True, mode="binned"):
+    """FP64 reaction-field forces, energies and virial (Eq. 2 with g(r) = -2 k r); eps_rf = 0: conducting."""
+    xyz = _c(xyz, np.float32); q = _c(q, np.float32); typ = _c(typ, np.int32)
+    box = _c(box, np.float64); eo = _c(excl_off, np.int32); ei = _c(excl_idx, np.int32)
+    nt, tab = _lj(c6c12)
+    n = xyz.shape[0]
+    f = np.zeros((n, 3)); e = np.zeros(2); v = np.zeros(9)
+    rcode = _lib().oracle_forces_rf(ctypes.c_int(n), _p(xyz, ctypes.c_float), _p(q, ctypes.c_float),
+                                    _p(typ, ctypes.c_int), _p(box, ctypes.c_double), _p(eo, ctypes.c_int),
+                                    _p(ei, ctypes.c_int), ctypes.c_int(nt), _p(tab, ctypes.c_double),
+                                    ctypes.c_double(rc), ctypes.c_double(eps_rf), ctypes.c_double(coulomb_f),
+                                    ctypes.c_int(int(shift)), ctypes.c_int(1 if mode == "binned" else 0),
+                                    _p(f, ctypes.c_double), _p(e, ctypes.c_double), _p(v, ctypes.c_double))
+    if rcode != 0:
+        raise MemoryError("oracle_forces_rf failed")
     return f, e, v.reshape(3, 3)
 
 

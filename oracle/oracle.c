@@ -47,6 +47,8 @@ typedef struct {
     int ntypes;
     const double *c6c12;     /* [ti][tj][2] = C6, C12 */
     int shift;               /* 1: potentials shifted to zero at rc */
+    int rf;                  /* 1: reaction field instead of Ewald (Eq. 2 with g(r) = -2 k r) */
+    double k_rf, c_rf;       /* reaction-field constant k and energy shift c */
 } oracle_params;
 
 static int is_excluded(const int *off, const int *idx, int a, int b) {
@@ -69,34 +71,59 @@ static int is_excluded(const int *off, const int *idx, int a, int b) {
  * Force-field-excluded pair within rc (Eq. 2 with e_ij = 0; the Ewald
  * correction is still applied, Sec. 2.4):
  *   F_i = f qi qj g(r) d/r,  V = -f qi qj erf(beta r)/r.
+ * Reaction field instead (Sec. 3.2, g(r) = -2 k r): F_i = [LJ + f qi qj (e/r^2
+ * - 2 k r)] d/r, V_C = f qi qj (e/r + k r^2 - c), with e = 1 for a
+ * non-excluded pair and 0 for an excluded one.
  */
 static void pair_term(const oracle_params *p, double qi, double qj, int ti, int tj, int excluded,
                       const double d[3], double fi[3], double *elj, double *ec, double vir[9]) {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (!(r2 < p->rc * p->rc)) return;
     double r = sqrt(r2);
-    double br = p->beta * r;
     double qq = p->f * qi * qj;
-    double gauss = 2.0 * p->beta / sqrt(M_PI) * exp(-br * br);
-    double g = gauss / r - erf(br) / r2;          /* d/dr [erf(beta r)/r] */
     double fr;                                    /* |F| along d/r, positive = repulsive */
-    if (excluded) {
-        fr = qq * g;
-        *ec += -qq * erf(br) / r;
-    } else {
-        double c6 = p->c6c12[2 * (ti * p->ntypes + tj)];
-        double c12 = p->c6c12[2 * (ti * p->ntypes + tj) + 1];
-        double r6 = r2 * r2 * r2;
-        fr = 12.0 * c12 / (r6 * r6 * r) - 6.0 * c6 / (r6 * r) + qq * (1.0 / r2 + g);
-        double vlj = c12 / (r6 * r6) - c6 / r6;
-        double vc = qq * erfc(br) / r;
-        if (p->shift) {
-            double rc6 = pow(p->rc, 6);
-            vlj -= c12 / (rc6 * rc6) - c6 / rc6;
-            vc -= qq * erfc(p->beta * p->rc) / p->rc;
+    if (p->rf) {
+        /* Reaction field (Eq. 2 with g(r) = -2 k r): |F| = qq (e/r^2 - 2 k r); the potential is
+         * qq (e/r + k r^2 - c) with c = 1/rc + k rc^2, so a non-excluded pair's is zero at rc */
+        double gk = -2.0 * p->k_rf * r;
+        if (excluded) {
+            fr = qq * gk;
+            *ec += qq * (p->k_rf * r2 - p->c_rf);
+        } else {
+            double c6 = p->c6c12[2 * (ti * p->ntypes + tj)];
+            double c12 = p->c6c12[2 * (ti * p->ntypes + tj) + 1];
+            double r6 = r2 * r2 * r2;
+            fr = 12.0 * c12 / (r6 * r6 * r) - 6.0 * c6 / (r6 * r) + qq * (1.0 / r2 + gk);
+            double vlj = c12 / (r6 * r6) - c6 / r6;
+            if (p->shift) {
+                double rc6 = pow(p->rc, 6);
+                vlj -= c12 / (rc6 * rc6) - c6 / rc6;
+            }
+            *elj += vlj;
+            *ec += qq * (1.0 / r + p->k_rf * r2 - p->c_rf);
         }
-        *elj += vlj;
-        *ec += vc;
+    } else {
+        double br = p->beta * r;
+        double gauss = 2.0 * p->beta / sqrt(M_PI) * exp(-br * br);
+        double g = gauss / r - erf(br) / r2;          /* d/dr [erf(beta r)/r] */
+        if (excluded) {
+            fr = qq * g;
+            *ec += -qq * erf(br) / r;
+        } else {
+            double c6 = p->c6c12[2 * (ti * p->ntypes + tj)];
+            double c12 = p->c6c12[2 * (ti * p->ntypes + tj) + 1];
+            double r6 = r2 * r2 * r2;
+            fr = 12.0 * c12 / (r6 * r6 * r) - 6.0 * c6 / (r6 * r) + qq * (1.0 / r2 + g);
+            double vlj = c12 / (r6 * r6) - c6 / r6;
+            double vc = qq * erfc(br) / r;
+            if (p->shift) {
+                double rc6 = pow(p->rc, 6);
+                vlj -= c12 / (rc6 * rc6) - c6 / rc6;
+                vc -= qq * erfc(p->beta * p->rc) / p->rc;
+            }
+            *elj += vlj;
+            *ec += vc;
+        }
     }
     for (int a = 0; a < 3; ++a) {
         double fa = fr * d[a] / r;
@@ -135,11 +162,11 @@ static void atom_sum(const oracle_params *p, int n, const float *xyz, const floa
  * independently over all of its partners, so Newton's third law is not built
  * in and the zero-net-force test is a real check.
  */
-int oracle_forces(int n, const float *xyz, const float *q, const int *type, const double L[3],
-                  const int *excl_off, const int *excl_idx, int ntypes, const double *c6c12,
-                  double rc, double beta, double coulomb_f, int shift, int mode,
-                  double *f, double *e, double *virial) {
-    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, shift};
+static int forces_impl(const oracle_params *pp, int n, const float *xyz, const float *q, const int *type,
+                       const double L[3], const int *excl_off, const int *excl_idx, int mode, double *f, double *e,
+                       double *virial) {
+    const oracle_params p = *pp;
+    const double rc = p.rc;
     double *ea = (double *)calloc((size_t)n * 2, sizeof(double));
     double *va = (double *)calloc((size_t)n * 9, sizeof(double));
     if (!ea || !va) { free(ea); free(va); return -1; }
@@ -216,12 +243,36 @@ int oracle_forces(int n, const float *xyz, const float *q, const int *type, cons
     return 0;
 }
 
+int oracle_forces(int n, const float *xyz, const float *q, const int *type, const double L[3],
+                  const int *excl_off, const int *excl_idx, int ntypes, const double *c6c12,
+                  double rc, double beta, double coulomb_f, int shift, int mode,
+                  double *f, double *e, double *virial) {
+    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, shift, 0, 0.0, 0.0};
+    return forces_impl(&p, n, xyz, q, type, L, excl_off, excl_idx, mode, f, e, virial);
+}
+
+/* Reaction-field constants (the paper gives g(r) = -2 k r with k a constant; the usual choice for a
+ * dielectric continuum eps_rf beyond rc): k = (eps_rf - 1) / ((2 eps_rf + 1) rc^3), eps_rf = 0 meaning a
+ * conducting boundary (k = 1 / (2 rc^3)); c = 1/rc + k rc^2. */
+static void rf_constants(double rc, double eps_rf, double *k, double *c) {
+    *k = eps_rf == 0.0 ? 1.0 / (2.0 * rc * rc * rc) : (eps_rf - 1.0) / ((2.0 * eps_rf + 1.0) * rc * rc * rc);
+    *c = 1.0 / rc + *k * rc * rc;
+}
+
+int oracle_forces_rf(int n, const float *xyz, const float *q, const int *type, const double L[3],
+                     const int *excl_off, const int *excl_idx, int ntypes, const double *c6c12, double rc,
+                     double eps_rf, double coulomb_f, int shift, int mode, double *f, double *e, double *virial) {
+    oracle_params p = {rc, 0.0, coulomb_f, ntypes, c6c12, shift, 1, 0.0, 0.0};
+    rf_constants(rc, eps_rf, &p.k_rf, &p.c_rf);
+    return forces_impl(&p, n, xyz, q, type, L, excl_off, excl_idx, mode, f, e, virial);
+}
+
 /* forces on the listed atoms only (brute force over all partners); per-atom half energies */
 int oracle_forces_subset(int n, const float *xyz, const float *q, const int *type, const double L[3],
                          const int *excl_off, const int *excl_idx, int ntypes, const double *c6c12,
                          double rc, double beta, double coulomb_f, int shift, int nsub, const int *sub,
                          double *f, double *e_atom) {
-    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, shift};
+    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, shift, 0, 0.0, 0.0};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int s = 0; s < nsub; ++s) {
         int i = sub[s];
