@@ -64,12 +64,28 @@ typedef struct { int m, n; } nb_shape;
  *   coulomb_f 1/(4 pi eps0) in the caller's units (138.935458 kJ mol^-1 nm e^-2)
  *   ntypes    number of LJ types (1..32)
  *   c6c12     DEVICE, ntypes*ntypes*2 floats: [ti][tj] = (C6, C12), symmetric
- *   shift_energies  1: LJ and Coulomb potentials shifted to zero at rc */
+ *   shift_energies  1: LJ and Coulomb potentials shifted to zero at rc
+ *   coulomb   the long-range correction g(r) of Eq. 2:
+ *             NB_COULOMB_EWALD (0): Ewald real space, g = d/dr[erf(beta r)/r],
+ *               evaluated analytically (a rational approximation of erfc);
+ *             NB_COULOMB_RF (1): reaction field, g = -2 k r with
+ *               k = (eps_rf - 1) / ((2 eps_rf + 1) rc^3) (eps_rf = 0: conducting,
+ *               k = 1/(2 rc^3)); potential e/r + k r^2 - c, c = 1/rc + k rc^2,
+ *               also for excluded pairs (e = 0); shift_energies affects LJ only;
+ *             NB_COULOMB_EWALD_TABLE (2): Ewald as 0, with the smooth parts of
+ *               force and potential interpolated linearly from a table in LDS
+ *               (spacing 1 pm; Sec. 3.2 "linear table interpolation").
+ *             RF and the table are supported by the direct force kernel on single
+ *             systems; the compact kernel, batches and nb_recount take Ewald only.
+ *   eps_rf    reaction field: relative permittivity beyond rc (>= 1, or 0) */
+enum { NB_COULOMB_EWALD = 0, NB_COULOMB_RF = 1, NB_COULOMB_EWALD_TABLE = 2 };
 typedef struct {
     float rc, beta, coulomb_f;
     int ntypes;
     const float *c6c12;
     int shift_energies;
+    int coulomb;
+    float eps_rf;
 } nb_params;
 
 /* ---------------------------------------------------------------- context */

@@ -38,6 +38,7 @@ EXPORTS = [
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
+NB_COULOMB_EWALD, NB_COULOMB_RF, NB_COULOMB_EWALD_TABLE = 0, 1, 2
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
 
 
@@ -53,7 +54,8 @@ class nb_shape(ctypes.Structure):
 
 class nb_params(ctypes.Structure):
     _fields_ = [("rc", ctypes.c_float), ("beta", ctypes.c_float), ("coulomb_f", ctypes.c_float),
-                ("ntypes", ctypes.c_int), ("c6c12", ctypes.c_void_p), ("shift_energies", ctypes.c_int)]
+                ("ntypes", ctypes.c_int), ("c6c12", ctypes.c_void_p), ("shift_energies", ctypes.c_int),
+                ("coulomb", ctypes.c_int), ("eps_rf", ctypes.c_float)]
 
 
 class nb_grid_info_t(ctypes.Structure):
@@ -262,10 +264,13 @@ def nb_list_export_canonical(lst):
 
 # ---------------------------------------------------------------- forces
 
-def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True):
-    """nb_params with c6c12 a (ntypes, ntypes, 2) float32 CUDA tensor (kept referenced by the struct's owner)."""
+def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True, coulomb=0, eps_rf=0.0):
+    """nb_params with c6c12 a (ntypes, ntypes, 2) float32 CUDA tensor (kept referenced by the struct's owner).
+    coulomb: NB_COULOMB_EWALD (default), NB_COULOMB_RF (eps_rf: permittivity beyond rc, 0 = conducting) or
+    NB_COULOMB_EWALD_TABLE."""
     nt = c6c12.shape[0]
-    p = nb_params(float(rc), float(beta), float(coulomb_f), int(nt), c6c12.data_ptr(), int(bool(shift_energies)))
+    p = nb_params(float(rc), float(beta), float(coulomb_f), int(nt), c6c12.data_ptr(), int(bool(shift_energies)),
+                  int(coulomb), float(eps_rf))
     p._keep = c6c12
     return p
 

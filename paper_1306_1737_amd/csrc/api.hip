@@ -121,6 +121,7 @@ void nb_destroy(nb_ctx *c) {
     for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
     release(c->partials);
     release(c->blockpart);
+    release(c->etab);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->h_pinned) hipHostFree(c->h_pinned);
     delete c;
@@ -506,7 +507,13 @@ int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_n
     if (!p->c6c12 || p->ntypes < 1 || p->ntypes > kMaxTypes) return fail(NB_ERR_ARG, "nb_forces: ntypes must be 1..32");
     if (!(p->rc > 0.0f) || !(p->rc <= l->rlist)) return fail(NB_ERR_ARG, "nb_forces: need 0 < rc <= rlist");
     if (!(p->beta >= 0.0f) || !std::isfinite(p->coulomb_f)) return fail(NB_ERR_ARG, "nb_forces: bad beta/coulomb_f");
-    if ((double)p->beta * p->rc > 4.0)
+    if (p->coulomb < NB_COULOMB_EWALD || p->coulomb > NB_COULOMB_EWALD_TABLE)
+        return fail(NB_ERR_ARG, "nb_forces: unknown coulomb type");
+    if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
+        return fail(NB_ERR_ARG, "nb_forces: eps_rf must be >= 1, or 0 for a conducting boundary");
+    if (p->coulomb != NB_COULOMB_EWALD && c->force_variant != NB_FORCE_DIRECT)
+        return fail(NB_ERR_UNSUPPORTED, "nb_forces: reaction field and the Ewald table need the direct kernel");
+    if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
         return fail(NB_ERR_UNSUPPORTED, "nb_forces: beta*rc > 4 is outside the fitted Ewald range");
     MXN_HIP(hipSetDevice(c->device));
     ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
@@ -678,6 +685,7 @@ static int batch_check(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flag
     for (int r = 0; r < b->n_rep; ++r)
         if (!(p->rc <= b->lists[r]->rlist)) return fail(NB_ERR_ARG, "nb_batch: rc exceeds a replica's rlist");
     if ((double)p->beta * p->rc > 4.0) return fail(NB_ERR_UNSUPPORTED, "nb_batch: beta*rc > 4");
+    if (p->coulomb != NB_COULOMB_EWALD) return fail(NB_ERR_UNSUPPORTED, "nb_batch: Ewald (analytic) only");
     return NB_OK;
 }
 
@@ -902,6 +910,7 @@ int nb_recount(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_
     if (p->ntypes < 1 || p->ntypes > kMaxTypes || !(p->rc > 0.0f) || !(p->rc <= l->rlist) || !(p->beta >= 0.0f))
         return fail(NB_ERR_ARG, "nb_recount: bad interaction parameters");
     if ((double)p->beta * p->rc > 4.0) return fail(NB_ERR_UNSUPPORTED, "nb_recount: beta*rc > 4");
+    if (p->coulomb != NB_COULOMB_EWALD) return fail(NB_ERR_UNSUPPORTED, "nb_recount: Ewald (analytic) only");
     const float want = l->rlist - c_bb > 0.0f ? l->rlist - c_bb : 0.0f;
     if (l->rbb != want) return fail(NB_ERR_ARG, "nb_recount: the list must be built with rbb = rlist - c_bb");
     MXN_HIP(hipSetDevice(c->device));

@@ -78,6 +78,12 @@ struct ForceArgs {
     const float *c6c12;
     int nt, shift_en;
     float rc2, beta, c_exp, c2bpi, coulomb_f, shiftC, rc6inv;
+    // Coulomb variant: 0 Ewald (rational erfc), 1 reaction field, 2 Ewald from a table
+    int elec;
+    float krf, k2rf, crf;      // reaction field: k, 2k, c
+    const float2 *etab;        // Ewald table: (G, H) at r = i / tab_scale, i < ntab
+    int ntab;
+    float tab_scale;
     float Lx, Ly, Lz;
     double *partials;
     float *f_out;
@@ -143,12 +149,18 @@ __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
 // duplicated body costs more than the selects it saves); a branch-free body
 // whose eight i-particle chains the compiler can interleave (132 registers,
 // occupancy 3: 240 us against 198 us on the 96k-atom box).
-template <int M, bool ENER>
-__device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float (&xi)[M], const float (&yi)[M],
-                                 const float (&zi)[M], const float (&qi)[M], const int (&ti)[M], float xj, float yj,
-                                 float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l, float (&fix)[M],
-                                 float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz, float &el,
-                                 float &ec) {
+// Coulomb variants (ELEC): 0 Ewald with erfc from a rational approximation;
+// 1 reaction field, F/r = qq (e/r^3 - 2k), V = qq (e/r + k r^2 - c); 2 Ewald
+// with F/r = qq (e/r^3 - G(r)) and V = qq (e/r - H(r) - e shift), where
+// G = (erf(beta r)/r - 2 beta/sqrt(pi) exp(-beta^2 r^2)) / r^2 and
+// H = erf(beta r)/r are smooth (finite at r = 0) and interpolated linearly
+// from the LDS table; e = 1 for a set mask bit, 0 for an excluded pair.
+template <int M, bool ENER, int ELEC>
+__device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float2 *tab, const float (&xi)[M],
+                                 const float (&yi)[M], const float (&zi)[M], const float (&qi)[M], const int (&ti)[M],
+                                 float xj, float yj, float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l,
+                                 float (&fix)[M], float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz,
+                                 float &el, float &ec) {
     const int znull = a.nt * a.nt;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -158,17 +170,32 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
             const bool bit = (mb >> k) & 1u;
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float rinv2 = rinv * rinv;
-            const float u = r2 * rinv * a.beta;
-            const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
-            // erfc(u) = exp(-u^2) P(u) / Q(u)
-            const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
-            const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u,
-                                 1.0f);
-            const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
-            const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
-            const float vc = em * rinv;
             const float qq = qi[k] * qj;
-            float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+            float fsc, vc;
+            if (ELEC == 0) {
+                const float u = r2 * rinv * a.beta;
+                const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+                // erfc(u) = exp(-u^2) P(u) / Q(u)
+                const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
+                const float Q =
+                    fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u, 1.0f);
+                const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
+                const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+                vc = em * rinv;
+                fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+            } else if (ELEC == 1) {
+                const float einv = bit ? rinv : 0.0f;
+                vc = einv + fmaf(a.krf, r2, -a.crf);
+                fsc = qq * fmaf(einv, rinv2, -a.k2rf);
+            } else {
+                const float t = r2 * rinv * a.tab_scale;
+                const int i0 = (int)t;
+                const float eps = t - (float)i0;
+                const float2 g0 = tab[i0], g1 = tab[i0 + 1];
+                const float einv = bit ? rinv : 0.0f;
+                vc = einv - fmaf(eps, g1.y - g0.y, g0.y);
+                fsc = qq * fmaf(einv, rinv2, -fmaf(eps, g1.x - g0.x, g0.x));
+            }
             const float4 lj = ljt[bit ? ti[k] + tj : znull];   // the zero row for a clear bit
             const float c6 = lj.x, c12 = lj.y;
             const float rinv6 = rinv2 * rinv2 * rinv2;
@@ -182,7 +209,7 @@ __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const fl
             fjz = fmaf(-fsc, dz, fjz);
             if (ENER) {
                 el += t12 - t6 - lj.z;
-                ec += qq * (vc - lj.w);
+                ec += qq * (ELEC == 1 ? vc : vc - lj.w);   // the reaction field's c is in vc
             }
         }
     }
@@ -212,9 +239,9 @@ __device__ inline long xcd_item(long total, int waves_per_block, int wave) {
 // (Issuing a pass's j-force atomics after the next pass's loads, so that the
 // in-order wait for those loads does not include them, measured slower on
 // gfx950: it costs registers and occupancy for no gain.)
-template <int M, int N, bool ENER, bool VIR, bool ACC64>
-__device__ inline void force_item(const ForceArgs &a, const SysView &v, const float4 *ljt, const float4 *svec,
-                                  int item, int lane) {
+template <int M, int N, bool ENER, bool VIR, bool ACC64, int ELEC>
+__device__ inline void force_item(const ForceArgs &a, const SysView &v, const float4 *ljt, const float2 *tab,
+                                  const float4 *svec, int item, int lane) {
     using acc_t = typename std::conditional<ACC64, double, float>::type;
     constexpr int B = 64 / N;                      // entries per pass
     constexpr unsigned FULL = (1u << M) - 1u;
@@ -266,8 +293,8 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         if (!valid || tjr < 0) act = 0u;
         float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
         const float rc2l = valid ? a.rc2 : -1.0f;
-        pair_pass<M, ENER>(a, ljt, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, act, rc2l, fix, fiy, fiz, fjx, fjy, fjz,
-                           el, ecl);
+        pair_pass<M, ENER, ELEC>(a, ljt, tab, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, act, rc2l, fix, fiy, fiz,
+                                 fjx, fjy, fjz, el, ecl);
         if (ENER) {
             elj += (acc_t)el;
             ec += (acc_t)ecl;
@@ -311,15 +338,18 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
     }
 }
 
-template <int M, int N, bool ENER, bool VIR, bool ACC64>
+template <int M, int N, bool ENER, bool VIR, bool ACC64, int ELEC>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     const long total = a.totals[2];
     if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
     extern __shared__ float4 smem[];
     float4 *svec = smem;        // 27 image shift vectors
     float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
+    float2 *tab = reinterpret_cast<float2 *>(smem + 32 + a.nt * a.nt + 1);   // Ewald table (ELEC == 2)
     for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
     fill_ljt(a, ljt);
+    if (ELEC == 2)
+        for (int t = threadIdx.x; t < a.ntab; t += blockDim.x) tab[t] = a.etab[t];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -327,7 +357,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     if (item < 0) return;
     const SysView v =
         make_view(a.xs_now, a.type_s, a.fj, a.fi, a.jrank, a.jstart, a.items, a.entries, a.partials, a.pstride, 0);
-    force_item<M, N, ENER, VIR, ACC64>(a, v, ljt, svec, (int)item, lane);
+    force_item<M, N, ENER, VIR, ACC64, ELEC>(a, v, ljt, tab, svec, (int)item, lane);
 }
 
 // Forces of one j-cluster's N slots: the j-forces in the j-cluster's rows
@@ -767,9 +797,14 @@ void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
 
 template <int M, int N, bool E, bool V, bool D>
 void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t st) {
-    if (variant == NB_FORCE_DIRECT)
-        k_forces<M, N, E, V, D><<<nb, 256, lds, st>>>(a);
-    else
+    if (variant == NB_FORCE_DIRECT) {
+        if (a.elec == NB_COULOMB_RF)
+            k_forces<M, N, E, V, D, 1><<<nb, 256, lds, st>>>(a);
+        else if (a.elec == NB_COULOMB_EWALD_TABLE)
+            k_forces<M, N, E, V, D, 2><<<nb, 256, lds + (size_t)a.ntab * sizeof(float2), st>>>(a);
+        else
+            k_forces<M, N, E, V, D, 0><<<nb, 256, lds, st>>>(a);
+    } else
         k_forces_c<M, N, E, V, D><<<nb, 256, lds + 4 * wave_lds_bytes<N>(), st>>>(a);
 }
 
@@ -894,7 +929,7 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     const SysView v =
         make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jrank, d.jstart, d.items, d.entries, b.partials, b.pstride,
                   d.pbase);
-    force_item<M, N, ENER, VIR, true>(a, v, ljt, d.shiftvec, (int)(idx - b.item_off[r]), lane);
+    force_item<M, N, ENER, VIR, true, 0>(a, v, ljt, nullptr, d.shiftvec, (int)(idx - b.item_off[r]), lane);
 }
 
 // one wavefront per j-cluster of every replica (the replicas' slot capacities
@@ -1001,6 +1036,40 @@ int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *x
     return NB_OK;
 }
 
+// The Ewald table of the tabulated variant: (G, H) at r = i h, h = 1 pm, i < ntab, with
+// G = (erf(beta r)/r - 2 beta/sqrt(pi) exp(-beta^2 r^2)) / r^2 and H = erf(beta r)/r, in FP64
+// rounded once; at r = 0 their limits 4 beta^3 / (3 sqrt(pi)) and 2 beta / sqrt(pi).  One
+// entry beyond rc guards the upper neighbour of the last interval.  Rebuilt (synchronously)
+// only when beta or rc change.
+constexpr double kTabScale = 1000.0;
+
+static int ensure_ewald_table(nb_ctx *ctx, float beta, float rc, int *ntab) {
+    const int n = (int)((double)rc * kTabScale) + 3;
+    *ntab = n;
+    if (ctx->etab.p && ctx->etab_beta == beta && ctx->etab_rc == rc) return NB_OK;
+    std::vector<float2> h((size_t)n);
+    const double b = beta, c = 2.0 * b / std::sqrt(M_PI);
+    for (int i = 0; i < n; ++i) {
+        const double r = i / kTabScale;
+        double G, H;
+        if (i == 0) {
+            G = 4.0 * b * b * b / (3.0 * std::sqrt(M_PI));
+            H = c;
+        } else {
+            H = std::erf(b * r) / r;
+            G = (H - c * std::exp(-b * b * r * r)) / (r * r);
+        }
+        h[(size_t)i] = make_float2((float)G, (float)H);
+    }
+    int rc_ = ensure(ctx->etab, (size_t)n * sizeof(float2));
+    if (rc_) return rc_;
+    MXN_HIP(hipMemcpyAsync(ctx->etab.p, h.data(), (size_t)n * sizeof(float2), hipMemcpyHostToDevice, ctx->stream));
+    MXN_HIP(hipStreamSynchronize(ctx->stream));   // h is released on return
+    ctx->etab_beta = beta;
+    ctx->etab_rc = rc;
+    return NB_OK;
+}
+
 int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
                   unsigned flags, float *f, double *energy, double *virial) {
     hipStream_t st = ctx->stream;
@@ -1039,6 +1108,19 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.coulomb_f = p->coulomb_f;
     a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
+    a.elec = p->coulomb;
+    if (p->coulomb == NB_COULOMB_RF) {   // k = (eps_rf - 1) / ((2 eps_rf + 1) rc^3), 0 = conducting; c = 1/rc + k rc^2
+        const double rc = p->rc, eps = p->eps_rf;
+        const double k = eps == 0.0 ? 1.0 / (2.0 * rc * rc * rc) : (eps - 1.0) / ((2.0 * eps + 1.0) * rc * rc * rc);
+        a.krf = (float)k;
+        a.k2rf = (float)(2.0 * k);
+        a.crf = (float)(1.0 / rc + k * rc * rc);
+    } else if (p->coulomb == NB_COULOMB_EWALD_TABLE) {
+        int rc = ensure_ewald_table(ctx, p->beta, p->rc, &a.ntab);
+        if (rc) return rc;
+        a.etab = (const float2 *)ctx->etab.p;
+        a.tab_scale = (float)kTabScale;
+    }
     a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
     a.partials = (double *)ctx->partials.p;
     a.pstride = pstride;

@@ -63,6 +63,8 @@ struct nb_ctx {
     int *h_pinned = nullptr;    // pinned host scratch (16 ints)
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     mxn::DevBuf blockpart;      // sums of the partials over contiguous shares of the work items
+    mxn::DevBuf etab;           // Ewald table of the tabulated Coulomb variant
+    float etab_beta = -1.0f, etab_rc = -1.0f;
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
     int search_parts = 0;   // 0: chosen from the number of i-clusters

@@ -1,0 +1,107 @@
+"""Coulomb variants of the direct force kernel (Eq. 2, Sec. 3.2) through the C ABI against the FP64 oracle:
+reaction field (g(r) = -2 k r) and the Ewald correction interpolated linearly from a table."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._nb import F, GpuSystem, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu-case] %s" % request.node.nodeid, file=sys.stderr, flush=True)
+    yield
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.water_box(1000, 3.104, seed=1306)
+
+
+def _run(s, rc, beta, flags, coulomb, eps_rf=0.0, xq=None):
+    mxn, torch = s.mxn, s.torch
+    f = torch.zeros((s.box.n, 3), dtype=torch.float32, device=s.dev)
+    e = torch.zeros(2, dtype=torch.float64, device=s.dev)
+    v = torch.zeros(9, dtype=torch.float64, device=s.dev)
+    p = mxn.make_params(rc, beta, F, s.lj, True, coulomb, eps_rf)
+    mxn.nb_forces(s.ctx, s.grid, s.lst, s.xyzq if xq is None else xq, p, flags, f, e, v)
+    mxn.nb_sync(s.ctx)
+    return f.cpu().numpy().astype(np.float64), e.cpu().numpy(), v.cpu().numpy().reshape(3, 3)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (8, 4), (8, 8)])
+@pytest.mark.parametrize("eps_rf", [78.0, 0.0])
+def test_reaction_field(c1, shape, eps_rf):
+    rc = 0.9
+    s = GpuSystem(c1, shape, rc)
+    try:
+        mxn = s.mxn
+        fl = mxn.NB_ENERGY | mxn.NB_VIRIAL
+        f, e, v = _run(s, rc, 0.0, fl, mxn.NB_COULOMB_RF, eps_rf)
+        fr, er, vr = oracle.forces_rf(c1.xyz, c1.q, c1.type, c1.box, c1.excl_off, c1.excl_idx,
+                                      synth.lj_table_spce(), rc, eps_rf, F, shift=True, mode="brute")
+        assert rel_rms(f, fr) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+        assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
+        # FP32 accumulation mode changes only the sums
+        f32, e32, _ = _run(s, rc, 0.0, fl | mxn.NB_ACC_FP32, mxn.NB_COULOMB_RF, eps_rf)
+        np.testing.assert_array_equal(f32, f)
+        np.testing.assert_allclose(e32, er, rtol=1e-3)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (8, 4), (8, 8)])
+@pytest.mark.parametrize("rc,beta", [(0.9, 3.47), (1.0, 3.12)])
+def test_ewald_table(c1, shape, rc, beta):
+    s = GpuSystem(c1, shape, rc)
+    try:
+        mxn = s.mxn
+        fl = mxn.NB_ENERGY | mxn.NB_VIRIAL
+        ft, et, vt = _run(s, rc, beta, fl, mxn.NB_COULOMB_EWALD_TABLE)
+        fa, ea, va = _run(s, rc, beta, fl, mxn.NB_COULOMB_EWALD)
+        fr, er, vr = oracle.forces(c1.xyz, c1.q, c1.type, c1.box, c1.excl_off, c1.excl_idx, synth.lj_table_spce(),
+                                   rc, beta, F, shift=True, mode="brute")
+        assert rel_rms(ft, fr) <= 1e-5
+        assert rel_rms(ft, fa) <= 2e-6
+        np.testing.assert_allclose(et, er, rtol=1e-5)
+        assert np.abs(vt - vr).max() <= 1e-5 * np.abs(vr).max()
+    finally:
+        s.close()
+
+
+def test_table_follows_parameter_changes(c1):
+    """The cached table is rebuilt when beta or rc change between calls on one context."""
+    s = GpuSystem(c1, (8, 8), 1.0)
+    try:
+        mxn = s.mxn
+        for rc, beta in ((1.0, 3.12), (0.9, 3.47), (1.0, 3.12)):
+            ft, et, _ = _run(s, rc, beta, mxn.NB_ENERGY, mxn.NB_COULOMB_EWALD_TABLE)
+            fr, er, _ = oracle.forces(c1.xyz, c1.q, c1.type, c1.box, c1.excl_off, c1.excl_idx,
+                                      synth.lj_table_spce(), rc, beta, F, shift=True, mode="brute")
+            assert rel_rms(ft, fr) <= 1e-5
+            np.testing.assert_allclose(et, er, rtol=1e-5)
+    finally:
+        s.close()
+
+
+def test_unsupported_combinations(c1):
+    s = GpuSystem(c1, (8, 8), 0.9, variant=1)   # compact kernel
+    try:
+        mxn = s.mxn
+        with pytest.raises(mxn.NbError):
+            _run(s, 0.9, 0.0, 0, mxn.NB_COULOMB_RF, 78.0)
+        with pytest.raises(mxn.NbError):
+            _run(s, 0.9, 3.47, 0, mxn.NB_COULOMB_EWALD_TABLE)
+        mxn.nb_set_force_variant(s.ctx, 0)
+        with pytest.raises(mxn.NbError):
+            _run(s, 0.9, 0.0, 0, mxn.NB_COULOMB_RF, 0.5)    # eps_rf in (0, 1)
+        with pytest.raises(mxn.NbError):
+            _run(s, 0.9, 3.47, 0, 7)
+    finally:
+        s.close()
