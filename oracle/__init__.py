@@ -12,6 +12,7 @@ no code with it; the only common module is `synth` (seeded input generation).
   cluster-pair list (Sec. 2.3, cluster-pair search pseudocode; Sec. 2.4 masks).
 * `gather`, `prune`: the second stage of a two-stage list (Sec. 2.3: box-only
   search, then a particle-distance prune), at positions of a later time.
+* `rdf`: pair distance histogram (pair correlation function, Sec. 1 and 2.3).
 * `recount`: exact missed-pair energy after displacements (Sec. 5, appendix).
 * `drift` (module): the appendix's analytic drift bound (with its V'' term
   corrected) and its numerical quadrature.
@@ -192,6 +193,19 @@ def prune(grid, xs_now, box, entries, r):
                             _p(perm, ctypes.c_int), _p(box, ctypes.c_double), ent.ctypes.data_as(ctypes.c_void_p),
                             ctypes.c_long(len(ent)), ctypes.c_float(r), out.ctypes.data_as(ctypes.c_void_p))
     return out[:k]
+
+
+def rdf(grid, xs, typ, box, r_max, nbins, ntypes, excl_off, excl_idx, skip_excluded=False):
+    """Pair distance histogram (ntypes, ntypes, nbins) uint64 over unordered real pairs below r_max, with the
+    cluster kernels' FP32 distance and bin edges e_k = (float)((k r_max/nbins)^2) (see oracle.c)."""
+    xs = _c(xs, np.float32); slot_of = _c(grid["slot_of"], np.int32); typ = _c(typ, np.int32)
+    box = _c(box, np.float64); eo = _c(excl_off, np.int32); ei = _c(excl_idx, np.int32)
+    hist = np.zeros(ntypes * ntypes * nbins, np.uint64)
+    _lib().oracle_rdf(ctypes.c_int(slot_of.shape[0]), _p(xs, ctypes.c_float), _p(slot_of, ctypes.c_int),
+                      _p(typ, ctypes.c_int), _p(box, ctypes.c_double), ctypes.c_float(r_max), ctypes.c_int(nbins),
+                      ctypes.c_int(ntypes), _p(eo, ctypes.c_int), _p(ei, ctypes.c_int),
+                      ctypes.c_int(int(skip_excluded)), hist.ctypes.data_as(ctypes.c_void_p))
+    return hist.reshape(ntypes, ntypes, nbins)
 
 
 def recount(xyz0, xyzt, q, typ, box, excl_off, excl_idx, c6c12, rc, beta, coulomb_f, m, n_, rl, c_bb, db, nb):

@@ -535,6 +535,69 @@ long oracle_prune(int M, int N, const float *xs, const int *perm, const double b
 }
 
 /* ------------------------------------------------------------------------- */
+/* 3c. Pair distance histogram (pair correlation function)                   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Sec. 1 and 2.3: pair correlation functions are pair evaluations of limited
+ * range too, with a list built every evaluation and no particle pruning.
+ * For every unordered pair of real atoms (a, b) -- optionally skipping
+ * force-field exclusions -- with separation below r_max, count it in bin k of
+ * its type pair (lo, hi) = (min, max of the types, each clamped to
+ * [0, ntypes)): hist[(lo * ntypes + hi) * nbins + k] += 1.
+ * The distance is the FP32 one of the cluster-pair kernels: positions are the
+ * wrapped slot positions xs; the pair is oriented and shifted as the half
+ * list holds it (the image s with x_a + s L nearest x_b, found in FP64; index
+ * s > 13 keeps (i, j) = (a, b), s < 13 swaps them and negates s, s == 13 puts
+ * the lower slot first); then d = x_i - (x_j - s L), r2 = (dx dx + dy dy) +
+ * dz dz, separately rounded.  Bin k is the largest with e_k <= r2 and r2 <
+ * e_nbins, where e_k = (float)((k dr)^2) in FP64, dr = r_max / nbins.
+ */
+void oracle_rdf(int n, const float *xs, const int *slot_of, const int *type, const double box[3], float r_max,
+                int nbins, int ntypes, const int *excl_off, const int *excl_idx, int skip_excl,
+                unsigned long long *hist) {
+    float Lf[3] = {(float)box[0], (float)box[1], (float)box[2]};
+    double dr = (double)r_max / nbins;
+    float *edge = (float *)malloc((size_t)(nbins + 1) * sizeof(float));
+    for (int k = 0; k <= nbins; ++k) edge[k] = (float)((k * dr) * (k * dr));
+    for (int a = 0; a < n; ++a) {
+        for (int b = a + 1; b < n; ++b) {
+            if (skip_excl && is_excluded(excl_off, excl_idx, a, b)) continue;
+            int sa = slot_of[a], sb = slot_of[b];
+            const float *xa = xs + 3 * sa, *xb = xs + 3 * sb;
+            int sh[3];
+            for (int k = 0; k < 3; ++k) {   /* the image of a nearest b: x_a + s L ~ x_b */
+                double d = ((double)xb[k] - (double)xa[k]) / (double)Lf[k];
+                sh[k] = d > 0.5 ? 1 : (d < -0.5 ? -1 : 0);
+            }
+            int idx = 9 * (sh[0] + 1) + 3 * (sh[1] + 1) + (sh[2] + 1);
+            const float *xi = xa, *xj = xb;
+            int ti = type[a], tj = type[b];
+            if (idx < 13 || (idx == 13 && sb < sa)) {
+                xi = xb; xj = xa; ti = type[b]; tj = type[a];
+                for (int k = 0; k < 3; ++k) sh[k] = -sh[k];
+            }
+            float d[3];
+            for (int k = 0; k < 3; ++k) {
+                volatile float sv = (float)sh[k] * Lf[k];
+                volatile float xjs = xj[k] - sv;
+                volatile float dk = xi[k] - xjs;
+                d[k] = dk;
+            }
+            float r2 = sq_sum3(d[0], d[1], d[2]);
+            if (!(r2 < edge[nbins])) continue;
+            int k = nbins - 1;
+            while (edge[k] > r2) --k;
+            ti = ti < 0 ? 0 : (ti >= ntypes ? ntypes - 1 : ti);
+            tj = tj < 0 ? 0 : (tj >= ntypes ? ntypes - 1 : tj);
+            int lo = ti < tj ? ti : tj, hi = ti < tj ? tj : ti;
+            hist[(size_t)(lo * ntypes + hi) * nbins + k] += 1;
+        }
+    }
+    free(edge);
+}
+
+/* ------------------------------------------------------------------------- */
 /* 4. Exact missed-pair recount (Verlet-buffer study, Sec. 5 and appendix)   */
 /* ------------------------------------------------------------------------- */
 
