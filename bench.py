@@ -185,7 +185,8 @@ def main():
     ap.add_argument("--coulomb", default="ewald", choices=["ewald", "rf", "table"],
                     help="Coulomb correction: Ewald (analytic), reaction field (eps_rf 78), Ewald from a table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="production", choices=["production", "batched", "twostage"])
+    ap.add_argument("--workload", default="production", choices=["production", "batched", "twostage", "rdf"])
+    ap.add_argument("--rdf-bins", type=int, default=500, help="rdf: histogram bins up to rc")
     ap.add_argument("--outer-rlist", type=float, default=0.0, metavar="NM",
                     help="twostage: radius of the box-only outer list (default: the workload's rlist)")
     ap.add_argument("--outer-nstlist", type=int, default=0, metavar="STEPS",
@@ -215,6 +216,8 @@ def main():
         return bench_batched(args)
     if args.workload == "twostage":
         return bench_twostage(args)
+    if args.workload == "rdf":
+        return bench_rdf(args)
 
     import numpy as np
     import torch
@@ -415,6 +418,76 @@ def bench_twostage(args):
                    "outer_rlist": r_out, "outer_nstlist": n_out, "prune_every": P, "r_inner": args.r_inner},
         "variants": out,
     }
+    mxn.nb_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+def bench_rdf(args):
+    """Pair correlation function on the production box (Sec. 1 and 2.3): each frame of the ballistic trajectory
+    is grid-sorted, gets a box-only list (no particle prune) at rc + 0.01 nm, and the pair distance histogram
+    of its pairs below rc (per type pair, exact counts).  Times whole frames and the histogram kernel alone."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1737_amd as mxn
+
+    w = synth.PRODUCTION
+    m, n = (int(v) for v in args.shape.split("x"))
+    r_max, nbins, rl = w.rc, args.rdf_bins, w.rc + 0.01
+    print("[bench] generating %d waters" % w.n_mol, file=sys.stderr, flush=True)
+    box = synth.water_box(w.n_mol, w.L, seed=1306)
+    vel = synth.velocities(box.mass, w.T, seed=1306)
+    xs = synth.free_flight(box.xyz, vel, w.dt, w.nstlist)
+    dev = torch.device("cuda:0")
+    xq = [torch.from_numpy(box.xyzq(x)).to(dev) for x in xs]
+    typ = torch.from_numpy(box.type).to(dev)
+    eo = torch.from_numpy(box.excl_off).to(dev)
+    ei = torch.from_numpy(box.excl_idx).to(dev)
+    nt = int(box.type.max()) + 1
+    hist = torch.zeros(nt * nt * nbins, dtype=torch.int64, device=dev)
+    ctx = mxn.nb_create(0)
+    st = {"grid": None, "lst": None}
+
+    def frame(k, flags):
+        st["grid"] = mxn.nb_grid_sort(ctx, box.box, xq[k], typ, (m, n), st["grid"])
+        st["lst"] = mxn.nb_pairlist_build(ctx, st["grid"], rl, rl, eo, ei, flags, st["lst"])
+        mxn.nb_rdf(ctx, st["grid"], st["lst"], xq[k], r_max, nbins, nt, hist)
+
+    frame(0, 0)                       # sizes the list storage
+    mxn.nb_sync(ctx)
+    for k in range(args.warmup):
+        frame(k % len(xq), mxn.NB_LIST_ASYNC)
+    mxn.nb_sync(ctx)
+    hist.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        frame(s % len(xq), mxn.NB_LIST_ASYNC)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mxn.nb_sync(ctx)
+    counted = int(hist.sum().item()) / args.steps
+    listed = mxn.nb_list_stats(ctx, st["grid"], st["lst"], xq[(args.steps - 1) % len(xq)], r_max)[0]
+    reps = 20
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        mxn.nb_rdf(ctx, st["grid"], st["lst"], xq[(args.steps - 1) % len(xq)], r_max, nbins, nt, hist)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ms_frame = (t1 - t0) * 1e3 / args.steps
+    us_rdf = (t3 - t2) * 1e6 / reps
+    result = {
+        "metric": "pair distances binned/s (pair correlation function)", "value": counted / (ms_frame * 1e-3),
+        "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_frame,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name + "-rdf", "shape": "%dx%d" % (m, n), "r_max": r_max, "nbins": nbins,
+                   "list": "box-only, rlist = r_max + 0.01 nm, rebuilt every frame"},
+        "pairs_counted_per_frame": counted, "listed_pairs_per_frame": listed,
+        "histogram_call_us": us_rdf, "listed_pairs_per_s_histogram": listed / (us_rdf * 1e-6),
+    }
+    mxn.nb_list_free(st["lst"])
+    mxn.nb_grid_free(st["grid"])
     mxn.nb_destroy(ctx)
     print(json.dumps(result), flush=True)
 

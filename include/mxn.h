@@ -213,6 +213,33 @@ void nb_list_free(nb_list *list);
  */
 int nb_pairlist_prune(nb_ctx *ctx, const nb_list *outer, const float *xyzq_now, float r, nb_list **inner);
 
+/*
+ * Pair distance histogram: the pair correlation function, a limited-range
+ * pair evaluation named in Sec. 1.  Sec. 2.3: with a list built for every
+ * evaluation, build it from bounding boxes alone (rbb = rlist, no particle
+ * prune); the kernel then has no cut-off conditional.  Every unordered pair
+ * of real particles of the list closer than r_max (optionally skipping
+ * force-field exclusions) is counted in bin k of its type pair:
+ *   hist[(lo * ntypes + hi) * nbins + k] += 1,  lo <= hi the two types
+ * (clamped to [0, ntypes)); the (hi, lo) half stays untouched.  The bin is
+ * decided in FP32: k is the largest with e_k <= r2, e_k = (float)((k dr)^2)
+ * computed in FP64 with dr = r_max / nbins, and r2 the squared FP32
+ * distance of the pair in its listed image.  Counts are exact (integer).
+ *   list      built on grid; must hold every pair below r_max at xyzq_now
+ *             (at its build positions any list with rlist >= r_max does)
+ *   xyzq_now  DEVICE float4[n], caller's order
+ *   r_max     histogram range (nm), 0 < r_max <= the list's rlist
+ *   nbins     bins; the histogram and the edges must fit 64 KB of LDS:
+ *             4 (ntypes^2 nbins + nbins + 1) + 512 bytes
+ *   flags     0 or NB_RDF_SKIP_EXCLUDED
+ *   hist      DEVICE uint64[ntypes * ntypes * nbins], added to (not cleared)
+ * Asynchronous; the first call with new r_max or nbins uploads the bin edges
+ * (one synchronisation).
+ */
+enum { NB_RDF_SKIP_EXCLUDED = 1 };
+int nb_rdf(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, float r_max, int nbins,
+           int ntypes, int flags, unsigned long long *hist);
+
 /* Synchronous.  Number of cluster-pair entries and force work items. */
 int nb_list_info(nb_list *list, long *n_entries, long *n_items);
 

@@ -28,7 +28,7 @@ NB_BUFFER_ANALYTIC, NB_BUFFER_MLP, NB_BUFFER_AUTO = 0, 1, 2
 EXPORTS = [
     "nb_create", "nb_destroy", "nb_set_stream", "nb_sync", "nb_last_error",
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
-    "nb_pairlist_build", "nb_pairlist_prune", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
+    "nb_pairlist_build", "nb_pairlist_prune", "nb_rdf", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
     "nb_list_stats", "nb_set_force_variant", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
@@ -39,6 +39,7 @@ EXPORTS = [
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
 NB_COULOMB_EWALD, NB_COULOMB_RF, NB_COULOMB_EWALD_TABLE = 0, 1, 2
+NB_RDF_SKIP_EXCLUDED = 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
 
 
@@ -99,6 +100,7 @@ def lib():
             "nb_grid_export": ([vp, vp, vp, vp, vp, vp], i),
             "nb_pairlist_build": ([vp, vp, f, f, vp, vp, i, pvp], i), "nb_list_free": ([vp], None),
             "nb_pairlist_prune": ([vp, vp, vp, f, pvp], i),
+            "nb_rdf": ([vp, vp, vp, vp, f, i, i, i, vp], i),
             "nb_list_info": ([vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)], i),
             "nb_list_export_canonical": ([vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_long)], i),
             "nb_forces": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), u, vp, vp, vp], i),
@@ -238,6 +240,12 @@ def nb_pairlist_prune(ctx, outer, xyzq_now, r, inner=None):
     h = inner if inner is not None else ctypes.c_void_p()
     _check(lib().nb_pairlist_prune(ctx, outer, _ptr(xyzq_now), float(r), ctypes.byref(h)))
     return h
+
+
+def nb_rdf(ctx, grid, lst, xyzq_now, r_max, nbins, ntypes, hist, skip_excluded=False):
+    """Pair distance histogram added to hist (uint64 CUDA tensor of ntypes*ntypes*nbins; torch int64 is fine)."""
+    _check(lib().nb_rdf(ctx, grid, lst, _ptr(xyzq_now), float(r_max), int(nbins), int(ntypes),
+                        NB_RDF_SKIP_EXCLUDED if skip_excluded else 0, _ptr(hist)))
 
 
 def nb_list_free(lst):

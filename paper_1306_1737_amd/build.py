@@ -24,6 +24,7 @@ SOURCES = {
     "api.hip": [],
     "grid.hip": ["-ffp-contract=off"],
     "pairlist.hip": ["-ffp-contract=off"],
+    "rdf.hip": ["-ffp-contract=off"],
     "forces.hip": [],
     "recount.hip": [],
     "mlp.hip": [],

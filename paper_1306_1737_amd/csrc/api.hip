@@ -122,6 +122,7 @@ void nb_destroy(nb_ctx *c) {
     release(c->partials);
     release(c->blockpart);
     release(c->etab);
+    release(c->rdf_edge);
     if (c->d_flags) hipFree(c->d_flags);
     if (c->h_pinned) hipHostFree(c->h_pinned);
     delete c;
@@ -518,6 +519,23 @@ int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_n
     MXN_HIP(hipSetDevice(c->device));
     ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
     return launch_forces(c, g, l, xyzq_now, p, flags, f, energy, virial);
+}
+
+// ------------------------------------------------------------ pair histogram
+
+int nb_rdf(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, float r_max, int nbins, int ntypes,
+           int flags, unsigned long long *hist) {
+    if (!c || !g || !l || !xyzq_now || !hist) return fail(NB_ERR_ARG, "nb_rdf: null argument");
+    if (g->ctx != c || l->ctx != c || l->grid != g || l->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, "nb_rdf: grid/list/context mismatch or stale list");
+    if (flags & ~NB_RDF_SKIP_EXCLUDED) return fail(NB_ERR_ARG, "nb_rdf: unknown flag");
+    if (!(r_max > 0.0f) || !(r_max <= l->rlist)) return fail(NB_ERR_ARG, "nb_rdf: need 0 < r_max <= rlist");
+    if (nbins < 1 || ntypes < 1 || ntypes > kMaxTypes) return fail(NB_ERR_ARG, "nb_rdf: bad nbins or ntypes");
+    if (rdf_lds_bytes(nbins, ntypes) > 64 * 1024)
+        return fail(NB_ERR_UNSUPPORTED, "nb_rdf: the histogram (ntypes^2 * nbins) and edges exceed 64 KB of LDS");
+    MXN_HIP(hipSetDevice(c->device));
+    int rc = launch_gather(c, g, xyzq_now);
+    return rc ? rc : launch_rdf(c, g, l, r_max, nbins, ntypes, (flags & NB_RDF_SKIP_EXCLUDED) ? 1 : 0, hist);
 }
 
 // -------------------------------------------------------- instrumentation

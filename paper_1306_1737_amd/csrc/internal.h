@@ -64,6 +64,9 @@ struct nb_ctx {
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     mxn::DevBuf blockpart;      // sums of the partials over contiguous shares of the work items
     mxn::DevBuf etab;           // Ewald table of the tabulated Coulomb variant
+    mxn::DevBuf rdf_edge;       // squared bin edges of the pair distance histogram
+    float rdf_rmax = -1.0f;
+    int rdf_nbins = 0;
     float etab_beta = -1.0f, etab_rc = -1.0f;
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
@@ -208,6 +211,10 @@ void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
 // at the grid's gathered positions (xs_now)
 int launch_prune(nb_list *in, const nb_list *outer, float r);
 int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now);
+// pair distance histogram at the grid's gathered positions (xs_now)
+size_t rdf_lds_bytes(int nbins, int nt);
+int launch_rdf(nb_ctx *ctx, const nb_grid *g, const nb_list *l, float r_max, int nbins, int nt, int skip_excl,
+               unsigned long long *hist);
 // exclusive scan of in[0..n) into out[0..n] that leaves in[] zeroed
 void launch_scan_clear(int *in, int *out, int n, hipStream_t s);
 
