@@ -42,20 +42,19 @@ struct SysView {
     gptr<const int> type_s;
     gptr<float> fj;        // j-force (x, y, z) per (row, j-particle)
     gptr<float4> fi;       // i-force per (item, i-particle)
-    gptr<const int> jrank, jstart;   // entry's rank within its j-cluster; j-cluster's first row
+    gptr<const int> jpos;  // row of each entry position
     gptr<const int4> items;
     gptr<const nb_jentry> entries;
     gptr<double> partials;
     long pstride, pbase;   // partial of item i, value k: partials[k * pstride + pbase + i]
 };
 
-__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fj, float4 *fi, const int *jrank,
-                                    const int *jstart, const int4 *items, const nb_jentry *entries, double *partials,
-                                    long pstride, long pbase) {
-    return SysView{(gptr<const float4>)xs_now,     (gptr<const int>)type_s, (gptr<float>)fj,
-                   (gptr<float4>)fi,               (gptr<const int>)jrank,  (gptr<const int>)jstart,
-                   (gptr<const int4>)items,        (gptr<const nb_jentry>)entries,
-                   (gptr<double>)partials,         pstride,                 pbase};
+__device__ inline SysView make_view(const float4 *xs_now, const int *type_s, float *fj, float4 *fi, const int *jpos,
+                                    const int4 *items, const nb_jentry *entries, double *partials, long pstride,
+                                    long pbase) {
+    return SysView{(gptr<const float4>)xs_now, (gptr<const int>)type_s, (gptr<float>)fj,
+                   (gptr<float4>)fi,           (gptr<const int>)jpos,   (gptr<const int4>)items,
+                   (gptr<const nb_jentry>)entries, (gptr<double>)partials, pstride, pbase};
 }
 
 struct ForceArgs {
@@ -64,8 +63,7 @@ struct ForceArgs {
     float4 *xs_now;
     float *fj;         // j-force (x, y, z) per (row, j-particle)
     float4 *fi;        // i-force per (item, i-particle)
-    const int *jstart, *jrank, *part_istart;   // first row of each j-cluster, rank of each entry in its j-cluster;
-                                               // first item of each region
+    const int *jstart, *jpos, *part_istart;   // first row of each j-cluster, row of each entry; first item of each region
     double *blockpart;   // energy reduction: per-share sums [kNAcc][kReduceParts]
     double *energy, *virial;
     int ener, vir;
@@ -275,7 +273,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         const int e = e0 + eo;
         const bool valid = e < je;
         const nb_jentry en = ld(v.entries + (valid ? e : e0));
-        const int rank = v.jrank[valid ? e : e0];   // the row (jstart[cj] + rank) is needed only at the store
+        const int row = v.jpos[valid ? e : e0];
         const int jslot = en.cj * N + jb;
         const float4 pj = ld(v.xs_now + jslot);
         const int tjr = v.type_s[jslot];
@@ -300,7 +298,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
             ec += (acc_t)ecl;
         }
         if (valid) {
-            const gptr<float> o = v.fj + ((long)(v.jstart[en.cj] + rank) * N + jb) * 3;
+            const gptr<float> o = v.fj + ((long)row * N + jb) * 3;
             o[0] = fjx;
             o[1] = fjy;
             o[2] = fjz;
@@ -355,8 +353,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const long item = xcd_item(total, 4, threadIdx.x >> 6);
     if (item < 0) return;
-    const SysView v =
-        make_view(a.xs_now, a.type_s, a.fj, a.fi, a.jrank, a.jstart, a.items, a.entries, a.partials, a.pstride, 0);
+    const SysView v = make_view(a.xs_now, a.type_s, a.fj, a.fi, a.jpos, a.items, a.entries, a.partials, a.pstride, 0);
     force_item<M, N, ENER, VIR, ACC64, ELEC>(a, v, ljt, tab, svec, (int)item, lane);
 }
 
@@ -757,8 +754,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         const int jidx = base + lane;
         if (jidx < nslot) {
             const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
-            const int e = js + jidx / N;
-            float *o = a.fj + ((long)(a.jstart[a.entries[e].cj] + a.jrank[e]) * N + jidx % N) * 3;
+            float *o = a.fj + ((long)a.jpos[js + jidx / N] * N + jidx % N) * 3;
             o[0] = gx;
             o[1] = gy;
             o[2] = gz;
@@ -835,7 +831,7 @@ struct RepDesc {
     const int *type_s, *perm, *img_s, *slot_of, *nslots;
     float *fj;
     float4 *fi;
-    const int *jstart, *jrank, *part_istart;
+    const int *jstart, *jpos, *part_istart;
     int parts, n;
     const int4 *items;
     const nb_jentry *entries;
@@ -927,8 +923,7 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
     const RepDesc &d = b.rep[r];
     const SysView v =
-        make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jrank, d.jstart, d.items, d.entries, b.partials, b.pstride,
-                  d.pbase);
+        make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
     force_item<M, N, ENER, VIR, true, 0>(a, v, ljt, nullptr, d.shiftvec, (int)(idx - b.item_off[r]), lane);
 }
 
@@ -1090,7 +1085,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.fj = (float *)l->fj.p;
     a.fi = (float4 *)l->fi.p;
     a.jstart = (const int *)l->jstart.p;
-    a.jrank = (const int *)l->jrank.p;
+    a.jpos = (const int *)l->jrank.p;   // rows, after the build's position pass
     a.part_istart = (const int *)l->part_istart.p;
     a.parts = l->resv_parts;
     a.n = g->n;
@@ -1224,7 +1219,7 @@ void fill_rep_desc(void *out, const nb_grid *g, const nb_list *l, const float *x
     d.fj = (float *)l->fj.p;
     d.fi = (float4 *)l->fi.p;
     d.jstart = (const int *)l->jstart.p;
-    d.jrank = (const int *)l->jrank.p;
+    d.jpos = (const int *)l->jrank.p;
     d.part_istart = (const int *)l->part_istart.p;
     d.parts = l->resv_parts;
     d.n = g->n;

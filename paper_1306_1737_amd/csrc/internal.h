@@ -113,9 +113,9 @@ struct nb_list {
     mxn::DevBuf totals;        // int[4]: entries, items, usable items (0 after an overflow), region overflow
     // j-cluster view, rebuilt with the list: entries per j-cluster (counters,
     // zero between builds), their exclusive scan (first row of each j-cluster),
-    // and for each entry position its rank among the j-cluster's entries, so
-    // that its row is jstart[cj] + jrank (jrank_canon: the fill pass's ranks
-    // before a distance sort)
+    // and for each entry position its rank among the j-cluster's entries,
+    // turned into its row jstart[cj] + rank by the build's last pass
+    // (jrank_canon: the fill pass's ranks before a distance sort)
     mxn::DevBuf jcount, jstart, jrank, jrank_canon;
     // force-call buffers: j-force (x, y, z) per (row, j-particle), rows grouped
     // by j-cluster, and float4 i-force per (work item, i-particle); summed per

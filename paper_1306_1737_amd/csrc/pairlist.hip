@@ -422,9 +422,33 @@ __global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_b
 // rows contiguously.  The fill pass (and the prune) take each written entry's
 // rank among its j-cluster's entries from a counter per j-cluster; after the
 // build an exclusive scan of the counters (which clears them for the next
-// build) gives each j-cluster's first row, and an entry's row is that plus
-// its rank.  The row order within a j-cluster depends on timing; the
+// build) gives each j-cluster's first row, and this pass turns every usable
+// entry's rank into its row (the force kernel then reads one row index per
+// entry instead of a dependent gather of the j-cluster's start: measured
+// cheaper).  The row order within a j-cluster depends on timing; the
 // reduction sums in fixed point, so the forces do not.
+struct JPosArgs {
+    const int *totals;   // [2]: usable items
+    const int4 *items;
+    const nb_jentry *entries;
+    const int *jstart;   // first row of each j-cluster
+    int *jrank;          // rank in, row out
+};
+
+// one wavefront per work item (a grid-stride loop), one lane per entry (items hold at most 64)
+__device__ inline void jpos_body(const JPosArgs &a, int blk, int nblk) {
+    const int lane = threadIdx.x & 63;
+    const int total = a.totals[2];
+    for (int t = blk * 4 + (threadIdx.x >> 6); t < total; t += nblk * 4) {
+        const int4 it = a.items[t];
+        const int e = it.y + lane;
+        if (e < it.z) a.jrank[e] += a.jstart[a.entries[e].cj];
+    }
+}
+
+constexpr int kJposBlocks = 1024;   // workgroups of the position pass (per replica in a batch: 256)
+
+__global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x, gridDim.x); }
 
 // --------------------------------------------------------------------------
 // Second stage of a two-stage list (Sec. 2.3: the list built from bounding
@@ -525,6 +549,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
 
 struct ListJob {
     SearchArgs a;
+    JPosArgs jp;
     int nregions, per_item;
     int *part_count, *part_start, *part_istart, *totals;
     int4 *items;
@@ -532,7 +557,7 @@ struct ListJob {
     int *flags;
 };
 
-enum { LS_SEARCH, LS_ITEMS, LS_NSTAGES };
+enum { LS_SEARCH, LS_ITEMS, LS_JPOS, LS_NSTAGES };
 
 __device__ inline int job_of(const int *off, int n, int b) {
     int lo = 0, hi = n - 1;   // last r with off[r] <= b
@@ -560,6 +585,11 @@ __global__ void kb_items(const ListJob *J, const int *off, int n) {
 __global__ void kb_finalize(const ListJob *J) {
     const ListJob &j = J[blockIdx.x];
     finalize_body(j.totals, j.cap_items, j.flags);
+}
+
+__global__ __launch_bounds__(256) void kb_jpos(const ListJob *J, const int *off, int n) {
+    const int r = job_of(off, n, blockIdx.x);
+    jpos_body(J[r].jp, blockIdx.x - off[r], off[r + 1] - off[r]);
 }
 
 
@@ -604,6 +634,16 @@ static SearchArgs make_search(const nb_list *l, const int *excl_off, const int *
 }
 
 
+static JPosArgs make_jpos(const nb_list *l) {
+    JPosArgs v{};
+    v.totals = (const int *)l->totals.p;
+    v.items = (const int4 *)l->items.p;
+    v.entries = (const nb_jentry *)l->entries.p;
+    v.jstart = (const int *)l->jstart.p;
+    v.jrank = (int *)l->jrank.p;
+    return v;
+}
+
 // item offsets per region (totals[0] = entries, totals[1] = items) and the work items
 static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
     const int pe = item_entries(l->grid->nn);
@@ -614,11 +654,13 @@ static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
                                                   l->cap_items, (int4 *)l->items.p);
 }
 
-// usable item count (overflow check) and the first row of each j-cluster
+// usable item count (overflow check), the first row of each j-cluster and every entry's row
 static void finish_view(nb_list *l, hipStream_t st) {
     const nb_grid *g = l->grid;
     k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, l->ctx->d_flags);
     launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
+    const int nb = (int)std::min<long>((l->cap_items + 3) / 4, kJposBlocks);
+    k_jpos<<<std::max(nb, 1), 256, 0, st>>>(make_jpos(l));
 }
 
 size_t list_job_size() { return sizeof(ListJob); }
@@ -631,6 +673,7 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.a = make_search(l, excl_off, excl_idx);
     j.a.jcount = (int *)l->jcount.p;
     j.a.jrank = (int *)l->jrank.p;
+    j.jp = make_jpos(l);
     j.a.parts = l->resv_parts;
     j.a.entries = (nb_jentry *)l->entries.p;
     j.a.keys = nullptr;
@@ -653,6 +696,7 @@ void list_job_blocks(const nb_list *l, int *blocks_per_stage) {
     const long nreg = (long)l->resv_nci * l->resv_parts;
     blocks_per_stage[LS_SEARCH] = (int)((nreg + 3) / 4);
     blocks_per_stage[LS_ITEMS] = (int)((nreg + 255) / 256);
+    blocks_per_stage[LS_JPOS] = (int)std::max(1L, std::min<long>((l->cap_items + 3) / 4, kJposBlocks / 4));
 }
 
 int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const int *off, int n_rep, const int *total,
@@ -667,6 +711,7 @@ int launch_pairlist_batch(hipStream_t st, int m, int nn, const void *jobs, const
     kb_items<<<total[LS_ITEMS], 256, 0, st>>>(J, off + LS_ITEMS * stride, n_rep);
     kb_finalize<<<n_rep, 64, 0, st>>>(J);
     launch_scan_batch(scans + n_rep, n_rep, st);
+    kb_jpos<<<total[LS_JPOS], 256, 0, st>>>(J, off + LS_JPOS * stride, n_rep);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
