@@ -285,9 +285,25 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
  *     kernel); passes whose pairs are all beyond rc skip the interaction.
  *   NB_FORCE_COMPACT: in-range pairs of each work item are first compacted
  *     through LDS into full wavefront passes.
- * Results agree to rounding; the choice is a tuning knob. */
-enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1 };
+ *   NB_FORCE_SUPER: the super-cluster layout of the paper's GPU kernel
+ *     (Sec. 2.3 and 3.2): 8 (or 4) consecutive i-clusters share one list
+ *     of j-clusters, each with a bit per i-cluster it reaches, so each
+ *     j-cluster's data is loaded and its j-force reduced and stored once per
+ *     super-cluster.  The view is built from the list by the first force
+ *     call after each build (or every call, for lists rebuilt inside a
+ *     captured batch graph).  Applies to 8x8 lists whose reserved entries
+ *     per i-cluster (all its search parts) are at most 512 (8 i-clusters
+ *     per super-cluster) or 1024 (4); other lists use the direct kernel.
+ * Results agree to rounding; the choice is a tuning knob.  Each variant's
+ * forces are reproducible bit for bit for a given list and positions. */
+enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1, NB_FORCE_SUPER = 2 };
 int nb_set_force_variant(nb_ctx *ctx, int variant);
+
+/* Super-cluster layout: i-clusters per super-cluster (4 or 8, or 0 for the
+ * largest that fits) and super-cluster entries per force work item (one
+ * wavefront each; 1..64, or 0 for the default 16).  Takes effect at the
+ * next force call (which rebuilds the view). */
+int nb_set_super_cluster(nb_ctx *ctx, int clusters, int entries);
 
 /* Wavefronts that share the pair search of one i-cluster (each takes a
  * contiguous share of the candidate grid columns of every image shift): 1, 2,

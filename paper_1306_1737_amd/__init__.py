@@ -30,14 +30,14 @@ EXPORTS = [
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_pairlist_prune", "nb_rdf", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
-    "nb_list_stats", "nb_set_force_variant", "nb_set_search_parts", "nb_recount",
+    "nb_list_stats", "nb_set_force_variant", "nb_set_super_cluster", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp",
     "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
     "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
-NB_FORCE_DIRECT, NB_FORCE_COMPACT = 0, 1
+NB_FORCE_DIRECT, NB_FORCE_COMPACT, NB_FORCE_SUPER = 0, 1, 2
 NB_COULOMB_EWALD, NB_COULOMB_RF, NB_COULOMB_EWALD_TABLE = 0, 1, 2
 NB_RDF_SKIP_EXCLUDED = 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
@@ -108,7 +108,7 @@ def lib():
                                     ip], i),
             "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
             "nb_list_stats": ([vp, vp, vp, vp, f, vp], i),
-            "nb_set_force_variant": ([vp, i], i),
+            "nb_set_force_variant": ([vp, i], i), "nb_set_super_cluster": ([vp, i, i], i),
             "nb_set_search_parts": ([vp, i], i),
             "nb_recount": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), f, f, i, vp], i),
             "nb_mlp_create": ([vp, vp, vp, vp, pvp], i), "nb_mlp_free": ([vp], None),
@@ -285,6 +285,10 @@ def make_params(rc, beta, coulomb_f, c6c12, shift_energies=True, coulomb=0, eps_
 
 def nb_set_force_variant(ctx, variant):
     _check(lib().nb_set_force_variant(ctx, int(variant)))
+
+
+def nb_set_super_cluster(ctx, clusters=0, entries=0):
+    _check(lib().nb_set_super_cluster(ctx, int(clusters), int(entries)))
 
 
 def nb_set_search_parts(ctx, parts):

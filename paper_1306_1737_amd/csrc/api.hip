@@ -313,7 +313,9 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
 static void list_release(nb_list *l) {
     DevBuf *bufs[] = {&l->entries,    &l->entries_canon, &l->keys,        &l->items,  &l->part_count,
                       &l->part_start, &l->part_istart,   &l->totals,      &l->jcount, &l->jstart,
-                      &l->jrank,      &l->jrank_canon,   &l->fj,          &l->fi};
+                      &l->jrank,      &l->jrank_canon,   &l->fj,          &l->fi,
+                      &l->sci_ent,    &l->sci_mask,      &l->sci_count,   &l->sci_base, &l->sci_istart,
+                      &l->sci_items,  &l->sci_jcount,    &l->sci_jstart,  &l->sci_totals, &l->sci_fi};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -489,9 +491,19 @@ int nb_set_search_parts(nb_ctx *c, int parts) {
 
 int nb_set_force_variant(nb_ctx *c, int variant) {
     if (!c) return fail(NB_ERR_ARG, "nb_set_force_variant: ctx is null");
-    if (variant != NB_FORCE_COMPACT && variant != NB_FORCE_DIRECT)
+    if (variant != NB_FORCE_COMPACT && variant != NB_FORCE_DIRECT && variant != NB_FORCE_SUPER)
         return fail(NB_ERR_ARG, "nb_set_force_variant: unknown variant");
     c->force_variant = variant;
+    return NB_OK;
+}
+
+int nb_set_super_cluster(nb_ctx *c, int clusters, int entries) {
+    if (!c) return fail(NB_ERR_ARG, "nb_set_super_cluster: ctx is null");
+    if (clusters != 0 && clusters != 4 && clusters != 8)
+        return fail(NB_ERR_ARG, "nb_set_super_cluster: clusters must be 0 (automatic), 4 or 8");
+    if (entries < 0 || entries > 64) return fail(NB_ERR_ARG, "nb_set_super_cluster: entries must be 0..64");
+    c->sci_clusters = clusters;
+    c->sci_per_item = entries;
     return NB_OK;
 }
 
@@ -512,8 +524,8 @@ int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_n
         return fail(NB_ERR_ARG, "nb_forces: unknown coulomb type");
     if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
         return fail(NB_ERR_ARG, "nb_forces: eps_rf must be >= 1, or 0 for a conducting boundary");
-    if (p->coulomb != NB_COULOMB_EWALD && c->force_variant != NB_FORCE_DIRECT)
-        return fail(NB_ERR_UNSUPPORTED, "nb_forces: reaction field and the Ewald table need the direct kernel");
+    if (p->coulomb != NB_COULOMB_EWALD && c->force_variant == NB_FORCE_COMPACT)
+        return fail(NB_ERR_UNSUPPORTED, "nb_forces: reaction field and the Ewald table need the direct or super-cluster kernel");
     if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
         return fail(NB_ERR_UNSUPPORTED, "nb_forces: beta*rc > 4 is outside the fitted Ewald range");
     MXN_HIP(hipSetDevice(c->device));
@@ -862,6 +874,7 @@ static int launch_rebuild(nb_ctx *c, nb_batch *b) {
     for (int r = 0; r < b->n_rep; ++r) {   // every replica's grid and list are now one generation newer
         ++b->grids[r]->generation;
         b->lists[r]->grid_generation = b->grids[r]->generation;
+        b->lists[r]->sci_valid = false;
     }
     return NB_OK;
 }
@@ -898,6 +911,7 @@ int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *
     hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? launch_rebuild(c, b) : NB_ERR_HIP;
     b->cycle = true;
+    for (int r = 0; r < b->n_rep; ++r) b->lists[r]->sci_volatile = true;   // graph replays rebuild these lists
     for (int k = 0; k < nsteps && rc == NB_OK; ++k) rc = launch_batch(c, b, p, flags, energy, virial);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);

@@ -68,6 +68,7 @@ struct ForceArgs {
     double *energy, *virial;
     int ener, vir;
     int parts;         // regions per i-cluster
+    int sci;           // i-clusters per work-item group of the fold's i-forces (super-cluster kernel), else 1
     int n;
     const int4 *items;
     const nb_jentry *entries;
@@ -141,74 +142,83 @@ __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
     }
 }
 
+// Force factor F/r of one pair within the cut-off, and its energy terms
+// added to el (Lennard-Jones) and ec (Coulomb).  Coulomb variants (ELEC):
+// 0 Ewald with erfc from a rational approximation; 1 reaction field,
+// F/r = qq (e/r^3 - 2k), V = qq (e/r + k r^2 - c); 2 Ewald with
+// F/r = qq (e/r^3 - G(r)) and V = qq (e/r - H(r) - e shift), where
+// G = (erf(beta r)/r - 2 beta/sqrt(pi) exp(-beta^2 r^2)) / r^2 and
+// H = erf(beta r)/r are smooth (finite at r = 0) and interpolated linearly
+// from the LDS table; e = bit = 1 for an interacting pair, 0 for an
+// excluded one (which keeps its Ewald correction and reads the all-zero
+// LJ row).  ljrow: the type pair's row of the LDS table.
+template <bool ENER, int ELEC>
+__device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const float2 *tab, float r2, float qq,
+                                  bool bit, int ljrow, float &el, float &ec) {
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    float fsc, vc;
+    if (ELEC == 0) {
+        const float u = r2 * rinv * a.beta;
+        const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
+        // erfc(u) = exp(-u^2) P(u) / Q(u)
+        const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
+        const float Q =
+            fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u, 1.0f);
+        const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
+        const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+        vc = em * rinv;
+        fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+    } else if (ELEC == 1) {
+        const float einv = bit ? rinv : 0.0f;
+        vc = einv + fmaf(a.krf, r2, -a.crf);
+        fsc = qq * fmaf(einv, rinv2, -a.k2rf);
+    } else {
+        const float t = r2 * rinv * a.tab_scale;
+        const int i0 = (int)t;
+        const float eps = t - (float)i0;
+        const float2 g0 = tab[i0], g1 = tab[i0 + 1];
+        const float einv = bit ? rinv : 0.0f;
+        vc = einv - fmaf(eps, g1.y - g0.y, g0.y);
+        fsc = qq * fmaf(einv, rinv2, -fmaf(eps, g1.x - g0.x, g0.x));
+    }
+    const float4 lj = ljt[bit ? ljrow : a.nt * a.nt];   // the zero row for a clear bit
+    const float c6 = lj.x, c12 = lj.y;
+    const float rinv6 = rinv2 * rinv2 * rinv2;
+    const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
+    fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+    if (ENER) {
+        el += t12 - t6 - lj.z;
+        ec += qq * (ELEC == 1 ? vc : vc - lj.w);   // the reaction field's c is in vc
+    }
+    return fsc;
+}
+
 // One pass of the direct kernel's inner loop: this lane's j-particle against
 // the M i-particles.  Measured slower on gfx950, and therefore not used:
 // a uniform mask-free copy of this loop for passes without exclusions (the
 // duplicated body costs more than the selects it saves); a branch-free body
 // whose eight i-particle chains the compiler can interleave (132 registers,
 // occupancy 3: 240 us against 198 us on the 96k-atom box).
-// Coulomb variants (ELEC): 0 Ewald with erfc from a rational approximation;
-// 1 reaction field, F/r = qq (e/r^3 - 2k), V = qq (e/r + k r^2 - c); 2 Ewald
-// with F/r = qq (e/r^3 - G(r)) and V = qq (e/r - H(r) - e shift), where
-// G = (erf(beta r)/r - 2 beta/sqrt(pi) exp(-beta^2 r^2)) / r^2 and
-// H = erf(beta r)/r are smooth (finite at r = 0) and interpolated linearly
-// from the LDS table; e = 1 for a set mask bit, 0 for an excluded pair.
 template <int M, bool ENER, int ELEC>
 __device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float2 *tab, const float (&xi)[M],
                                  const float (&yi)[M], const float (&zi)[M], const float (&qi)[M], const int (&ti)[M],
                                  float xj, float yj, float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l,
                                  float (&fix)[M], float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz,
                                  float &el, float &ec) {
-    const int znull = a.nt * a.nt;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2l && ((act >> k) & 1u)) {
             const bool bit = (mb >> k) & 1u;
-            const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float rinv2 = rinv * rinv;
-            const float qq = qi[k] * qj;
-            float fsc, vc;
-            if (ELEC == 0) {
-                const float u = r2 * rinv * a.beta;
-                const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
-                // erfc(u) = exp(-u^2) P(u) / Q(u)
-                const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
-                const float Q =
-                    fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u, 1.0f);
-                const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
-                const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
-                vc = em * rinv;
-                fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
-            } else if (ELEC == 1) {
-                const float einv = bit ? rinv : 0.0f;
-                vc = einv + fmaf(a.krf, r2, -a.crf);
-                fsc = qq * fmaf(einv, rinv2, -a.k2rf);
-            } else {
-                const float t = r2 * rinv * a.tab_scale;
-                const int i0 = (int)t;
-                const float eps = t - (float)i0;
-                const float2 g0 = tab[i0], g1 = tab[i0 + 1];
-                const float einv = bit ? rinv : 0.0f;
-                vc = einv - fmaf(eps, g1.y - g0.y, g0.y);
-                fsc = qq * fmaf(einv, rinv2, -fmaf(eps, g1.x - g0.x, g0.x));
-            }
-            const float4 lj = ljt[bit ? ti[k] + tj : znull];   // the zero row for a clear bit
-            const float c6 = lj.x, c12 = lj.y;
-            const float rinv6 = rinv2 * rinv2 * rinv2;
-            const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
-            fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+            const float fsc = pair_term<ENER, ELEC>(a, ljt, tab, r2, qi[k] * qj, bit, ti[k] + tj, el, ec);
             fix[k] = fmaf(fsc, dx, fix[k]);
             fiy[k] = fmaf(fsc, dy, fiy[k]);
             fiz[k] = fmaf(fsc, dz, fiz[k]);
             fjx = fmaf(-fsc, dx, fjx);
             fjy = fmaf(-fsc, dy, fjy);
             fjz = fmaf(-fsc, dz, fjz);
-            if (ENER) {
-                el += t12 - t6 - lj.z;
-                ec += qq * (ELEC == 1 ? vc : vc - lj.w);   // the reaction field's c is in vc
-            }
         }
     }
 }
@@ -357,6 +367,197 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     force_item<M, N, ENER, VIR, ACC64, ELEC>(a, v, ljt, tab, svec, (int)item, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Super-cluster kernel (8x8 clusters).  The GPU layout of Sec. 2.3 and 3.2:
+// S consecutive i-clusters form a super-cluster whose list holds each
+// j-cluster (with its image shift) once, with a bit per i-cluster that has
+// the pair and that pair's exclusion mask.  A wavefront owns a run of such
+// super-cluster entries; lane = 8 b + a holds i-particle a of every
+// i-cluster of the super-cluster (registers) and j-particle b of the
+// current entry, so one pass evaluates the 64 pairs of one cluster pair and
+// the list's j-major mask bit b*8 + a is the lane's own bit: the mask and
+// the half-list triangle act as lane masks straight from scalar registers.
+// The i-clusters an entry does not reach are skipped without cost (uniform
+// branch).  Per entry the j-forces, summed over the S cluster pairs in
+// registers, are reduced over the 8 a-lanes with DPP and stored once into
+// the entry's row, so a j-cluster has one row per super-cluster that
+// reaches it instead of one per i-cluster; i-forces are reduced across the
+// wavefront once per work item and stored per (item, i-particle).  Dummy
+// slots are moved far apart (i to +1e20, j to -1e20 in x), so that their
+// squared distance overflows to infinity and fails the cut-off test.
+constexpr float kFarX = 1.0e20f;
+
+constexpr unsigned long long upper_triangle_lanes() {   // lanes 8b + a with a < b
+    unsigned long long m = 0;
+    for (int l = 0; l < 64; ++l)
+        if ((l & 7) < (l >> 3)) m |= 1ull << l;
+    return m;
+}
+
+// sum over the 8 lanes of each aligned octet (DPP: quad swaps, then the half-row mirror)
+__device__ inline float octet_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));   // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false));   // [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false));  // half mirror
+    return v;
+}
+
+// sum over the lanes with equal (lane & 7)
+__device__ inline float stride8_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));  // row_ror 8
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// The cluster pairs of one super-cluster entry: for each i-cluster g that the
+// entry reaches (bit g of gm), one pass of the 64 pairs with the pair's
+// exclusion mask (slot g of the entry's mask record).  selfg: the i-cluster
+// that is the entry's j-cluster itself (zero shift; -1 if none), whose pass
+// takes the half-list triangle a < b only.
+template <int S, bool ENER, int ELEC>
+__device__ inline void sci_entry(const ForceArgs &a, const float4 *ljt, const float2 *tab, const uint2 *mrec, int gm,
+                                 int selfg, const float4 *ip, const int *it, float xj, float yj, float zj, float qj,
+                                 int tj, float (&fix)[S], float (&fiy)[S], float (&fiz)[S], float &fjx, float &fjy,
+                                 float &fjz, float &el, float &ec) {
+    constexpr unsigned long long kUpper = upper_triangle_lanes();
+    uint2 mw[S];   // the whole record at once (one scalar load; unreached slots are not used)
+#pragma unroll
+    for (int g = 0; g < S; ++g) mw[g] = mrec[g];
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+        if ((gm >> g) & 1) {
+            const unsigned long long m64 = ((unsigned long long)mw[g].y << 32) | mw[g].x;
+            const float4 pi = ip[g * 8];   // (x, y, z, f q) of i-particle a of i-cluster g
+            const float dx = pi.x - xj, dy = pi.y - yj, dz = pi.z - zj;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (__builtin_amdgcn_inverse_ballot_w64(g == selfg ? kUpper : ~0ull) && r2 < a.rc2) {
+                const bool bit = __builtin_amdgcn_inverse_ballot_w64(m64);
+                const float fsc = pair_term<ENER, ELEC>(a, ljt, tab, r2, pi.w * qj, bit, it[g * 8] + tj, el, ec);
+                fix[g] = fmaf(fsc, dx, fix[g]);
+                fiy[g] = fmaf(fsc, dy, fiy[g]);
+                fiz[g] = fmaf(fsc, dz, fiz[g]);
+                fjx = fmaf(-fsc, dx, fjx);
+                fjy = fmaf(-fsc, dy, fjy);
+                fjz = fmaf(-fsc, dz, fjz);
+            }
+        }
+    }
+}
+
+template <int S, bool ENER, bool VIR, bool ACC64, int ELEC>
+__global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__restrict__ sent,
+                                                    const uint2 *__restrict__ smask,
+                                                    const int4 *__restrict__ sitems) {
+    using acc_t = typename std::conditional<ACC64, double, float>::type;
+    const long total = a.totals[2];
+    if (xcd_block_first(total, 4) < 0) return;
+    extern __shared__ float4 smem[];
+    float4 *svec = smem;
+    float4 *ljt = smem + 32;
+    float2 *tab = reinterpret_cast<float2 *>(smem + 32 + a.nt * a.nt + 1);
+    // per wavefront: its super-cluster's i-particles, (x, y, z, f q) and the type row
+    const int ioff = 32 + a.nt * a.nt + 1 + (ELEC == 2 ? (a.ntab + 1) / 2 : 0);
+    float4 *ipw = smem + ioff + (threadIdx.x >> 6) * S * 8;
+    int *itw = reinterpret_cast<int *>(smem + ioff + 4 * S * 8) + (threadIdx.x >> 6) * S * 8;
+    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
+    fill_ljt(a, ljt);
+    if (ELEC == 2)
+        for (int t = threadIdx.x; t < a.ntab; t += blockDim.x) tab[t] = a.etab[t];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const long item = xcd_item(total, 4, threadIdx.x >> 6);
+    if (item < 0) return;
+    const int4 it = sitems[item];
+    const int grp = __builtin_amdgcn_readfirstlane(it.x);
+    const int js = __builtin_amdgcn_readfirstlane(it.y);
+    const int je = __builtin_amdgcn_readfirstlane(it.z);
+    const int ia = lane & 7, jb = lane >> 3;
+    const int ci0 = grp * S;
+    const int nci = *a.nslots / 8;
+    const gptr<const float4> xs = (gptr<const float4>)a.xs_now;
+    const gptr<const int> types = (gptr<const int>)a.type_s;
+    if (jb < S) {   // lane (a, b) stages i-particle a of i-cluster b
+        const bool in = ci0 + jb < nci;
+        const int slot = in ? (ci0 + jb) * 8 + ia : ia;
+        const float4 p = ld(xs + slot);
+        const int t = in ? types[slot] : -1;
+        ipw[lane] = make_float4(t >= 0 ? p.x : kFarX, p.y, p.z, p.w * a.coulomb_f);
+        itw[lane] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the wavefront's staging is visible to all its lanes
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float4 *ip = ipw + ia;
+    const int *itp = itw + ia;
+    float fix[S], fiy[S], fiz[S];
+#pragma unroll
+    for (int g = 0; g < S; ++g) fix[g] = fiy[g] = fiz[g] = 0.0f;
+    acc_t elj = 0, ec = 0;
+    acc_t vir[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vir[k] = 0;
+
+    for (int e = js; e < je; ++e) {
+        const int4 en = sent[e];   // uniform: scalar load
+        const int cj = en.x, shift = en.y & 31, gm = (en.y >> 8) & 255, selfg = ((en.y >> 16) & 15) - 1, row = en.w;
+        const uint2 *mrec = smask + (long)e * S;   // exclusion mask of i-cluster g in slot g
+        const int jslot = cj * 8 + jb;
+        const float4 pj = ld(xs + jslot);
+        const int tjr = types[jslot];
+        const int tj = min(max(tjr, 0), a.nt - 1);
+        const float4 sv = svec[shift];
+        const float xj = tjr >= 0 ? pj.x - sv.x : -kFarX, yj = pj.y - sv.y, zj = pj.z - sv.z;
+        const float qj = pj.w;
+        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
+        sci_entry<S, ENER, ELEC>(a, ljt, tab, mrec, gm, selfg, ip, itp, xj, yj, zj, qj, tj, fix, fiy, fiz, fjx, fjy,
+                                 fjz, el, ecl);
+        if (ENER) {
+            elj += (acc_t)el;
+            ec += (acc_t)ecl;
+        }
+        if (VIR) {   // this lane's share of the j-force (the octet sum is linear)
+            vir[0] += (acc_t)(xj * fjx); vir[1] += (acc_t)(xj * fjy); vir[2] += (acc_t)(xj * fjz);
+            vir[3] += (acc_t)(yj * fjx); vir[4] += (acc_t)(yj * fjy); vir[5] += (acc_t)(yj * fjz);
+            vir[6] += (acc_t)(zj * fjx); vir[7] += (acc_t)(zj * fjy); vir[8] += (acc_t)(zj * fjz);
+        }
+        fjx = octet_sum(fjx);
+        fjy = octet_sum(fjy);
+        fjz = octet_sum(fjz);
+        if (ia < 3) {   // lanes a = 0, 1, 2 of octet b store its x, y, z: one 96-byte row
+            const float c = ia == 0 ? fjx : (ia == 1 ? fjy : fjz);
+            ((gptr<float>)a.fj)[((long)row * 8 + jb) * 3 + ia] = c;
+        }
+    }
+    acc_t viri[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) viri[k] = 0;
+    const gptr<float4> fo = (gptr<float4>)a.fi;
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+        const float fx = stride8_sum(fix[g]), fy = stride8_sum(fiy[g]), fz = stride8_sum(fiz[g]);
+        if (jb == 0) {
+            mxn::st(fo + ((long)item * S + g) * 8 + ia, make_float4(fx, fy, fz, 0.0f));
+            const float4 pi = ip[g * 8];
+            if (VIR && pi.x != kFarX) {
+                viri[0] += (acc_t)pi.x * (acc_t)fx; viri[1] += (acc_t)pi.x * (acc_t)fy; viri[2] += (acc_t)pi.x * (acc_t)fz;
+                viri[3] += (acc_t)pi.y * (acc_t)fx; viri[4] += (acc_t)pi.y * (acc_t)fy; viri[5] += (acc_t)pi.y * (acc_t)fz;
+                viri[6] += (acc_t)pi.z * (acc_t)fx; viri[7] += (acc_t)pi.z * (acc_t)fy; viri[8] += (acc_t)pi.z * (acc_t)fz;
+            }
+        }
+    }
+    if (ENER || VIR) {
+        acc_t out[kNAcc];
+        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[1] = ENER ? wave_sum(ec) : (acc_t)0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k] + viri[k]) : (acc_t)0;
+        if (lane == 0)
+            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
+    }
+}
+
 // Forces of one j-cluster's N slots: the j-forces in the j-cluster's rows
 // plus the i-forces stored by the work items of the i-cluster(s) holding
 // these slots; written to the caller's array in input order (or added to it).
@@ -374,6 +575,7 @@ struct FoldView {
     gptr<const float4> fi;
     float *f_out;
     int parts, accumulate;
+    int sci;   // i-clusters per item group: the i-forces of cluster c are slot c % sci of group c / sci's items
 };
 
 constexpr float kFixScale = 67108864.0f;           // 2^26
@@ -421,9 +623,10 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
             }
         }
         const int ci = s / M, o = s % M;
-        const int t1 = v.part_istart[(ci + 1) * v.parts];
-        for (int t = v.part_istart[ci * v.parts] + g; t < t1; t += G) {
-            const float4 f = ld(v.fi + (long)t * M + o);
+        const int gi = ci / v.sci, sub = ci % v.sci;
+        const int t1 = v.part_istart[(gi + 1) * v.parts];
+        for (int t = v.part_istart[gi * v.parts] + g; t < t1; t += G) {
+            const float4 f = ld(v.fi + ((long)t * v.sci + sub) * M + o);
             sx += to_fix(f.x, bad);
             sy += to_fix(f.y, bad);
             sz += to_fix(f.z, bad);
@@ -515,7 +718,7 @@ __global__ __launch_bounds__(256) void k_fold(ForceArgs a) {
     const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,   (gptr<const int>)a.totals,
                      (gptr<const int>)a.jstart, (gptr<const int>)a.part_istart,
                      (gptr<const float>)a.fj,   (gptr<const float4>)a.fi,  a.f_out,
-                     a.parts,                   a.accumulate};
+                     a.parts,                   a.accumulate,              a.sci > 1 ? a.sci : 1};
     fold_body<M, N>(v, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
     if (ACC == 1) fold_energy<false>(a);
     if (ACC == 2) fold_energy<true>(a);
@@ -793,7 +996,7 @@ void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
 
 template <int M, int N, bool E, bool V, bool D>
 void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t st) {
-    if (variant == NB_FORCE_DIRECT) {
+    if (variant != NB_FORCE_COMPACT) {   // direct (also for lists the super-cluster kernel does not take)
         if (a.elec == NB_COULOMB_RF)
             k_forces<M, N, E, V, D, 1><<<nb, 256, lds, st>>>(a);
         else if (a.elec == NB_COULOMB_EWALD_TABLE)
@@ -802,6 +1005,33 @@ void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t s
             k_forces<M, N, E, V, D, 0><<<nb, 256, lds, st>>>(a);
     } else
         k_forces_c<M, N, E, V, D><<<nb, 256, lds + 4 * wave_lds_bytes<N>(), st>>>(a);
+}
+
+template <int S, bool E, bool V, bool D>
+void launch_sci_k(const ForceArgs &a, const int4 *sent, const uint2 *smask, const int4 *sitems, int nb, size_t lds,
+                  hipStream_t st) {
+    lds += 4 * S * 8 * (sizeof(float4) + sizeof(int));   // staged i-particles of the four wavefronts
+    if (a.elec == NB_COULOMB_RF)
+        k_forces_sci<S, E, V, D, 1><<<nb, 256, lds, st>>>(a, sent, smask, sitems);
+    else if (a.elec == NB_COULOMB_EWALD_TABLE)
+        k_forces_sci<S, E, V, D, 2><<<nb, 256, lds + (size_t)(a.ntab + 1) / 2 * sizeof(float4), st>>>(a, sent, smask,
+                                                                                                    sitems);
+    else
+        k_forces_sci<S, E, V, D, 0><<<nb, 256, lds, st>>>(a, sent, smask, sitems);
+}
+
+template <int S>
+void launch_sci(const ForceArgs &a, const nb_list *l, unsigned flags, int nb, size_t lds, hipStream_t st) {
+    const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL, D = !(flags & NB_ACC_FP32);
+    const int4 *se = (const int4 *)l->sci_ent.p, *si = (const int4 *)l->sci_items.p;
+    const uint2 *sm = (const uint2 *)l->sci_mask.p;
+    if (E && V && D) launch_sci_k<S, true, true, true>(a, se, sm, si, nb, lds, st);
+    else if (E && V) launch_sci_k<S, true, true, false>(a, se, sm, si, nb, lds, st);
+    else if (E && D) launch_sci_k<S, true, false, true>(a, se, sm, si, nb, lds, st);
+    else if (E) launch_sci_k<S, true, false, false>(a, se, sm, si, nb, lds, st);
+    else if (V && D) launch_sci_k<S, false, true, true>(a, se, sm, si, nb, lds, st);
+    else if (V) launch_sci_k<S, false, true, false>(a, se, sm, si, nb, lds, st);
+    else launch_sci_k<S, false, false, true>(a, se, sm, si, nb, lds, st);
 }
 
 template <int M, int N>
@@ -938,7 +1168,7 @@ __global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
     const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,   (gptr<const int>)d.totals,
                      (gptr<const int>)d.jstart, (gptr<const int>)d.part_istart,
                      (gptr<const float>)d.fj,   (gptr<const float4>)d.fi,  d.f_out,
-                     d.parts,                   b.accumulate};
+                     d.parts,                   b.accumulate,              1};
     fold_body<M, N>(v, (int)((g0 - b.slot_off[r]) / N), threadIdx.x & 63);
 }
 
@@ -1069,11 +1299,21 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
                   unsigned flags, float *f, double *energy, double *virial) {
     hipStream_t st = ctx->stream;
     const bool need_acc = flags & (NB_ENERGY | NB_VIRIAL);
+    // super-cluster view: (re)built by the first call after a list build
+    const int S = ctx->force_variant == NB_FORCE_SUPER ? sci_size(l, ctx->sci_clusters) : 0;
+    if (S) {
+        const int per = ctx->sci_per_item > 0 ? ctx->sci_per_item : kSciPerItem;
+        if (!l->sci_valid || l->sci_volatile || l->sci_S != S || l->sci_per_item != per) {
+            int rc = launch_sci_view(l, S, per);
+            if (rc) return rc;
+        }
+    }
+    const long cap_items = S ? l->sci_cap_items : l->cap_items;
     if (need_acc) {
-        int rc = ensure(ctx->partials, (size_t)(l->cap_items + 4) * kNAcc * sizeof(double));
+        int rc = ensure(ctx->partials, (size_t)(cap_items + 4) * kNAcc * sizeof(double));
         if (rc) return rc;
     }
-    const long pstride = l->cap_items + 4;
+    const long pstride = cap_items + 4;
     ForceArgs a{};
     a.nslots = (const int *)g->nslots.p;
     a.perm = (const int *)g->perm.p;
@@ -1117,6 +1357,15 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         a.tab_scale = (float)kTabScale;
     }
     a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
+    a.sci = 1;
+    if (S) {   // the fold reads the view's rows, i-forces and items
+        a.fi = (float4 *)l->sci_fi.p;
+        a.jstart = (const int *)l->sci_jstart.p;
+        a.part_istart = (const int *)l->sci_istart.p;
+        a.parts = 1;
+        a.totals = (const int *)l->sci_totals.p;
+        a.sci = S;
+    }
     a.partials = (double *)ctx->partials.p;
     a.pstride = pstride;
     a.f_out = f;
@@ -1134,7 +1383,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         a.vir = (flags & NB_VIRIAL) ? 1 : 0;
     }
     k_gather<<<(g->slots_cap + 255) / 256, 256, 0, st>>>(a);
-    const long nwaves = l->cap_items;
+    const long nwaves = cap_items;
     int nb = (int)((nwaves + 3) / 4);
     nb = (nb + 7) / 8 * 8;
     if (nb == 0) nb = 8;
@@ -1142,7 +1391,9 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
         const int var = ctx->force_variant;
-        if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, var, st);
+        if (S == 8) launch_sci<8>(a, l, flags, nb, lds, st);
+        else if (S == 4) launch_sci<4>(a, l, flags, nb, lds, st);
+        else if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, var, st);
         else if (g->m == 4 && g->nn == 8) launch_shape<4, 8>(a, flags, nb, lds, var, st);
         else if (g->m == 8 && g->nn == 4) launch_shape<8, 4>(a, flags, nb, lds, var, st);
         else launch_shape<8, 8>(a, flags, nb, lds, var, st);

@@ -70,6 +70,8 @@ struct nb_ctx {
     float etab_beta = -1.0f, etab_rc = -1.0f;
     bool timing = false;
     int force_variant = NB_FORCE_DIRECT;
+    int sci_clusters = 0;   // i-clusters per super-cluster (0: the largest that fits)
+    int sci_per_item = 0;   // super-cluster entries per work item (0: default)
     int search_parts = 0;   // 0: chosen from the number of i-clusters
     const nb_mlp *mlp = nullptr;   // attached buffer predictor (nb_buffer_set_mlp)
     double mlp_margin = 0.0;
@@ -123,8 +125,19 @@ struct nb_list {
     mxn::DevBuf fj, fi;
     int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
     int resv_nci = 0;          // i-cluster capacity of the reserved layout
+    long resv_size = 0;        // entries per region of the reserved layout
     long last_entries = 0;     // host copy after a synchronous build
     long grid_generation = -1;
+    // Super-cluster view (8x8 lists; the grouped force kernel): a cache built
+    // from the list by the first force call after each build.  Entries and
+    // masks use the list's capacity; rows reuse fj; items, their i-forces and
+    // the j-cluster counters, starts and totals are its own.
+    mutable mxn::DevBuf sci_ent, sci_mask, sci_count, sci_base, sci_istart, sci_items, sci_jcount, sci_jstart,
+        sci_totals, sci_fi;
+    mutable long sci_cap_items = 0, sci_njc = 0;
+    mutable int sci_S = 0, sci_per_item = 0;
+    mutable bool sci_valid = false;   // built from the list's latest build
+    bool sci_volatile = false;        // rebuilt inside a captured graph: the view is rebuilt by every call
 };
 
 struct nb_batch {
@@ -211,6 +224,10 @@ void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
 // at the grid's gathered positions (xs_now)
 int launch_prune(nb_list *in, const nb_list *outer, float r);
 int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now);
+// super-cluster view of an 8x8 list: i-clusters per super-cluster (0: none) and the build
+constexpr int kSciPerItem = 16;
+int sci_size(const nb_list *l, int want);
+int launch_sci_view(const nb_list *l, int S, int per_item);
 // pair distance histogram at the grid's gathered positions (xs_now)
 size_t rdf_lds_bytes(int nbins, int nt);
 int launch_rdf(nb_ctx *ctx, const nb_grid *g, const nb_list *l, float r_max, int nbins, int nt, int skip_excl,

@@ -542,6 +542,138 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// Super-cluster view of an 8x8 list (the grouped layout of Sec. 2.3 and 3.2:
+// S consecutive i-clusters share one list of j-clusters).  One workgroup per
+// super-cluster gathers the entries of its S i-clusters as 64-bit keys
+// (shift, j-cluster, i-cluster within the super-cluster, entry position),
+// sorts them in LDS (bitonic), and writes one super-cluster entry per
+// distinct (shift, j-cluster): (j-cluster, shift | i-cluster bits << 8 |
+// (self i-cluster + 1) << 16, 0, rank among the j-cluster's entries) and a
+// record of S exclusion masks, slot g for i-cluster g (slots of i-clusters
+// the entry does not reach are not written).  The self i-cluster is the
+// one the j-cluster is (zero shift), whose pass is a half triangle; 0 if
+// none.  Outputs go to the super-cluster's span of the list's regions (its
+// keys fit there, so its entries do too).  The order depends only on the
+// list, so the forces do as well.
+constexpr int kSciKeys = 4096;
+
+struct SciArgs {
+    const int *nslots;
+    const int *totals;   // the list's: [2] usable items (0 after an overflow)
+    const int *part_start, *part_count;
+    const nb_jentry *entries;
+    int parts, nregions, S, ngroups;
+    int4 *ent;
+    uint2 *mask;
+    int *count, *base;   // per super-cluster: entries; first position (base[ngroups]: end)
+    int *jcount;         // per j-cluster counters (zero before the pass)
+};
+
+// exclusive prefix of a flag over the 256 threads, and the flag count
+__device__ inline int block_flag_scan(bool f, int *sw, int &total) {
+    const unsigned long long b = __ballot(f);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+    if (lane == 0) sw[w] = __popcll(b);
+    __syncthreads();
+    int off = 0;
+    for (int k = 0; k < w; ++k) off += sw[k];
+    total = sw[0] + sw[1] + sw[2] + sw[3];
+    __syncthreads();
+    return off + r;
+}
+
+__global__ __launch_bounds__(256) void k_sci_view(SciArgs a) {
+    __shared__ unsigned long long key[kSciKeys];
+    __shared__ int roff[65];
+    __shared__ int sw[4];
+    const int grp = blockIdx.x, t = threadIdx.x;
+    const int span = a.S * a.parts;
+    const int r0 = min(grp * span, a.nregions), r1 = min(r0 + span, a.nregions);
+    const int base = a.part_start[r0];
+    if (t == 0) {
+        a.base[grp] = base;
+        if (grp == a.ngroups - 1) a.base[grp + 1] = a.part_start[r1];
+        const int nci = *a.nslots / 8;
+        const bool usable = a.totals[2] > 0;
+        int o = 0;
+        for (int r = r0; r < r1; ++r) {
+            roff[r - r0] = o;
+            const int cap = a.part_start[r + 1] - a.part_start[r];
+            o += (usable && r / a.parts < nci) ? min(a.part_count[r], cap) : 0;
+        }
+        roff[r1 - r0] = o;
+    }
+    __syncthreads();
+    const int n = min(roff[r1 - r0], kSciKeys);   // the host sizes S so that every span fits
+    for (int r = r0; r < r1; ++r) {
+        const int o = roff[r - r0], cnt = roff[r - r0 + 1] - o, s0 = a.part_start[r];
+        const unsigned g = (unsigned)((r - r0) / a.parts);
+        for (int k = t; k < cnt && o + k < kSciKeys; k += 256) {
+            const nb_jentry e = a.entries[s0 + k];
+            const unsigned kk = ((unsigned)e.shift << 27) | ((unsigned)e.cj << 3) | g;
+            key[o + k] = ((unsigned long long)kk << 32) | (unsigned)(s0 + k);
+        }
+    }
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int k = n + t; k < np; k += 256) key[k] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < np / 2; i += 256) {
+                const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long x = key[lo], y = key[hi];
+                if ((x > y) == up) {
+                    key[lo] = y;
+                    key[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    int done = 0;
+    for (int p0 = 0; p0 < n; p0 += 256) {
+        const int p = p0 + t;
+        unsigned long long kp = 0;
+        bool head = false;
+        if (p < n) {
+            kp = key[p];
+            head = p == 0 || (key[p - 1] >> 35) != (kp >> 35);
+        }
+        int tot;
+        const int idx = done + block_flag_scan(head, sw, tot);
+        if (head) {
+            const int cj = (int)((kp >> 35) & 0xFFFFFFu), shift = (int)(kp >> 59);
+            int gm = 0;
+            for (int q = p; q < n && (key[q] >> 35) == (kp >> 35); ++q) {
+                const int g = (int)((key[q] >> 32) & 7u);
+                const nb_jentry e = a.entries[(int)(unsigned)key[q]];
+                a.mask[(long)(base + idx) * a.S + g] = make_uint2(e.mlo, e.mhi);
+                gm |= 1 << g;
+            }
+            const int own = cj - grp * a.S;
+            const int self = (shift == 13 && own >= 0 && own < a.S) ? own + 1 : 0;
+            const int rank = atomicAdd(a.jcount + cj, 1);
+            a.ent[base + idx] = make_int4(cj, shift | (gm << 8) | (self << 16), 0, rank);
+        }
+        done += tot;
+    }
+    if (t == 0) a.count[grp] = done;
+}
+
+// rank -> row for every super-cluster entry of a usable work item
+__global__ __launch_bounds__(256) void k_sci_rows(const int *totals, const int4 *items, int4 *ent, const int *jstart) {
+    const int lane = threadIdx.x & 63;
+    const int total = totals[2];
+    for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < total; t += gridDim.x * 4) {
+        const int4 it = items[t];
+        const int e = it.y + lane;
+        if (e < it.z) ent[e].w += jstart[ent[e].x];
+    }
+}
+
+// --------------------------------------------------------------------------
 // Batched rebuild of many replicas' lists (the fill pass into the regions the
 // replicas' last synchronous builds sized), one launch per stage; a
 // workgroup finds its replica by binary search in the stage's prefix of
@@ -780,6 +912,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         l->resv_parts = parts;
         l->resv_nci = nci_cap;
         l->last_entries = ce;
+        l->resv_size = size;
     }
     if (by_distance) {   // the fill pass writes canonical order and keys; the sort orders each region
         int rc = ensure(l->entries_canon, (size_t)l->cap_entries * sizeof(nb_jentry));
@@ -807,7 +940,79 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
                                                 (nb_jentry *)l->entries.p, (const int *)l->jrank_canon.p,
                                                 (int *)l->jrank.p);
     finish_view(l, st);
+    l->sci_valid = false;
     MXN_HIP(hipGetLastError());
+    return NB_OK;
+}
+
+// i-clusters per super-cluster for a list (0: no super-cluster view): the
+// largest of 8 and 4 (at most want, if nonzero) whose span of regions fits
+// the LDS sort
+int sci_size(const nb_list *l, int want) {
+    const nb_grid *g = l->grid;
+    if (!g || g->m != 8 || g->nn != 8 || l->resv_parts <= 0 || l->resv_size <= 0) return 0;
+    if ((long)g->slots_cap / 8 >= (1L << 24)) return 0;   // j-cluster index in 24 key bits
+    for (int S = 8; S >= 4; S >>= 1)
+        if ((want == 0 || S <= want) && (long)S * l->resv_parts * l->resv_size <= kSciKeys) return S;
+    return 0;
+}
+
+// Build the super-cluster view of l (S i-clusters per super-cluster, per_item
+// entries per work item) on the context stream: keys and entries, work
+// items, the j-cluster rows of the entries.
+int launch_sci_view(const nb_list *l, int S, int per_item) {
+    const nb_grid *g = l->grid;
+    hipStream_t st = l->ctx->stream;
+    const int nregions = l->resv_nci * l->resv_parts;
+    const int ngroups = (l->resv_nci + S - 1) / S;
+    const long njc = g->slots_cap / g->nn;
+    const long cap_items = l->cap_entries / per_item + ngroups + 256;
+    void *old_jc = l->sci_jcount.p, *old_tot = l->sci_totals.p;
+    int rc = ensure(l->sci_ent, (size_t)l->cap_entries * sizeof(int4));
+    rc = rc ? rc : ensure(l->sci_mask, (size_t)l->cap_entries * S * sizeof(uint2));
+    rc = rc ? rc : ensure(l->sci_count, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->sci_base, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->sci_istart, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->sci_items, (size_t)cap_items * sizeof(int4));
+    rc = rc ? rc : ensure(l->sci_jcount, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(l->sci_jstart, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(l->sci_totals, 16);
+    rc = rc ? rc : ensure(l->sci_fi, (size_t)cap_items * S * 8 * sizeof(float4));
+    if (rc) return rc;
+    if (l->sci_jcount.p != old_jc || l->sci_njc != njc) {   // counters start cleared; the scan clears them after use
+        MXN_HIP(hipMemsetAsync(l->sci_jcount.p, 0, (size_t)(njc + 1) * 4, st));
+        l->sci_njc = njc;
+    }
+    if (l->sci_totals.p != old_tot) MXN_HIP(hipMemsetAsync(l->sci_totals.p, 0, 16, st));
+    SciArgs a{};
+    a.nslots = (const int *)g->nslots.p;
+    a.totals = (const int *)l->totals.p;
+    a.part_start = (const int *)l->part_start.p;
+    a.part_count = (const int *)l->part_count.p;
+    a.entries = (const nb_jentry *)l->entries.p;
+    a.parts = l->resv_parts;
+    a.nregions = nregions;
+    a.S = S;
+    a.ngroups = ngroups;
+    a.ent = (int4 *)l->sci_ent.p;
+    a.mask = (uint2 *)l->sci_mask.p;
+    a.count = (int *)l->sci_count.p;
+    a.base = (int *)l->sci_base.p;
+    a.jcount = (int *)l->sci_jcount.p;
+    int *tot = (int *)l->sci_totals.p;
+    k_sci_view<<<ngroups, 256, 0, st>>>(a);
+    launch_scan_mode(a.count, (int *)l->sci_istart.p, ngroups, 2, per_item, tot + 1, tot, st);
+    k_items<<<(ngroups + 255) / 256, 256, 0, st>>>(ngroups, 1, per_item, a.count, a.base,
+                                                  (const int *)l->sci_istart.p, cap_items, (int4 *)l->sci_items.p);
+    k_finalize<<<1, 64, 0, st>>>(tot, cap_items, l->ctx->d_flags);
+    launch_scan_clear(a.jcount, (int *)l->sci_jstart.p, (int)njc, st);
+    const int nb = (int)std::max<long>(1, std::min<long>((cap_items + 3) / 4, kJposBlocks));
+    k_sci_rows<<<nb, 256, 0, st>>>(tot, (const int4 *)l->sci_items.p, a.ent, (const int *)l->sci_jstart.p);
+    MXN_HIP(hipGetLastError());
+    l->sci_cap_items = cap_items;
+    l->sci_S = S;
+    l->sci_per_item = per_item;
+    l->sci_valid = true;
     return NB_OK;
 }
 
@@ -844,6 +1049,8 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     in->resv_parts = outer->resv_parts;
     in->resv_nci = outer->resv_nci;
     in->last_entries = outer->last_entries;
+    in->resv_size = outer->resv_size;
+    in->sci_valid = false;
     MXN_HIP(hipMemcpyAsync(in->part_start.p, outer->part_start.p, (size_t)(nregions + 1) * 4, hipMemcpyDeviceToDevice,
                            st));
     PruneArgs a{};

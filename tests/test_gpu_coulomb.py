@@ -34,11 +34,12 @@ def _run(s, rc, beta, flags, coulomb, eps_rf=0.0, xq=None):
     return f.cpu().numpy().astype(np.float64), e.cpu().numpy(), v.cpu().numpy().reshape(3, 3)
 
 
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 @pytest.mark.parametrize("shape", [(4, 4), (8, 4), (8, 8)])
 @pytest.mark.parametrize("eps_rf", [78.0, 0.0])
-def test_reaction_field(c1, shape, eps_rf):
+def test_reaction_field(c1, shape, eps_rf, variant):
     rc = 0.9
-    s = GpuSystem(c1, shape, rc)
+    s = GpuSystem(c1, shape, rc, variant=variant)
     try:
         mxn = s.mxn
         fl = mxn.NB_ENERGY | mxn.NB_VIRIAL
@@ -56,10 +57,11 @@ def test_reaction_field(c1, shape, eps_rf):
         s.close()
 
 
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 @pytest.mark.parametrize("shape", [(4, 4), (8, 4), (8, 8)])
 @pytest.mark.parametrize("rc,beta", [(0.9, 3.47), (1.0, 3.12)])
-def test_ewald_table(c1, shape, rc, beta):
-    s = GpuSystem(c1, shape, rc)
+def test_ewald_table(c1, shape, rc, beta, variant):
+    s = GpuSystem(c1, shape, rc, variant=variant)
     try:
         mxn = s.mxn
         fl = mxn.NB_ENERGY | mxn.NB_VIRIAL

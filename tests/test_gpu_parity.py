@@ -187,7 +187,7 @@ def _oracle_forces(box, rc, beta, xyz=None, mode="brute"):
                          synth.lj_table_spce(), rc, beta, F, shift=True, mode=mode)
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_forces_energies_virial(c1, shape, variant):
     rc, rlist, beta = 0.9, 0.9, 3.47
@@ -208,7 +208,7 @@ def test_forces_energies_virial(c1, shape, variant):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_forces_buffered_after_motion(c1, shape, variant):
     """List built at rlist = rc + 0.1 from step-0 positions, forces at step 9 of ballistic motion (300 K, 2 fs)."""
@@ -240,7 +240,7 @@ def test_accumulate_flag(c1):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
 @pytest.mark.parametrize("shape", [(4, 8), (8, 4), (8, 8)])
 def test_forces_reproducible_across_rebuilds(c1, shape, variant):
     """The j-forces of a j-cluster are summed in fixed point, so the forces do not depend on the order in
@@ -268,7 +268,7 @@ def test_forces_reproducible_across_rebuilds(c1, shape, variant):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["direct", "compact"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
 def test_tiny_and_ragged(ragged, variant):
     """One water in a box; and a ragged 291-atom box, all shapes."""
     one = synth.water_box(1, 2.5, seed=1)
