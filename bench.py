@@ -14,7 +14,7 @@ whole steps (listed cluster pairs x M x N per force call, the paper's
 pairs-per-cycle convention); effective (r < rc) pairs/s are reported beside.
 
 Roofline of the force kernel (bound: FP32 VALU ALU work, no MFMA):
-algorithmic flops = 69 per interacting pair (full LJ + Ewald evaluation; FP32
+algorithmic flops = 65 per interacting pair (full LJ + Ewald evaluation; FP32
 VALU count of the built 8x8 force+energy kernel, FMA = 2) + 8 per listed pair
 beyond rc (distance and cut-off test), divided by the force kernel's average
 duration from HIP events on the library stream; peak = 157.3 TFLOP/s
@@ -33,14 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FLOPS_PER_PAIR = 69          # FP32 flops of one in-range pair evaluation (8x8 force+energy kernel)
+FLOPS_PER_PAIR = 65          # FP32 flops of one in-range pair evaluation (8x8 force+energy kernel)
 FLOPS_PER_DISTANCE = 8       # FP32 flops of the distance and cut-off test of a listed pair
 PEAK_FP32 = 157.3e12
 # HBM traffic of one force-kernel launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device-to-device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid only for the kernel sources the counters were taken on.
-FORCE_TRAFFIC = {"sources_sha1": "9bf0e87865cfcbfd004297efcfa2813303d1690c", "fetch_kib": 16341.6,
-                 "write_kib": 108337.0, "fetch_scale": 2.0, "write_scale": 1.0}
+FORCE_TRAFFIC = {"sources_sha1": "b9a4846b6dfe493425202b78f0a2c311dd403d8d", "fetch_kib": 16335.7,
+                 "write_kib": 108277.7, "fetch_scale": 2.0, "write_scale": 1.0}
 FORCE_SOURCES = ("paper_1306_1737_amd/csrc/forces.hip", "paper_1306_1737_amd/csrc/devptr.h",
                  "paper_1306_1737_amd/csrc/ewald_fit.h")
 METRIC = "atom-pair interactions/s (FP32, ≤1e-5 rel force err) + % FP32 VALU peak"

@@ -126,10 +126,13 @@ __device__ inline float wave_sum_dpp(float v) {
     return __int_as_float(x);
 }
 
-// Per-type-pair table in LDS: [ti*nt + tj] = (C6, C12, LJ shift at rc,
-// Coulomb shift at rc), and one all-zero row at nt*nt that pairs with a
+// Per-type-pair table in LDS: [ti*nt + tj] = (6 C6, 12 C12, 12 x LJ shift at
+// rc, Coulomb shift at rc), and one all-zero row at nt*nt that pairs with a
 // clear mask bit (excluded or dummy) read instead, so the pair math needs no
-// per-term selects for them.
+// per-term selects for them.  The LJ energy is accumulated as 12 V_LJ and
+// scaled once per work item (kLJScale).
+constexpr double kLJScale = 1.0 / 12.0;
+
 __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
     for (int t = threadIdx.x; t <= a.nt * a.nt; t += blockDim.x) {
         if (t == a.nt * a.nt) {
@@ -138,26 +141,28 @@ __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
         }
         const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
         const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
-        ljt[t] = make_float4(c6, c12, sh, a.shiftC);
+        ljt[t] = make_float4(6.0f * c6, 12.0f * c12, 12.0f * sh, a.shiftC);
     }
 }
 
 // Force factor F/r of one pair within the cut-off, and its energy terms
-// added to el (Lennard-Jones) and ec (Coulomb).  Coulomb variants (ELEC):
-// 0 Ewald with erfc from a rational approximation; 1 reaction field,
+// added to el (12 x Lennard-Jones) and ec (Coulomb).  Coulomb variants
+// (ELEC): 0 Ewald with erfc from a rational approximation; 1 reaction field,
 // F/r = qq (e/r^3 - 2k), V = qq (e/r + k r^2 - c); 2 Ewald with
 // F/r = qq (e/r^3 - G(r)) and V = qq (e/r - H(r) - e shift), where
 // G = (erf(beta r)/r - 2 beta/sqrt(pi) exp(-beta^2 r^2)) / r^2 and
 // H = erf(beta r)/r are smooth (finite at r = 0) and interpolated linearly
 // from the LDS table; e = bit = 1 for an interacting pair, 0 for an
 // excluded one (which keeps its Ewald correction and reads the all-zero
-// LJ row).  ljrow: the type pair's row of the LDS table.
+// LJ row).  ljrow: the type pair's row of the LDS table.  Both terms are
+// gathered as F/r = (qq T + B / r^6) / r^2 with T = r F_Coulomb / qq (1/r
+// for plain Coulomb) and B = 12 C12 / r^6 - 6 C6; 12 V_LJ = (B - 6 C6) / r^6.
 template <bool ENER, int ELEC>
 __device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const float2 *tab, float r2, float qq,
                                   bool bit, int ljrow, float &el, float &ec) {
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
-    float fsc, vc;
+    float T, vc;
     if (ELEC == 0) {
         const float u = r2 * rinv * a.beta;
         const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
@@ -168,11 +173,11 @@ __device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const f
         const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
         const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
         vc = em * rinv;
-        fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
+        T = fmaf(a.c2bpi, ex, vc);
     } else if (ELEC == 1) {
         const float einv = bit ? rinv : 0.0f;
         vc = einv + fmaf(a.krf, r2, -a.crf);
-        fsc = qq * fmaf(einv, rinv2, -a.k2rf);
+        T = fmaf(-a.k2rf, r2, einv);
     } else {
         const float t = r2 * rinv * a.tab_scale;
         const int i0 = (int)t;
@@ -180,15 +185,14 @@ __device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const f
         const float2 g0 = tab[i0], g1 = tab[i0 + 1];
         const float einv = bit ? rinv : 0.0f;
         vc = einv - fmaf(eps, g1.y - g0.y, g0.y);
-        fsc = qq * fmaf(einv, rinv2, -fmaf(eps, g1.x - g0.x, g0.x));
+        T = fmaf(-fmaf(eps, g1.x - g0.x, g0.x), r2, einv);
     }
     const float4 lj = ljt[bit ? ljrow : a.nt * a.nt];   // the zero row for a clear bit
-    const float c6 = lj.x, c12 = lj.y;
     const float rinv6 = rinv2 * rinv2 * rinv2;
-    const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
-    fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+    const float B = fmaf(lj.y, rinv6, -lj.x);
+    const float fsc = rinv2 * fmaf(qq, T, B * rinv6);
     if (ENER) {
-        el += t12 - t6 - lj.z;
+        el = fmaf(rinv6, B - lj.x, el) - lj.z;
         ec += qq * (ELEC == 1 ? vc : vc - lj.w);   // the reaction field's c is in vc
     }
     return fsc;
@@ -337,7 +341,7 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
     }
     if (ENER || VIR) {
         acc_t out[kNAcc];
-        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[0] = ENER ? wave_sum(elj) * (acc_t)kLJScale : (acc_t)0;
         out[1] = ENER ? wave_sum(ec) : (acc_t)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
     }
     if (ENER || VIR) {
         acc_t out[kNAcc];
-        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[0] = ENER ? wave_sum(elj) * (acc_t)kLJScale : (acc_t)0;
         out[1] = ENER ? wave_sum(ec) : (acc_t)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k] + viri[k]) : (acc_t)0;
@@ -564,11 +568,14 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
 // One wavefront per j-cluster, lane = (group g, j-particle b): the 64/N
 // groups take every (64/N)-th row and item (four rows in flight per lane;
 // each step reads 64/N consecutive rows), and a butterfly sums the groups.
-// The sums are taken in 64-bit fixed point (2^-26 units: a range beyond
-// 1e11 and a resolution far below FP32 rounding of the forces), so they do
-// not depend on the order of the rows; a non-finite term (or one beyond the
-// fixed-point range) makes the force NaN.  After an overflowed build (no
-// usable items) every force is zero.
+// The sums are taken in fixed point: each term rounded to a multiple of
+// 2^-22 (below FP32 rounding of forces of 4 and more) and held as an
+// integer-valued double, so every addition is exact while a term stays
+// below 2^20 in magnitude and at most 2^11 terms meet in one force (rows
+// of a j-cluster plus items of an i-cluster: a few hundred at most), and
+// the sums do not depend on the order of the rows.  A non-finite term, or
+// one beyond the fixed-point range, makes the force NaN.  After an
+// overflowed build (no usable items) every force is zero.
 struct FoldView {
     gptr<const int> nslots, perm, totals, jstart, part_istart;
     gptr<const float> fj;
@@ -578,16 +585,16 @@ struct FoldView {
     int sci;   // i-clusters per item group: the i-forces of cluster c are slot c % sci of group c / sci's items
 };
 
-constexpr float kFixScale = 67108864.0f;           // 2^26
-constexpr double kFixInv = 1.0 / 67108864.0;
+constexpr double kFixScale = 4194304.0;        // 2^22
+constexpr double kFixInv = 1.0 / 4194304.0;
+constexpr double kFixMax = 4398046511104.0;    // 2^42 units: terms up to 2^20
 
-// x in 2^-26 units (rounded); 0 with bad set for NaN, infinities and values
-// beyond the int64 range
-__device__ inline long long to_fix(float x, bool &bad) {
-    const float y = x * kFixScale;
-    const bool ok = fabsf(y) < 9.0e18f;
-    bad |= !ok;
-    return ok ? (long long)rintf(y) : 0ll;
+// x in 2^-22 units, rounded (exact: FP32 to FP64, times a power of two, to
+// the nearest integer); bad set for NaN, infinities and values beyond the range
+__device__ inline double to_fix(float x, bool &bad) {
+    const double y = rint((double)x * kFixScale);
+    bad |= !(fabs(y) < kFixMax);
+    return y;
 }
 
 template <int M, int N>
@@ -596,7 +603,7 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
     cj = __builtin_amdgcn_readfirstlane(cj);   // wave-uniform: scalar loads of the row bounds
     if (cj >= *v.nslots / N) return;
     const int b = lane % N, g = lane / N, s = cj * N + b;
-    long long sx = 0, sy = 0, sz = 0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
     bool bad = false;
     if (v.totals[2] > 0) {
         const int k1 = v.jstart[cj + 1];
@@ -615,10 +622,10 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
             for (int u = 0; u < 4; ++u) {   // branch-free: the loads above stay in flight together
                 const bool ok = k0 + u * G < k1;
                 bool b3 = false;
-                const long long qx = to_fix(f[u][0], b3), qy = to_fix(f[u][1], b3), qz = to_fix(f[u][2], b3);
-                sx += ok ? qx : 0ll;
-                sy += ok ? qy : 0ll;
-                sz += ok ? qz : 0ll;
+                const double qx = to_fix(f[u][0], b3), qy = to_fix(f[u][1], b3), qz = to_fix(f[u][2], b3);
+                sx += ok ? qx : 0.0;
+                sy += ok ? qy : 0.0;
+                sz += ok ? qz : 0.0;
                 bad |= ok && b3;
             }
         }
@@ -645,8 +652,7 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
             bool nonfinite = false;
 #pragma unroll
             for (int q = 0; q < G; ++q) nonfinite |= (badm >> (q * N + b)) & 1ull;
-            float fx = (float)((double)sx * kFixInv), fy = (float)((double)sy * kFixInv),
-                  fz = (float)((double)sz * kFixInv);
+            float fx = (float)(sx * kFixInv), fy = (float)(sy * kFixInv), fz = (float)(sz * kFixInv);
             if (nonfinite) fx = fy = fz = __builtin_nanf("");
             float *out = v.f_out + 3 * (long)at;
             if (v.accumulate) {
@@ -882,33 +888,13 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
             const float dx = pik.x - pj.x, dy = pik.y - pj.y, dz = pik.z - pj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const bool bit = (info >> (8 + k)) & 1;
-            const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float rinv2 = rinv * rinv;
-            const float u = r2 * rinv * a.beta;
-            const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
-            const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
-            const float Q = fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u,
-                                 1.0f);
-            const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
-            const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
-            const float vc = em * rinv;
-            const float qq = qik * pj.w;
-            float fsc = qq * rinv2 * fmaf(a.c2bpi, ex, vc);
-            const float4 lj = ljt[tik + (info & 255)];
-            const float c6 = bit ? lj.x : 0.0f, c12 = bit ? lj.y : 0.0f;
-            const float rinv6 = rinv2 * rinv2 * rinv2;
-            const float t6 = c6 * rinv6, t12 = c12 * rinv6 * rinv6;
-            fsc = fmaf(12.0f * t12 - 6.0f * t6, rinv2, fsc);
+            const float fsc = pair_term<ENER, 0>(a, ljt, nullptr, r2, qik * pj.w, bit, tik + (info & 255), el, ecl);
             fx = fmaf(fsc, dx, fx);
             fy = fmaf(fsc, dy, fy);
             fz = fmaf(fsc, dz, fz);
             atomicAdd(fjx + pidx, -fsc * dx);
             atomicAdd(fjy + pidx, -fsc * dy);
             atomicAdd(fjz + pidx, -fsc * dz);
-            if (ENER) {
-                el += t12 - t6 - (bit ? lj.z : 0.0f);
-                ecl += qq * (vc - (bit ? a.shiftC : 0.0f));
-            }
         };
         int P = 0;
         for (int base = 0; base < nslot; base += 64) {
@@ -971,7 +957,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
     }
     if (ENER || VIR) {
         acc_t out[kNAcc];
-        out[0] = ENER ? wave_sum(elj) : (acc_t)0;
+        out[0] = ENER ? wave_sum(elj) * (acc_t)kLJScale : (acc_t)0;
         out[1] = ENER ? wave_sum(ec) : (acc_t)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
