@@ -474,11 +474,15 @@ int nb_list_stats(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const f
 
 /* Kernel timing with HIP events recorded on the context's stream around the
  * force kernel, the whole nb_forces call, nb_grid_sort and nb_pairlist_build.
- * Off by default.  nb_timing_read synchronises, returns the summed elapsed
- * milliseconds and the number of timed launches per timer since the last read
- * (HOST arrays of NB_TIMER_COUNT), and resets. */
+ * Off by default.  on: 0 off, 1 every timer, or NB_TIMING_SELECT with the
+ * bits 1 << NB_TIMER_* of the timers wanted (each recorded event costs a few
+ * microseconds of stream time, so a caller timing a long sequence can time
+ * a sample of its launches).  nb_timing_read synchronises, returns the
+ * summed elapsed milliseconds and the number of timed launches per timer
+ * since the last read (HOST arrays of NB_TIMER_COUNT), and resets. */
 enum { NB_TIMER_FORCE_KERNEL = 0, NB_TIMER_FORCE_CALL = 1, NB_TIMER_GRID_SORT = 2, NB_TIMER_PAIRLIST = 3,
        NB_TIMER_COUNT = 4 };
+enum { NB_TIMING_SELECT = 0x100 };
 int nb_timing_enable(nb_ctx *ctx, int on);
 int nb_timing_read(nb_ctx *ctx, double *ms, long *launches);
 

@@ -41,6 +41,7 @@ NB_FORCE_DIRECT, NB_FORCE_COMPACT, NB_FORCE_SUPER = 0, 1, 2
 NB_COULOMB_EWALD, NB_COULOMB_RF, NB_COULOMB_EWALD_TABLE = 0, 1, 2
 NB_RDF_SKIP_EXCLUDED = 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
+NB_TIMING_SELECT = 0x100
 
 
 class NbError(RuntimeError):
@@ -327,8 +328,15 @@ def nb_buffer_estimate(ctx, *, T, dt, nstlist, mass, charge, c6c12, count, volum
 
 # ------------------------------------------------------- instrumentation
 
-def nb_timing_enable(ctx, on=True):
-    _check(lib().nb_timing_enable(ctx, int(bool(on))))
+def nb_timing_enable(ctx, on=True, timers=None):
+    """Every timer (on=True), none (on=False), or only the NB_TIMER_* indices in `timers`."""
+    if not on:
+        val = 0
+    elif timers is None:
+        val = 1
+    else:
+        val = NB_TIMING_SELECT | sum(1 << int(t) for t in timers)
+    _check(lib().nb_timing_enable(ctx, val))
 
 
 def nb_timing_read(ctx):

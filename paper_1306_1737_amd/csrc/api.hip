@@ -53,7 +53,7 @@ static hipEvent_t take_event(nb_ctx *c) {
 }
 
 ScopedTimer::ScopedTimer(nb_ctx *c, int w) : ctx(c), which(w) {
-    if (!ctx->timing) return;
+    if (!((ctx->timing >> which) & 1)) return;
     hipEvent_t start = take_event(ctx);
     stop = take_event(ctx);
     if (!start || !stop) {
@@ -579,7 +579,10 @@ int nb_list_stats(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xy
 
 int nb_timing_enable(nb_ctx *c, int on) {
     if (!c) return fail(NB_ERR_ARG, "nb_timing_enable: ctx is null");
-    c->timing = on != 0;
+    constexpr int all = (1 << NB_TIMER_COUNT) - 1;
+    if (on == 0 || on == 1) c->timing = on ? all : 0;
+    else if ((on & NB_TIMING_SELECT) && !(on & ~(NB_TIMING_SELECT | all))) c->timing = on & all;
+    else return fail(NB_ERR_ARG, "nb_timing_enable: on must be 0, 1 or NB_TIMING_SELECT | timer bits");
     return NB_OK;
 }
 
@@ -741,9 +744,9 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
     if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     MXN_HIP(hipStreamSynchronize(c->stream));
     hipStream_t saved = c->stream;
-    const bool timing = c->timing;
+    const int timing = c->timing;
     c->stream = b->capture_stream;
-    c->timing = false;
+    c->timing = 0;
     hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? launch_batch(c, b, p, flags, energy, virial) : NB_ERR_HIP;
     b->cycle = false;
@@ -905,9 +908,9 @@ int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *
     if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     MXN_HIP(hipStreamSynchronize(c->stream));
     hipStream_t saved = c->stream;
-    const bool timing = c->timing;
+    const int timing = c->timing;
     c->stream = b->capture_stream;
-    c->timing = false;
+    c->timing = 0;
     hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? launch_rebuild(c, b) : NB_ERR_HIP;
     b->cycle = true;

@@ -68,7 +68,7 @@ struct nb_ctx {
     float rdf_rmax = -1.0f;
     int rdf_nbins = 0;
     float etab_beta = -1.0f, etab_rc = -1.0f;
-    bool timing = false;
+    int timing = 0;   // bit k: timer k records events
     int force_variant = NB_FORCE_DIRECT;
     int sci_clusters = 0;   // i-clusters per super-cluster (0: the largest that fits)
     int sci_per_item = 0;   // super-cluster entries per work item (0: default)

@@ -369,3 +369,28 @@ def test_buffer_estimate_matches_oracle():
         assert rb == pytest.approx(ref, abs=1e-9)
         assert d == pytest.approx(drift.drift_rate(rb, nstlist=nst, **kw), rel=1e-9)
         assert not fb
+
+
+def test_timing_selects_timers(c1):
+    """HIP-event timers: all, none, or a selection (the benchmark times one force kernel per step)."""
+    s = GpuSystem(c1, (8, 8), 0.9)
+    try:
+        mxn = s.mxn
+        mxn.nb_timing_read(s.ctx)
+        mxn.nb_timing_enable(s.ctx, True, timers=[mxn.NB_TIMER_FORCE_KERNEL])
+        s.forces(0.9, 3.47, 0)
+        s.forces(0.9, 3.47, 0)
+        t = mxn.nb_timing_read(s.ctx)
+        assert t["force_kernel"][1] == 2 and t["force_kernel"][0] > 0
+        assert t["force_call"][1] == 0 and t["grid_sort"][1] == 0
+        mxn.nb_timing_enable(s.ctx, True)
+        s.forces(0.9, 3.47, 0)
+        t = mxn.nb_timing_read(s.ctx)
+        assert t["force_kernel"][1] == 1 and t["force_call"][1] == 1
+        mxn.nb_timing_enable(s.ctx, False)
+        s.forces(0.9, 3.47, 0)
+        assert mxn.nb_timing_read(s.ctx)["force_kernel"][1] == 0
+        assert mxn.lib().nb_timing_enable(s.ctx, 5) != 0                           # neither 0, 1 nor a selection
+        assert mxn.lib().nb_timing_enable(s.ctx, mxn.NB_TIMING_SELECT | 64) != 0   # no such timer
+    finally:
+        s.close()
