@@ -252,18 +252,30 @@ __device__ inline void search_body(const A &a, int blk) {
                     }
                     bool acc = ok;
                     if (ok && !(d2 < a.rb2)) {
-                        // particle-pair check of this lane's candidate
+                        // particle-pair check of this lane's candidate, four j-particles per step
+                        // with their loads in flight together (early exit between steps)
                         bool hit = false;
-                        for (int b = 0; b < N && !hit; ++b) {
-                            const int sb = cj * N + b;
-                            const float4 pj = ld(a.xs + sb);
-                            if (a.perm[sb] < 0) continue;
-                            const float g = sq3(axis_gap(pj.x, pj.x, slx, shx), axis_gap(pj.y, pj.y, sly, shy),
-                                                axis_gap(pj.z, pj.z, slz, shz));
-                            if (!(g < rp2)) continue;   // too far from the whole i-cluster
+                        for (int b0 = 0; b0 < N && !hit; b0 += 4) {
+                            float4 pj[4];
+                            int pm[4];
 #pragma unroll
-                            for (int ia = 0; ia < M; ++ia)
-                                hit |= ((ireal >> ia) & 1u) && sq3(px[ia] - pj.x, py[ia] - pj.y, pz[ia] - pj.z) < a.rl2;
+                            for (int u = 0; u < 4; ++u) {
+                                const int sb = cj * N + b0 + u;
+                                pj[u] = ld(a.xs + sb);
+                                pm[u] = a.perm[sb];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (pm[u] < 0) continue;
+                                const float g = sq3(axis_gap(pj[u].x, pj[u].x, slx, shx),
+                                                    axis_gap(pj[u].y, pj[u].y, sly, shy),
+                                                    axis_gap(pj[u].z, pj[u].z, slz, shz));
+                                if (!(g < rp2)) continue;   // too far from the whole i-cluster
+#pragma unroll
+                                for (int ia = 0; ia < M; ++ia)
+                                    hit |= ((ireal >> ia) & 1u) &&
+                                           sq3(px[ia] - pj[u].x, py[ia] - pj[u].y, pz[ia] - pj[u].z) < a.rl2;
+                            }
                         }
                         acc = hit;
                     }
