@@ -145,6 +145,7 @@ __device__ inline void search_body(const A &a, int blk) {
     // exclusion partners of the i-particles: (slot * 8 + i-index, position), staged in LDS
     int nexcl = 0;
     bool staged = true;
+    int xlo = 0x7fffffff, xhi = -1;   // slot range of the staged partners
     if (FILL) {
         int e0 = 0, e1 = 0;
         if (lane < M && ((ireal >> lane) & 1u)) {
@@ -166,7 +167,14 @@ __device__ inline void search_body(const A &a, int blk) {
                 const int ps = a.slot_of[a.excl_idx[e]];
                 xinfo[w][q] = ps * 8 + lane;
                 xpos[w][q] = ld(a.xs + ps);
+                xlo = min(xlo, ps);
+                xhi = max(xhi, ps);
             }
+        }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            xlo = min(xlo, __shfl_xor(xlo, o, 64));
+            xhi = max(xhi, __shfl_xor(xhi, o, 64));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -296,7 +304,9 @@ __device__ inline void search_body(const A &a, int blk) {
                                 mask |= (unsigned long long)keep << (b * M);
                             }
                             if (staged) {
-                                for (int q = 0; q < nexcl; ++q) {
+                                // only a j-cluster holding a staged partner's slot can lose mask bits
+                                const bool near = cj * N + N - 1 >= xlo && cj * N <= xhi;
+                                for (int q = 0; near && q < nexcl; ++q) {
                                     const int v = xinfo[w][q], ia = v & 7, b = (v >> 3) - cj * N;
                                     if (b < 0 || b >= N) continue;
                                     const float4 pj = xpos[w][q];
