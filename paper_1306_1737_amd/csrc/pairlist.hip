@@ -128,15 +128,11 @@ __device__ inline void search_body(const A &a, int blk) {
         resv = a.part_start[gw + 1] - wpos;
     }
     const float4 lo = ld(a.bbi_lo + ci), hi = ld(a.bbi_hi + ci);
-    // the i-cluster (uniform across the wavefront)
-    float ix[M], iy[M], iz[M];
+    // the i-cluster (uniform across the wavefront; its positions are re-read per
+    // image shift, which keeps them out of the vector registers in between)
     unsigned ireal = 0;
 #pragma unroll
-    for (int ia = 0; ia < M; ++ia) {
-        const float4 p = ld(a.xs + ci * M + ia);
-        ix[ia] = p.x; iy[ia] = p.y; iz[ia] = p.z;
-        ireal |= (a.perm[ci * M + ia] >= 0 ? 1u : 0u) << ia;
-    }
+    for (int ia = 0; ia < M; ++ia) ireal |= (a.perm[ci * M + ia] >= 0 ? 1u : 0u) << ia;
     // keeps the z windows conservative against rounding: the FP32 squared distances
     // carry a relative error below 1e-6, so sqrt of that error is below 1e-3 rlist
     const float zmargin = 1e-3f + 2e-3f * a.rlist;
@@ -198,7 +194,8 @@ __device__ inline void search_body(const A &a, int blk) {
             float px[M], py[M], pz[M];   // shifted i-particles
 #pragma unroll
             for (int ia = 0; ia < M; ++ia) {
-                px[ia] = ix[ia] + sx; py[ia] = iy[ia] + sy; pz[ia] = iz[ia] + sz;
+                const float4 p = ld(a.xs + ci * M + ia);
+                px[ia] = p.x + sx; py[ia] = p.y + sy; pz[ia] = p.z + sz;
             }
             const int ncy = cy1 - cy0 + 1, ncols = (cx1 - cx0 + 1) * ncy;
             const int c_lo = ncols * part / P, c_hi = ncols * (part + 1) / P;   // this part's columns
