@@ -9,10 +9,10 @@
 // lane evaluates M pair interactions per pass with no cross-lane traffic:
 // j-forces stay in the lane and are added to memory once per entry with
 // one store per entry into the entry's row of a buffer whose rows are grouped
-// by j-cluster (the N lanes of an entry write one 16N-byte row); i-forces stay
+// by j-cluster (the N lanes of an entry write one 12N-byte row); i-forces stay
 // in registers for the whole item, are reduced across the wavefront once at
 // its end and stored per item.  A second kernel sums each cluster's stored j-
-// and i-forces in 64-bit fixed point (order-independent) and writes them in
+// and i-forces in fixed point (exact, so order-independent) and writes them in
 // input order, so no force goes through an atomic and the forces of a given
 // list and positions are reproducible bit for bit.  The image shift is
 // applied to the j-particle, so entries of different shifts can share a pass.
