@@ -275,6 +275,13 @@ enum {
  *            NB_ACCUMULATE)
  *   energy   DEVICE double[2] (E_LJ, E_Coulomb), written when NB_ENERGY
  *   virial   DEVICE double[9] row-major sum of r_ij (x) F_i, when NB_VIRIAL
+ *
+ * Forces are summed per particle in fixed point (multiples of 2^-20
+ * kJ mol^-1 nm^-1, exact while the sums stay below 8.6e9), so they do not
+ * depend on the order of the partial sums: for a given list and positions
+ * they are reproducible bit for bit.  A partial force of 2^32 kJ mol^-1 nm^-1
+ * or more (overlapping particles) or a non-finite one makes that particle's
+ * force NaN and latches NB_ERR_NONFINITE for nb_sync.
  */
 int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial);

@@ -143,6 +143,9 @@ int nb_sync(nb_ctx *c) {
     if (flags) MXN_HIP(hipMemset(c->d_flags, 0, sizeof(int)));
     if (flags & FLAG_NONFINITE) return fail(NB_ERR_NONFINITE, "non-finite or out-of-range coordinate or charge");
     if (flags & FLAG_OVERFLOW) return fail(NB_ERR_OVERFLOW, "pair-list capacity exceeded: rebuild the list");
+    if (flags & FLAG_FORCE_RANGE)
+        return fail(NB_ERR_NONFINITE, "a force term is non-finite or beyond the summation range (|F| >= 2^32 "
+                                      "kJ/mol/nm, overlapping particles): those forces are NaN");
     return NB_OK;
 }
 

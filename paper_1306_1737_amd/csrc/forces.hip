@@ -569,13 +569,15 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
 // groups take every (64/N)-th row and item (four rows in flight per lane;
 // each step reads 64/N consecutive rows), and a butterfly sums the groups.
 // The sums are taken in fixed point: each term rounded to a multiple of
-// 2^-22 (below FP32 rounding of forces of 4 and more) and held as an
-// integer-valued double, so every addition is exact while a term stays
-// below 2^20 in magnitude and at most 2^11 terms meet in one force (rows
-// of a j-cluster plus items of an i-cluster: a few hundred at most), and
-// the sums do not depend on the order of the rows.  A non-finite term, or
-// one beyond the fixed-point range, makes the force NaN.  After an
-// overflowed build (no usable items) every force is zero.
+// 2^-20 (the FP32 rounding step of a term of magnitude 16) and held as an
+// integer-valued double, so every addition is exact while the running sums
+// stay below 2^53 units (8.6e9 in force units; guaranteed for terms below
+// 2^22 with at most 2^11 of them per force, i.e. rows of a j-cluster plus
+// items of an i-cluster: a few hundred), and the sums do not depend on the
+// order of the rows.  A non-finite term, or one of 2^52 units (4.3e9) or
+// more (overlapping particles), makes the force NaN and latches
+// FLAG_FORCE_RANGE for nb_sync.  After an overflowed build (no usable
+// items) every force is zero.
 struct FoldView {
     gptr<const int> nslots, perm, totals, jstart, part_istart;
     gptr<const float> fj;
@@ -583,13 +585,14 @@ struct FoldView {
     float *f_out;
     int parts, accumulate;
     int sci;   // i-clusters per item group: the i-forces of cluster c are slot c % sci of group c / sci's items
+    int *flags;
 };
 
-constexpr double kFixScale = 4194304.0;        // 2^22
-constexpr double kFixInv = 1.0 / 4194304.0;
-constexpr double kFixMax = 4398046511104.0;    // 2^42 units: terms up to 2^20
+constexpr double kFixScale = 1048576.0;        // 2^20
+constexpr double kFixInv = 1.0 / 1048576.0;
+constexpr double kFixMax = 4503599627370496.0;   // 2^52 units: terms below 2^32
 
-// x in 2^-22 units, rounded (exact: FP32 to FP64, times a power of two, to
+// x in 2^-20 units, rounded (exact: FP32 to FP64, times a power of two, to
 // the nearest integer); bad set for NaN, infinities and values beyond the range
 __device__ inline double to_fix(float x, bool &bad) {
     const double y = rint((double)x * kFixScale);
@@ -653,7 +656,10 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
 #pragma unroll
             for (int q = 0; q < G; ++q) nonfinite |= (badm >> (q * N + b)) & 1ull;
             float fx = (float)(sx * kFixInv), fy = (float)(sy * kFixInv), fz = (float)(sz * kFixInv);
-            if (nonfinite) fx = fy = fz = __builtin_nanf("");
+            if (nonfinite) {
+                fx = fy = fz = __builtin_nanf("");
+                atomicOr(v.flags, mxn::FLAG_FORCE_RANGE);
+            }
             float *out = v.f_out + 3 * (long)at;
             if (v.accumulate) {
                 fx += out[0]; fy += out[1]; fz += out[2];
@@ -724,7 +730,8 @@ __global__ __launch_bounds__(256) void k_fold(ForceArgs a) {
     const FoldView v{(gptr<const int>)a.nslots, (gptr<const int>)a.perm,   (gptr<const int>)a.totals,
                      (gptr<const int>)a.jstart, (gptr<const int>)a.part_istart,
                      (gptr<const float>)a.fj,   (gptr<const float4>)a.fi,  a.f_out,
-                     a.parts,                   a.accumulate,              a.sci > 1 ? a.sci : 1};
+                     a.parts,                   a.accumulate,              a.sci > 1 ? a.sci : 1,
+                     a.flags};
     fold_body<M, N>(v, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
     if (ACC == 1) fold_energy<false>(a);
     if (ACC == 2) fold_energy<true>(a);
@@ -1154,7 +1161,8 @@ __global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
     const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,   (gptr<const int>)d.totals,
                      (gptr<const int>)d.jstart, (gptr<const int>)d.part_istart,
                      (gptr<const float>)d.fj,   (gptr<const float4>)d.fi,  d.f_out,
-                     d.parts,                   b.accumulate,              1};
+                     d.parts,                   b.accumulate,              1,
+                     b.flags};
     fold_body<M, N>(v, (int)((g0 - b.slot_off[r]) / N), threadIdx.x & 63);
 }
 

@@ -26,7 +26,7 @@ int fail(int status, const std::string &msg);
     } while (0)
 
 // bits latched by kernels in ctx->d_flags
-enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2 };
+enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_FORCE_RANGE = 4 };
 
 // work items of the force kernel hold at most this many j-entries of one i-cluster
 // Entries per force work item: four wavefront passes of 64/N entries each.

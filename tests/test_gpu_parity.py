@@ -4,6 +4,7 @@ Bars: grid sort, bounding boxes and the canonical cluster-pair list bit-exact;
 forces within 1e-5 relative RMS of FP64; energies and virial (FP64
 accumulation of FP32 pair terms) within 1e-5 relative.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -392,5 +393,32 @@ def test_timing_selects_timers(c1):
         assert mxn.nb_timing_read(s.ctx)["force_kernel"][1] == 0
         assert mxn.lib().nb_timing_enable(s.ctx, 5) != 0                           # neither 0, 1 nor a selection
         assert mxn.lib().nb_timing_enable(s.ctx, mxn.NB_TIMING_SELECT | 64) != 0   # no such timer
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
+def test_overlapping_particles_flagged(c1, variant):
+    """Two oxygens of different waters 0.03 nm apart: their LJ force (~2e15 kJ/mol/nm) is beyond the fixed-point
+    summation range, so exactly those two forces come back NaN and nb_sync reports NB_ERR_NONFINITE; the other
+    forces stay finite, and the report clears the flag."""
+    import paper_1306_1737_amd as mxn
+    xyz = c1.xyz.copy()
+    o1, o2 = 0, 3                                    # oxygens of waters 0 and 1
+    shift = xyz[o1] + np.array([0.03, 0.0, 0.0]) - xyz[o2]
+    xyz[o2:o2 + 3] += shift                          # move water 1 rigidly next to water 0's oxygen
+    box = dataclasses.replace(c1, xyz=xyz.astype(np.float32))
+    s = GpuSystem(box, (8, 8), 0.9, variant=variant)
+    try:
+        f = s.torch.zeros((box.n, 3), dtype=s.torch.float32, device=s.dev)
+        p = mxn.make_params(0.9, 3.47, F, s.lj)
+        mxn.nb_forces(s.ctx, s.grid, s.lst, s.xyzq, p, 0, f)
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_sync(s.ctx)
+        assert ei.value.status == mxn.NB_ERR_NONFINITE
+        fh = f.cpu().numpy()
+        bad = np.flatnonzero(~np.isfinite(fh).all(axis=1))
+        assert set(bad.tolist()) == {o1, o2}
+        mxn.nb_sync(s.ctx)                           # the flag was cleared by the report
     finally:
         s.close()
