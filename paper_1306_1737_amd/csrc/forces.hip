@@ -77,6 +77,7 @@ struct ForceArgs {
     const float *c6c12;
     int nt, shift_en;
     float rc2, beta, c_exp, c2bpi, coulomb_f, shiftC, rc6inv;
+    float ep[4], eq[5];   // erfc(beta r) exp(beta^2 r^2) = P(r) / Q(r): the fit's coefficients times beta^k
     // Coulomb variant: 0 Ewald (rational erfc), 1 reaction field, 2 Ewald from a table
     int elec;
     float krf, k2rf, crf;      // reaction field: k, 2k, c
@@ -126,23 +127,47 @@ __device__ inline float wave_sum_dpp(float v) {
     return __int_as_float(x);
 }
 
-// Per-type-pair table in LDS: [ti*nt + tj] = (6 C6, 12 C12, 12 x LJ shift at
-// rc, Coulomb shift at rc), and one all-zero row at nt*nt that pairs with a
-// clear mask bit (excluded or dummy) read instead, so the pair math needs no
-// per-term selects for them.  The LJ energy is accumulated as 12 V_LJ and
+// Per-type-pair table in LDS: row 1 + ti*nt + tj = (6 C6, 12 C12, 12 x LJ
+// shift at rc, Coulomb shift at rc), and the all-zero row 0 that a pair with a
+// clear mask bit (excluded) reads instead, so the pair math needs no per-term
+// selects for it.  The kernels address rows by byte offset (row x 16).  The LJ energy is accumulated as 12 V_LJ and
 // scaled once per work item (kLJScale).
 constexpr double kLJScale = 1.0 / 12.0;
 
 __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
     for (int t = threadIdx.x; t <= a.nt * a.nt; t += blockDim.x) {
-        if (t == a.nt * a.nt) {
-            ljt[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (t == 0) {
+            ljt[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             continue;
         }
-        const float c6 = a.c6c12[2 * t], c12 = a.c6c12[2 * t + 1];
+        const float c6 = a.c6c12[2 * (t - 1)], c12 = a.c6c12[2 * (t - 1) + 1];
         const float sh = a.shift_en ? c12 * a.rc6inv * a.rc6inv - c6 * a.rc6inv : 0.0f;
         ljt[t] = make_float4(6.0f * c6, 12.0f * c12, 12.0f * sh, a.shiftC);
     }
+}
+
+// Byte offset of the LJ row of i-type ti (clamped to the table) and j-row offset of j-type tj.
+__device__ inline int lj_ioff(const ForceArgs &a, int ti) {
+    return (1 + (ti < 0 ? 0 : (ti >= a.nt ? a.nt - 1 : ti)) * a.nt) * 16;
+}
+__device__ inline int lj_joff(const ForceArgs &a, int tj) {
+    return min(max(tj, 0), a.nt - 1) * 16;
+}
+
+// The rational erfc fit in powers of r (ForceArgs::ep, eq).  p2 and q3 are
+// held in vector registers for the whole work item: the Horner steps that
+// start from them would otherwise read two scalar operands, which one VALU
+// instruction cannot, and the compiler copies them again for every pair.
+struct EwPoly {
+    float p0, p1, p2, p3, q1, q2, q3, q4;
+};
+__device__ inline float in_vreg(float x) {
+    float y;
+    asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+__device__ inline EwPoly ew_poly(const ForceArgs &a) {
+    return {a.ep[0], a.ep[1], in_vreg(a.ep[2]), a.ep[3], a.eq[1], a.eq[2], in_vreg(a.eq[3]), a.eq[4]};
 }
 
 // Force factor F/r of one pair within the cut-off, and its energy terms
@@ -154,24 +179,23 @@ __device__ inline void fill_ljt(const ForceArgs &a, float4 *ljt) {
 // H = erf(beta r)/r are smooth (finite at r = 0) and interpolated linearly
 // from the LDS table; e = bit = 1 for an interacting pair, 0 for an
 // excluded one (which keeps its Ewald correction and reads the all-zero
-// LJ row).  ljrow: the type pair's row of the LDS table.  Both terms are
+// LJ row).  ljoff: byte offset of the type pair's row of the LDS table.  Both terms are
 // gathered as F/r = (qq T + B / r^6) / r^2 with T = r F_Coulomb / qq (1/r
 // for plain Coulomb) and B = 12 C12 / r^6 - 6 C6; 12 V_LJ = (B - 6 C6) / r^6.
 template <bool ENER, int ELEC>
-__device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const float2 *tab, float r2, float qq,
-                                  bool bit, int ljrow, float &el, float &ec) {
+__device__ inline float pair_term(const ForceArgs &a, const EwPoly &ew, const float4 *ljt, const float2 *tab, float r2,
+                                  float qq, bool bit, int ljoff, float &el, float &ec) {
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
     float T, vc;
     if (ELEC == 0) {
-        const float u = r2 * rinv * a.beta;
+        const float r = r2 * rinv;
         const float ex = __builtin_amdgcn_exp2f(a.c_exp * r2);
-        // erfc(u) = exp(-u^2) P(u) / Q(u)
-        const float P = fmaf(fmaf(fmaf(MXN_EWALD_P3, u, MXN_EWALD_P2), u, MXN_EWALD_P1), u, MXN_EWALD_P0);
-        const float Q =
-            fmaf(fmaf(fmaf(fmaf(MXN_EWALD_Q4, u, MXN_EWALD_Q3), u, MXN_EWALD_Q2), u, MXN_EWALD_Q1), u, 1.0f);
-        const float erfcv = ex * P * __builtin_amdgcn_rcpf(Q);
-        const float em = bit ? erfcv : erfcv - 1.0f;   // excluded pair: -erf(beta r)
+        // erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
+        const float P = fmaf(fmaf(fmaf(ew.p3, r, ew.p2), r, ew.p1), r, ew.p0);
+        const float Q = fmaf(fmaf(fmaf(fmaf(ew.q4, r, ew.q3), r, ew.q2), r, ew.q1), r, 1.0f);
+        // erfc for an interacting pair, erfc - 1 = -erf(beta r) for an excluded one
+        const float em = fmaf(ex * P, __builtin_amdgcn_rcpf(Q), bit ? 0.0f : -1.0f);
         vc = em * rinv;
         T = fmaf(a.c2bpi, ex, vc);
     } else if (ELEC == 1) {
@@ -187,7 +211,7 @@ __device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const f
         vc = einv - fmaf(eps, g1.y - g0.y, g0.y);
         T = fmaf(-fmaf(eps, g1.x - g0.x, g0.x), r2, einv);
     }
-    const float4 lj = ljt[bit ? ljrow : a.nt * a.nt];   // the zero row for a clear bit
+    const float4 lj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(ljt) + (bit ? ljoff : 0));
     const float rinv6 = rinv2 * rinv2 * rinv2;
     const float B = fmaf(lj.y, rinv6, -lj.x);
     const float fsc = rinv2 * fmaf(qq, T, B * rinv6);
@@ -199,24 +223,31 @@ __device__ inline float pair_term(const ForceArgs &a, const float4 *ljt, const f
 }
 
 // One pass of the direct kernel's inner loop: this lane's j-particle against
-// the M i-particles.  Measured slower on gfx950, and therefore not used:
-// a uniform mask-free copy of this loop for passes without exclusions (the
-// duplicated body costs more than the selects it saves); a branch-free body
-// whose eight i-particle chains the compiler can interleave (132 registers,
-// occupancy 3: 240 us against 198 us on the 96k-atom box).
+// the M i-particles.  Which lanes take part is decided in scalar registers:
+// ireal (uniform) skips dummy i-particles, live holds the lanes with a real
+// j-particle of a valid entry, and only in a pass with a self cluster pair
+// (anyself) does the triangle test slot(i) < slot(j), k < tri, cost a vector
+// compare.  The exclusion bits become a lane mask likewise, and only in a
+// pass that has an exclusion (anyexcl).  Measured slower on gfx950, and
+// therefore not used: a uniform mask-free copy of the pair block for passes
+// without exclusions; a branch-free body whose eight i-particle chains the
+// compiler can interleave (132 registers, occupancy 3).
 template <int M, bool ENER, int ELEC>
-__device__ inline void pair_pass(const ForceArgs &a, const float4 *ljt, const float2 *tab, const float (&xi)[M],
+__device__ inline void pair_pass(const ForceArgs &a, const EwPoly &ew, const float4 *ljt, const float2 *tab, const float (&xi)[M],
                                  const float (&yi)[M], const float (&zi)[M], const float (&qi)[M], const int (&ti)[M],
-                                 float xj, float yj, float zj, float qj, int tj, unsigned mb, unsigned act, float rc2l,
-                                 float (&fix)[M], float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz,
-                                 float &el, float &ec) {
+                                 float xj, float yj, float zj, float qj, int tj, unsigned mb, unsigned ireal,
+                                 unsigned long long live, bool anyself, int tri, bool anyexcl, float (&fix)[M],
+                                 float (&fiy)[M], float (&fiz)[M], float &fjx, float &fjy, float &fjz, float &el,
+                                 float &ec) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
+        const unsigned long long am = (((ireal >> k) & 1u) ? live : 0ull) & __builtin_amdgcn_ballot_w64(k < tri);
+        const unsigned long long bm = __builtin_amdgcn_ballot_w64((mb >> k) & 1u);
         const float dx = xi[k] - xj, dy = yi[k] - yj, dz = zi[k] - zj;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2l && ((act >> k) & 1u)) {
-            const bool bit = (mb >> k) & 1u;
-            const float fsc = pair_term<ENER, ELEC>(a, ljt, tab, r2, qi[k] * qj, bit, ti[k] + tj, el, ec);
+        if ((r2 < a.rc2) & __builtin_amdgcn_inverse_ballot_w64(am)) {
+            const bool bit = __builtin_amdgcn_inverse_ballot_w64(bm);
+            const float fsc = pair_term<ENER, ELEC>(a, ew, ljt, tab, r2, qi[k] * qj, bit, ti[k] + tj, el, ec);
             fix[k] = fmaf(fsc, dx, fix[k]);
             fiy[k] = fmaf(fsc, dy, fiy[k]);
             fiz[k] = fmaf(fsc, dz, fiz[k]);
@@ -272,8 +303,10 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         qi[k] = p.w * a.coulomb_f;
         const int t = v.type_s[ci * M + k];
         ireal |= (t >= 0 ? 1u : 0u) << k;
-        ti[k] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;   // types beyond ntypes are clamped
+        ti[k] = lj_ioff(a, t);   // types beyond ntypes are clamped
     }
+    ireal = __builtin_amdgcn_readfirstlane(ireal);
+    const EwPoly ew = ew_poly(a);
     float fix[M], fiy[M], fiz[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
@@ -291,22 +324,21 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         const int jslot = en.cj * N + jb;
         const float4 pj = ld(v.xs_now + jslot);
         const int tjr = v.type_s[jslot];
-        const int tj = min(max(tjr, 0), a.nt - 1);
+        const int tj = lj_joff(a, tjr);
         const float4 sv = svec[en.shift];
         const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
         const float qj = pj.w;
         const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
         const unsigned mb = (unsigned)(m64 >> (jb * M)) & FULL;
-        unsigned act = ireal;   // pairs of real particles only: dummies never interact
-        if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
-            const int t = jslot - ci * M;
-            act &= t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
-        }
-        if (!valid || tjr < 0) act = 0u;
+        const bool lv = valid && tjr >= 0;   // pairs of real particles only: dummies never interact
+        // self or overlapping cluster pair (zero shift): only slot(i) < slot(j), i.e. i-slot k < tri
+        const int tri = en.shift == 13 ? min(max(jslot - ci * M, 0), M) : M;
+        const unsigned long long live = __builtin_amdgcn_ballot_w64(lv);
+        const bool anyself = __builtin_amdgcn_ballot_w64(lv && tri < M) != 0;
+        const bool anyexcl = __builtin_amdgcn_ballot_w64(lv && ((mb | ~ireal) & FULL) != FULL) != 0;
         float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
-        const float rc2l = valid ? a.rc2 : -1.0f;
-        pair_pass<M, ENER, ELEC>(a, ljt, tab, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, act, rc2l, fix, fiy, fiz,
-                                 fjx, fjy, fjz, el, ecl);
+        pair_pass<M, ENER, ELEC>(a, ew, ljt, tab, xi, yi, zi, qi, ti, xj, yj, zj, qj, tj, mb, ireal, live, anyself, tri,
+                                 anyexcl, fix, fiy, fiz, fjx, fjy, fjz, el, ecl);
         if (ENER) {
             elj += (acc_t)el;
             ec += (acc_t)ecl;
@@ -356,7 +388,7 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
     extern __shared__ float4 smem[];
     float4 *svec = smem;        // 27 image shift vectors
-    float4 *ljt = smem + 32;    // [ti][tj] = (C6, C12, LJ shift at rc, 0)
+    float4 *ljt = smem + 32;    // LJ rows by type pair (fill_ljt)
     float2 *tab = reinterpret_cast<float2 *>(smem + 32 + a.nt * a.nt + 1);   // Ewald table (ELEC == 2)
     for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
     fill_ljt(a, ljt);
@@ -420,7 +452,7 @@ __device__ inline float stride8_sum(float v) {
 // that is the entry's j-cluster itself (zero shift; -1 if none), whose pass
 // takes the half-list triangle a < b only.
 template <int S, bool ENER, int ELEC>
-__device__ inline void sci_entry(const ForceArgs &a, const float4 *ljt, const float2 *tab, const uint2 *mrec, int gm,
+__device__ inline void sci_entry(const ForceArgs &a, const EwPoly &ew, const float4 *ljt, const float2 *tab, const uint2 *mrec, int gm,
                                  int selfg, const float4 *ip, const int *it, float xj, float yj, float zj, float qj,
                                  int tj, float (&fix)[S], float (&fiy)[S], float (&fiz)[S], float &fjx, float &fjy,
                                  float &fjz, float &el, float &ec) {
@@ -437,7 +469,7 @@ __device__ inline void sci_entry(const ForceArgs &a, const float4 *ljt, const fl
             const float r2 = dx * dx + dy * dy + dz * dz;
             if (__builtin_amdgcn_inverse_ballot_w64(g == selfg ? kUpper : ~0ull) && r2 < a.rc2) {
                 const bool bit = __builtin_amdgcn_inverse_ballot_w64(m64);
-                const float fsc = pair_term<ENER, ELEC>(a, ljt, tab, r2, pi.w * qj, bit, it[g * 8] + tj, el, ec);
+                const float fsc = pair_term<ENER, ELEC>(a, ew, ljt, tab, r2, pi.w * qj, bit, it[g * 8] + tj, el, ec);
                 fix[g] = fmaf(fsc, dx, fix[g]);
                 fiy[g] = fmaf(fsc, dy, fiy[g]);
                 fiz[g] = fmaf(fsc, dz, fiz[g]);
@@ -488,12 +520,13 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
         const float4 p = ld(xs + slot);
         const int t = in ? types[slot] : -1;
         ipw[lane] = make_float4(t >= 0 ? p.x : kFarX, p.y, p.z, p.w * a.coulomb_f);
-        itw[lane] = (t < 0 ? 0 : (t >= a.nt ? a.nt - 1 : t)) * a.nt;
+        itw[lane] = lj_ioff(a, t);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the wavefront's staging is visible to all its lanes
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const float4 *ip = ipw + ia;
+    const EwPoly ew = ew_poly(a);
     const int *itp = itw + ia;
     float fix[S], fiy[S], fiz[S];
 #pragma unroll
@@ -510,12 +543,12 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
         const int jslot = cj * 8 + jb;
         const float4 pj = ld(xs + jslot);
         const int tjr = types[jslot];
-        const int tj = min(max(tjr, 0), a.nt - 1);
+        const int tj = lj_joff(a, tjr);
         const float4 sv = svec[shift];
         const float xj = tjr >= 0 ? pj.x - sv.x : -kFarX, yj = pj.y - sv.y, zj = pj.z - sv.z;
         const float qj = pj.w;
         float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, el = 0.0f, ecl = 0.0f;
-        sci_entry<S, ENER, ELEC>(a, ljt, tab, mrec, gm, selfg, ip, itp, xj, yj, zj, qj, tj, fix, fiy, fiz, fjx, fjy,
+        sci_entry<S, ENER, ELEC>(a, ew, ljt, tab, mrec, gm, selfg, ip, itp, xj, yj, zj, qj, tj, fix, fiy, fiz, fjx, fjy,
                                  fjz, el, ecl);
         if (ENER) {
             elj += (acc_t)el;
@@ -826,6 +859,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
 
     using acc_t = typename std::conditional<ACC64, double, float>::type;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const EwPoly ew = ew_poly(a);
     char *wb = reinterpret_cast<char *>(smem + 32 + a.nt * a.nt + 1) + (size_t)wave * wave_lds_bytes<N>();
     float4 *jd = reinterpret_cast<float4 *>(wb);
     int *jinfo = reinterpret_cast<int *>(wb + JMAX * 16);
@@ -886,7 +920,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
         const float4 pik = a.xs_now[ci * M + k];
         const float qik = pik.w * a.coulomb_f;
         const int tt = a.type_s[ci * M + k];
-        const int tik = (tt < 0 ? 0 : (tt >= a.nt ? a.nt - 1 : tt)) * a.nt;
+        const int tik = lj_ioff(a, tt);
         float fx = 0.0f, fy = 0.0f, fz = 0.0f, el = 0.0f, ecl = 0.0f;
         auto pass = [&](int pidx) {
             if (pidx < 0) return;
@@ -895,7 +929,7 @@ __global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
             const float dx = pik.x - pj.x, dy = pik.y - pj.y, dz = pik.z - pj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const bool bit = (info >> (8 + k)) & 1;
-            const float fsc = pair_term<ENER, 0>(a, ljt, nullptr, r2, qik * pj.w, bit, tik + (info & 255), el, ecl);
+            const float fsc = pair_term<ENER, 0>(a, ew, ljt, nullptr, r2, qik * pj.w, bit, tik + ((info & 255) << 4), el, ecl);
             fx = fmaf(fsc, dx, fx);
             fy = fmaf(fsc, dy, fy);
             fz = fmaf(fsc, dz, fz);
@@ -1289,6 +1323,19 @@ static int ensure_ewald_table(nb_ctx *ctx, float beta, float rc, int *ntab) {
     return NB_OK;
 }
 
+
+// The rational erfc fit in powers of r instead of u = beta r (coefficient k times beta^k), so the kernels
+// evaluate it without forming u.
+void set_ewald_poly(ForceArgs &a, float beta) {
+    const double P[4] = {MXN_EWALD_P0, MXN_EWALD_P1, MXN_EWALD_P2, MXN_EWALD_P3};
+    const double Q[5] = {MXN_EWALD_Q0, MXN_EWALD_Q1, MXN_EWALD_Q2, MXN_EWALD_Q3, MXN_EWALD_Q4};
+    double bk = 1.0;
+    for (int k = 0; k < 5; ++k, bk *= (double)beta) {
+        if (k < 4) a.ep[k] = (float)(P[k] * bk);
+        a.eq[k] = (float)(Q[k] * bk);
+    }
+}
+
 int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
                   unsigned flags, float *f, double *energy, double *virial) {
     hipStream_t st = ctx->stream;
@@ -1334,6 +1381,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.beta = p->beta;
     a.c_exp = (float)(-(double)p->beta * (double)p->beta * 1.4426950408889634);
     a.c2bpi = (float)(2.0 * (double)p->beta / 1.7724538509055160);
+    set_ewald_poly(a, p->beta);
     a.coulomb_f = p->coulomb_f;
     a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
@@ -1412,6 +1460,7 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
     a.beta = p->beta;
     a.c_exp = (float)(-(double)p->beta * (double)p->beta * 1.4426950408889634);
     a.c2bpi = (float)(2.0 * (double)p->beta / 1.7724538509055160);
+    set_ewald_poly(a, p->beta);
     a.coulomb_f = p->coulomb_f;
     a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
