@@ -14,7 +14,7 @@ whole steps (listed cluster pairs x M x N per force call, the paper's
 pairs-per-cycle convention); effective (r < rc) pairs/s are reported beside.
 
 Roofline of the force kernel (bound: FP32 VALU ALU work, no MFMA):
-algorithmic flops = 65 per interacting pair (full LJ + Ewald evaluation; FP32
+algorithmic flops = 63 per interacting pair (full LJ + Ewald evaluation; FP32
 VALU count of the built 8x8 force+energy kernel, FMA = 2) + 8 per listed pair
 beyond rc (distance and cut-off test), divided by the force kernel's average
 duration from HIP events on the library stream; peak = 157.3 TFLOP/s
@@ -33,14 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FLOPS_PER_PAIR = 65          # FP32 flops of one in-range pair evaluation (8x8 force+energy kernel)
+FLOPS_PER_PAIR = 63          # FP32 flops of one in-range pair evaluation (8x8 force+energy kernel)
 FLOPS_PER_DISTANCE = 8       # FP32 flops of the distance and cut-off test of a listed pair
 PEAK_FP32 = 157.3e12
 # HBM traffic of one force-kernel launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device-to-device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid only for the kernel sources the counters were taken on.
-FORCE_TRAFFIC = {"sources_sha1": "d22784eda3b491678e6bb12ec3dfd9426ea392d6", "fetch_kib": 16388.7,
-                 "write_kib": 108154.0, "fetch_scale": 2.0, "write_scale": 1.0}
+FORCE_TRAFFIC = {"sources_sha1": "ab237a6a11f76b638964469261fa3f9d7e5ffb99", "fetch_kib": 16442.3,
+                 "write_kib": 108021.0, "fetch_scale": 2.0, "write_scale": 1.0}
 FORCE_SOURCES = ("paper_1306_1737_amd/csrc/forces.hip", "paper_1306_1737_amd/csrc/devptr.h",
                  "paper_1306_1737_amd/csrc/ewald_fit.h")
 METRIC = "atom-pair interactions/s (FP32, ≤1e-5 rel force err) + % FP32 VALU peak"
