@@ -276,10 +276,10 @@ enum {
  *   energy   DEVICE double[2] (E_LJ, E_Coulomb), written when NB_ENERGY
  *   virial   DEVICE double[9] row-major sum of r_ij (x) F_i, when NB_VIRIAL
  *
- * Forces are summed per particle in fixed point (multiples of 2^-20
- * kJ mol^-1 nm^-1, exact while the sums stay below 8.6e9), so they do not
+ * Forces are summed per particle in fixed point (multiples of 2^-16
+ * kJ mol^-1 nm^-1, exact while the sums stay below 1.4e11), so they do not
  * depend on the order of the partial sums: for a given list and positions
- * they are reproducible bit for bit.  A partial force of 2^32 kJ mol^-1 nm^-1
+ * they are reproducible bit for bit.  A partial force of 2^36 kJ mol^-1 nm^-1
  * or more (overlapping particles) or a non-finite one makes that particle's
  * force NaN and latches NB_ERR_NONFINITE for nb_sync.
  */

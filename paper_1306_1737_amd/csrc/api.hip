@@ -144,7 +144,7 @@ int nb_sync(nb_ctx *c) {
     if (flags & FLAG_NONFINITE) return fail(NB_ERR_NONFINITE, "non-finite or out-of-range coordinate or charge");
     if (flags & FLAG_OVERFLOW) return fail(NB_ERR_OVERFLOW, "pair-list capacity exceeded: rebuild the list");
     if (flags & FLAG_FORCE_RANGE)
-        return fail(NB_ERR_NONFINITE, "a force term is non-finite or beyond the summation range (|F| >= 2^32 "
+        return fail(NB_ERR_NONFINITE, "a force term is non-finite or beyond the summation range (|F| >= 2^36 "
                                       "kJ/mol/nm, overlapping particles): those forces are NaN");
     return NB_OK;
 }

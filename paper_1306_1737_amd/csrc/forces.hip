@@ -602,14 +602,15 @@ __global__ __launch_bounds__(256) void k_forces_sci(ForceArgs a, const int4 *__r
 // groups take every (64/N)-th row and item (four rows in flight per lane;
 // each step reads 64/N consecutive rows), and a butterfly sums the groups.
 // The sums are taken in fixed point: each term rounded to a multiple of
-// 2^-20 (the FP32 rounding step of a term of magnitude 16) and held as an
-// integer-valued double, so every addition is exact while the running sums
-// stay below 2^53 units (8.6e9 in force units; guaranteed for terms below
-// 2^22 with at most 2^11 of them per force, i.e. rows of a j-cluster plus
-// items of an i-cluster: a few hundred), and the sums do not depend on the
-// order of the rows.  A non-finite term, or one of 2^52 units (4.3e9) or
-// more (overlapping particles), makes the force NaN and latches
-// FLAG_FORCE_RANGE for nb_sync.  After an overflowed build (no usable
+// 2^-16 (the FP32 rounding step of a term of magnitude 128; a few hundred
+// such roundings per force stay near 1e-4 in force units, against forces of
+// order 1e3) and held as an integer-valued double, so every addition is
+// exact while the running sums stay below 2^53 units (1.4e11 in force units;
+// guaranteed for terms below 2^26 with at most 2^11 of them per force, i.e.
+// rows of a j-cluster plus items of an i-cluster: a few hundred), and the
+// sums do not depend on the order of the rows.  A non-finite term, or one of
+// 2^52 units (6.9e10) or more (overlapping particles), makes the force NaN
+// and latches FLAG_FORCE_RANGE for nb_sync.  After an overflowed build (no usable
 // items) every force is zero.
 struct FoldView {
     gptr<const int> nslots, perm, totals, jstart, part_istart;
@@ -621,11 +622,11 @@ struct FoldView {
     int *flags;
 };
 
-constexpr double kFixScale = 1048576.0;        // 2^20
-constexpr double kFixInv = 1.0 / 1048576.0;
-constexpr double kFixMax = 4503599627370496.0;   // 2^52 units: terms below 2^32
+constexpr double kFixScale = 65536.0;          // 2^16
+constexpr double kFixInv = 1.0 / 65536.0;
+constexpr double kFixMax = 4503599627370496.0;   // 2^52 units: terms below 2^36
 
-// x in 2^-20 units, rounded (exact: FP32 to FP64, times a power of two, to
+// x in 2^-16 units, rounded (exact: FP32 to FP64, times a power of two, to
 // the nearest integer); bad set for NaN, infinities and values beyond the range
 __device__ inline double to_fix(float x, bool &bad) {
     const double y = rint((double)x * kFixScale);

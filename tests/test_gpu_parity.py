@@ -422,3 +422,29 @@ def test_overlapping_particles_flagged(c1, variant):
         mxn.nb_sync(s.ctx)                           # the flag was cleared by the report
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
+def test_close_contact_within_range(c1, variant):
+    """Two oxygens of different waters 0.075 nm apart, as free flight produces within 80 fs on the production
+    box: their LJ force (1.3e10 kJ/mol/nm) is within the fixed-point summation range, so every force is finite,
+    nb_sync reports nothing, and the forces match the FP64 oracle (the pair's own and all the others)."""
+    xyz = c1.xyz.copy()
+    o1, o2 = 0, 3                                    # oxygens of waters 0 and 1
+    xyz[o2:o2 + 3] += xyz[o1] + np.array([0.075, 0.0, 0.0]) - xyz[o2]
+    box = dataclasses.replace(c1, xyz=xyz.astype(np.float32))
+    rc, beta = 0.9, 3.47
+    s = GpuSystem(box, (8, 8), rc, variant=variant)
+    try:
+        f, e, _ = s.forces(rc, beta, s.mxn.NB_ENERGY)
+        s.mxn.nb_sync(s.ctx)
+        assert np.isfinite(f).all()
+        fr, er, _ = _oracle_forces(box, rc, beta)
+        assert np.linalg.norm(f[o1] - fr[o1]) <= 1e-5 * np.linalg.norm(fr[o1])
+        assert np.linalg.norm(fr[o1]) > 2.0 ** 33
+        rest = np.ones(box.n, dtype=bool)
+        rest[[o1, o2]] = False
+        assert rel_rms(f[rest], fr[rest]) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+    finally:
+        s.close()
