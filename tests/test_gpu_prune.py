@@ -122,3 +122,46 @@ def test_prune_errors_and_overflow(c1):
         mxn.nb_list_free(inner)
     finally:
         s.close()
+
+
+def test_production_box_rolling_prune():
+    """The benchmark's rolling schedule on the 96k-atom production box: a box-only outer list at 1.3 nm,
+    pruned at 1.05 nm at free-flight steps 20 and 39 (80 fs, where atoms of different waters have passed
+    within 0.08 nm of each other).  Outer and inner lists bit-exact against the oracle on sampled
+    i-clusters, and at step 39 the forces on the pruned list match the FP64 oracle everywhere."""
+    box = synth.water_box(32000, 9.86, seed=1306)
+    r_out, r_in, rc, beta = 1.3, 1.05, 1.0, 3.12
+    s = GpuSystem(box, (8, 8), r_out, rbb=r_out)
+    try:
+        mxn, torch = s.mxn, s.torch
+        g = oracle.grid_sort(box.xyz, box.box, 8, 8)
+        nci = g["n_slots"] // 8
+        outer = mxn.nb_list_export_canonical(s.lst)
+        ranges = [(0, 40), (nci // 2, nci // 2 + 40), (nci - 40, nci)]
+        sub = []
+        for c0, c1_ in ranges:
+            ref = oracle.pairlist(g, box.box, np.float32(r_out), np.float32(r_out), box.excl_off, box.excl_idx,
+                                  c0, c1_)
+            sel = outer[(outer["ci"] >= c0) & (outer["ci"] < c1_)]
+            _cmp(sel, ref)
+            sub.append(ref)
+        traj = synth.free_flight(box.xyz, synth.velocities(box.mass, 300.0, seed=1306), 0.002, 40)
+        inner = None
+        for step in (20, 39):
+            x = traj[step].astype(np.float32)
+            xq = torch.from_numpy(box.xyzq(x)).to(s.dev)
+            inner = mxn.nb_pairlist_prune(s.ctx, s.lst, xq, r_in, inner)
+            got = mxn.nb_list_export_canonical(inner)
+            xs_now = oracle.gather(g, x, box.box)
+            for (c0, c1_), ref_out in zip(ranges, sub):
+                ref = oracle.prune(g, xs_now, box.box, ref_out, np.float32(r_in))
+                _cmp(got[(got["ci"] >= c0) & (got["ci"] < c1_)], ref)
+        f, e, _ = _forces(mxn, torch, s, inner, xq, rc, beta, mxn.NB_ENERGY)
+        assert np.isfinite(f).all()
+        fr, er, _ = oracle.forces(x, box.q, box.type, box.box, box.excl_off, box.excl_idx, synth.lj_table_spce(),
+                                  rc, beta, F, mode="binned")
+        assert rel_rms(f, fr) <= 1e-5
+        np.testing.assert_allclose(e, er, rtol=1e-5)
+        mxn.nb_list_free(inner)
+    finally:
+        s.close()
