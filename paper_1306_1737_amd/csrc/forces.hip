@@ -427,8 +427,9 @@ __device__ inline void force_item(const ForceArgs &a, const SysView &v, const fl
         out[1] = ENER ? wave_sum(ec) : (acc_t)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
-        if (lane == 63)   // the lane that holds the i-force terms
-            for (int k = 0; k < kNAcc; ++k) v.partials[(size_t)k * v.pstride + v.pbase + item] = (double)out[k];
+        if (lane == 63)   // the lane that holds the i-force terms (virial slots are read only with the virial)
+            for (int k = 0; k < (VIR ? kNAcc : 2); ++k)
+                v.partials[(size_t)k * v.pstride + v.pbase + item] = (double)out[k];
     }
 }
 
