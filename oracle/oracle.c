@@ -405,11 +405,78 @@ static float sq_sum3(float a, float b, float c) {
     return ab + cc;
 }
 
+/* Entries of one i-cluster in canonical order (shift, cj), appended to *buf. */
+typedef struct {
+    oracle_entry *e;
+    long n, cap;
+} entry_buf;
+
+static void buf_push(entry_buf *b, int ci, int s, int cj, uint64_t mask) {
+    if (b->n == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->e = (oracle_entry *)realloc(b->e, (size_t)b->cap * sizeof(oracle_entry));
+    }
+    oracle_entry *o = b->e + b->n++;
+    o->ci = ci;
+    o->shift = s;
+    o->cj = cj;
+    o->pad = 0;
+    o->mask = mask;
+}
+
+static void list_one_ci(int ci, int M, int N, int ncj, const float *xs, const int *perm, const float Lf[3],
+                        const float *blo, const float *bhi, float rl2, float rb2, const int *excl_off,
+                        const int *excl_idx, entry_buf *out) {
+    float ilo[3], ihi[3];
+    bb_of(xs, perm, ci * M, M, ilo, ihi);
+    for (int s = 13; s < 27; ++s) {
+        int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
+        float sv[3];
+        for (int a = 0; a < 3; ++a) sv[a] = (float)sh[a] * Lf[a];
+        float slo[3], shi[3];
+        for (int a = 0; a < 3; ++a) { volatile float l = ilo[a] + sv[a], h = ihi[a] + sv[a]; slo[a] = l; shi[a] = h; }
+        for (int cj = 0; cj < ncj; ++cj) {
+            if (s == 13 && !(cj * N + N - 1 > ci * M)) continue;
+            float d[3];
+            for (int a = 0; a < 3; ++a) {
+                volatile float d1 = blo[3 * cj + a] - shi[a], d2 = slo[a] - bhi[3 * cj + a];
+                float m = d1 > d2 ? d1 : d2;
+                d[a] = m > 0.0f ? m : 0.0f;
+            }
+            float bd2 = sq_sum3(d[0], d[1], d[2]);
+            if (!(bd2 < rl2)) continue;
+            int keep = bd2 < rb2;
+            uint64_t mask = 0;
+            for (int a = 0; a < M; ++a) {
+                int sa = ci * M + a, oa = perm[sa];
+                if (oa < 0) continue;
+                float xa[3];
+                for (int k = 0; k < 3; ++k) { volatile float t = xs[3 * sa + k] + sv[k]; xa[k] = t; }
+                for (int b = 0; b < N; ++b) {
+                    int sb = cj * N + b, ob = perm[sb];
+                    if (ob < 0) continue;
+                    volatile float dx = xa[0] - xs[3 * sb], dy = xa[1] - xs[3 * sb + 1], dz = xa[2] - xs[3 * sb + 2];
+                    float r2 = sq_sum3(dx, dy, dz);
+                    if (r2 < rl2) keep = 1;
+                    int bit = 1;
+                    if (s == 13 && sa >= sb) bit = 0;
+                    if (bit && r2 < rl2 && is_excluded(excl_off, excl_idx, oa, ob)) bit = 0;
+                    if (bit) mask |= (uint64_t)1 << (a * N + b);
+                }
+            }
+            if (keep) buf_push(out, ci, s, cj, mask);
+        }
+    }
+}
+
 /*
  * xs: sorted FP32 positions per slot (3 per slot; dummy slots ignored);
  * perm: slot -> original atom or -1.  Brute force over all triples for
  * ci in [ci_begin, ci_end).  Writes up to cap entries in canonical order
  * (ci, shift, cj) and returns the total count (which may exceed cap).
+ * The i-clusters are split into fixed blocks listed in parallel (OpenMP)
+ * and concatenated in block order, so the output does not depend on the
+ * thread count.
  */
 long oracle_pairlist(int n_slots, int M, int N, const float *xs, const int *perm, const double box[3],
                      float rlist, float rbb, const int *excl_off, const int *excl_idx, int ci_begin,
@@ -421,57 +488,24 @@ long oracle_pairlist(int n_slots, int M, int N, const float *xs, const int *perm
     volatile float rl2v = rlist * rlist, rb2v = rbb * rbb;
     float rl2 = rl2v, rb2 = rb2v;
     if (ci_end > nci) ci_end = nci;
-    long total = 0;
-    for (int ci = ci_begin; ci < ci_end; ++ci) {
-        float ilo[3], ihi[3];
-        bb_of(xs, perm, ci * M, M, ilo, ihi);
-        for (int s = 13; s < 27; ++s) {
-            int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
-            float sv[3];
-            for (int a = 0; a < 3; ++a) sv[a] = (float)sh[a] * Lf[a];
-            float slo[3], shi[3];
-            for (int a = 0; a < 3; ++a) { volatile float l = ilo[a] + sv[a], h = ihi[a] + sv[a]; slo[a] = l; shi[a] = h; }
-            for (int cj = 0; cj < ncj; ++cj) {
-                if (s == 13 && !(cj * N + N - 1 > ci * M)) continue;
-                float d[3];
-                for (int a = 0; a < 3; ++a) {
-                    volatile float d1 = blo[3 * cj + a] - shi[a], d2 = slo[a] - bhi[3 * cj + a];
-                    float m = d1 > d2 ? d1 : d2;
-                    d[a] = m > 0.0f ? m : 0.0f;
-                }
-                float bd2 = sq_sum3(d[0], d[1], d[2]);
-                if (!(bd2 < rl2)) continue;
-                int keep = bd2 < rb2;
-                uint64_t mask = 0;
-                for (int a = 0; a < M; ++a) {
-                    int sa = ci * M + a, oa = perm[sa];
-                    if (oa < 0) continue;
-                    float xa[3];
-                    for (int k = 0; k < 3; ++k) { volatile float t = xs[3 * sa + k] + sv[k]; xa[k] = t; }
-                    for (int b = 0; b < N; ++b) {
-                        int sb = cj * N + b, ob = perm[sb];
-                        if (ob < 0) continue;
-                        volatile float dx = xa[0] - xs[3 * sb], dy = xa[1] - xs[3 * sb + 1], dz = xa[2] - xs[3 * sb + 2];
-                        float r2 = sq_sum3(dx, dy, dz);
-                        if (r2 < rl2) keep = 1;
-                        int bit = 1;
-                        if (s == 13 && sa >= sb) bit = 0;
-                        if (bit && r2 < rl2 && is_excluded(excl_off, excl_idx, oa, ob)) bit = 0;
-                        if (bit) mask |= (uint64_t)1 << (a * N + b);
-                    }
-                }
-                if (!keep) continue;
-                if (total < cap) {
-                    out[total].ci = ci;
-                    out[total].shift = s;
-                    out[total].cj = cj;
-                    out[total].pad = 0;
-                    out[total].mask = mask;
-                }
-                ++total;
-            }
-        }
+    if (ci_begin < 0) ci_begin = 0;
+    const int blk = 16;
+    int nblk = ci_end > ci_begin ? (ci_end - ci_begin + blk - 1) / blk : 0;
+    entry_buf *bufs = (entry_buf *)calloc((size_t)(nblk > 0 ? nblk : 1), sizeof(entry_buf));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < nblk; ++b) {
+        int c1 = ci_begin + (b + 1) * blk;
+        if (c1 > ci_end) c1 = ci_end;
+        for (int ci = ci_begin + b * blk; ci < c1; ++ci)
+            list_one_ci(ci, M, N, ncj, xs, perm, Lf, blo, bhi, rl2, rb2, excl_off, excl_idx, bufs + b);
     }
+    long total = 0;
+    for (int b = 0; b < nblk; ++b) {
+        for (long k = 0; k < bufs[b].n; ++k, ++total)
+            if (total < cap) out[total] = bufs[b].e[k];
+        free(bufs[b].e);
+    }
+    free(bufs);
     free(blo); free(bhi);
     return total;
 }
@@ -648,10 +682,20 @@ long oracle_recount(int n, const float *xyz0, const float *xyzt, const float *q,
     }
     float Lf[3] = {(float)box[0], (float)box[1], (float)box[2]};
     int nci = n_slots / M, ncj = n_slots / N;
-    for (int k = 0; k < nb; ++k) hist[k] = 0.0;
-    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, 1};
+    float *blo = (float *)malloc((size_t)ncj * 3 * sizeof(float)), *bhi = (float *)malloc((size_t)ncj * 3 * sizeof(float));
+    for (int cj = 0; cj < ncj; ++cj) bb_of(xs, perm, cj * N, N, blo + 3 * cj, bhi + 3 * cj);
+    oracle_params p = {rc, beta, coulomb_f, ntypes, c6c12, 1, 0, 0.0, 0.0};
+    /* i-clusters in fixed blocks, each with its own histogram, summed in block
+     * order afterwards: the result does not depend on the thread count */
+    const int blk = 16;
+    int nblk = (nci + blk - 1) / blk;
+    double *bh = (double *)calloc((size_t)(nblk > 0 ? nblk : 1) * nb, sizeof(double));
     long counted = 0;
-    for (int ci = 0; ci < nci; ++ci) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : counted)
+    for (int bk = 0; bk < nblk; ++bk) {
+      double *h = bh + (size_t)bk * nb;
+      int c1 = (bk + 1) * blk < nci ? (bk + 1) * blk : nci;
+      for (int ci = bk * blk; ci < c1; ++ci) {
         float ilo[3], ihi[3];
         bb_of(xs, perm, ci * M, M, ilo, ihi);
         for (int s = 13; s < 27; ++s) {
@@ -660,12 +704,10 @@ long oracle_recount(int n, const float *xyz0, const float *xyzt, const float *q,
             for (int a = 0; a < 3; ++a) sv[a] = (float)sh[a] * Lf[a];
             for (int cj = 0; cj < ncj; ++cj) {
                 if (s == 13 && !(cj * N + N - 1 > ci * M)) continue;
-                float jlo[3], jhi[3];
-                bb_of(xs, perm, cj * N, N, jlo, jhi);
                 float d[3];
                 for (int a = 0; a < 3; ++a) {
-                    volatile float l = ilo[a] + sv[a], h = ihi[a] + sv[a];
-                    volatile float d1 = jlo[a] - h, d2 = l - jhi[a];
+                    volatile float l = ilo[a] + sv[a], hh = ihi[a] + sv[a];
+                    volatile float d1 = blo[3 * cj + a] - hh, d2 = l - bhi[3 * cj + a];
                     float m = d1 > d2 ? d1 : d2;
                     d[a] = m > 0.0f ? m : 0.0f;
                 }
@@ -709,13 +751,18 @@ long oracle_recount(int n, const float *xyz0, const float *xyzt, const float *q,
                         int kb = (int)floor((tau - rc) / db);
                         if (kb < 0) continue;          /* listed even at zero buffer */
                         if (kb >= nb) kb = nb - 1;
-                        hist[kb] += elj + ec;
+                        h[kb] += elj + ec;
                         ++counted;
                     }
                 }
             }
         }
+      }
     }
+    for (int k = 0; k < nb; ++k) hist[k] = 0.0;
+    for (int bk = 0; bk < nblk; ++bk)
+        for (int k = 0; k < nb; ++k) hist[k] += bh[(size_t)bk * nb + k];
+    free(bh); free(blo); free(bhi);
     free(slot_of); free(img); free(xw); free(cs); free(cc); free(perm); free(xs);
     return counted;
 }

@@ -151,3 +151,92 @@ def test_mlp_special_cases():
     g = np.random.default_rng(1).normal(size=mlp.NPARAM)
     p1, m, v = mlp.adam_step(np.zeros_like(g), g, np.zeros_like(g), np.zeros_like(g), 1, 0.01)
     np.testing.assert_allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def _pair_potential(r, rc, beta, f, qa, qb, c6, c12):
+    """LJ + Ewald real-space pair potential (Eq. 1 and the erfc term of Eq. 2), shifted to zero at rc."""
+    def v(x):
+        return c12 / x ** 12 - c6 / x ** 6 + f * qa * qb * math.erfc(beta * x) / x
+    return v(r) - v(rc)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("rc,beta", [(1.0, 3.12), (0.9, 3.47), (1.2, 2.6)])
+def test_potential_derivatives_match_finite_differences(ta, tb, rc, beta):
+    """V'(rc) and V''(rc) of every SPC/E type pair equal Richardson-extrapolated central differences of the
+    shifted pair potential itself (appendix: the Taylor coefficients of the potential at the cut-off)."""
+    lj = synth.lj_table_spce()
+    q = [synth.Q_O, synth.Q_H]
+    c6, c12 = lj[ta, tb]
+    args = (rc, beta, synth.COULOMB_F, q[ta], q[tb], c6, c12)
+
+    def d1(h):
+        return (_pair_potential(rc + h, *args) - _pair_potential(rc - h, *args)) / (2 * h)
+
+    def d2(h):
+        return (_pair_potential(rc + h, *args) - 2 * _pair_potential(rc, *args) + _pair_potential(rc - h, *args)) / h ** 2
+
+    h = 2e-3
+    fd1 = (4 * d1(h / 2) - d1(h)) / 3
+    fd2 = (4 * d2(h / 2) - d2(h)) / 3
+    v1, v2 = drift.pot_derivs(rc, beta, synth.COULOMB_F, q[ta], q[tb], c6, c12)
+    assert v1 == pytest.approx(fd1, rel=1e-7)
+    assert v2 == pytest.approx(fd2, rel=1e-6)
+
+
+def test_list_lifetime_is_eighteen_fs():
+    """Sec. 5 quotes a pair-list lifetime of 18 fs for lists updated every 10 steps of 2 fs: the displacement
+    time of the bound is (nstlist - 1) dt, not nstlist dt."""
+    kw = _spce_kw(nstlist=10)
+    rb = 0.03
+    t = 0.018
+    n = np.asarray(kw["counts"], float)
+    m = np.asarray(kw["masses"], float)
+    q = np.asarray(kw["charges"], float)
+    total = 0.0
+    for a in range(2):
+        for b in range(2):
+            sig = math.sqrt(synth.KB * kw["T"] * t * t * (1 / m[a] + 1 / m[b]))
+            v1, v2 = drift.pot_derivs(kw["rc"], kw["beta"], synth.COULOMB_F, q[a], q[b], *kw["c6c12"][a][b])
+            total += 0.5 * n[a] * abs(drift.dV_pair(rb, kw["rc"], sig, n[b] / kw["volume"], v1, v2))
+    assert drift.drift_rate(rb, **kw) == pytest.approx(total / (n.sum() * 10 * 0.002), rel=1e-12)
+
+
+def test_bound_matches_monte_carlo_free_particles():
+    """The appendix's setting simulated directly: an ideal gas of one species (uniform positions, a purely
+    repulsive screened-Coulomb pair potential shifted at rc), each particle displaced by a Gaussian of
+    variance kB T t^2 / m per dimension.  The energy of the pairs that start beyond r_l = rc + r_b and end
+    inside rc, summed over unordered pairs, is what the bound estimates per list lifetime:
+    drift_rate * N * nstlist * dt.  The bound takes r_0^2 ~ (r_l + sigma)^2 and a second-order expansion of
+    the potential, so it sits a few per cent above the simulated value; a lost 1/2 (pairs counted twice) or a
+    per-type instead of per-atom normalisation would put it off by 2x."""
+    rng = np.random.default_rng(20130607)
+    n, L = 4000, 5.1
+    rc, beta, rb = 0.6, 3.0, 0.02
+    qv, mass, T, dt, nst = 0.5, 1.008, 300.0, 0.002, 10
+    t = (nst - 1) * dt
+    sd = math.sqrt(synth.KB * T * t * t / mass)
+    from scipy import special
+    vc = synth.COULOMB_F * qv * qv * special.erfc(beta * rc) / rc
+    rl = rc + rb
+    missed = []
+    for draw in range(4):
+        x0 = rng.uniform(0, L, (n, 3))
+        xt = x0 + rng.normal(0, sd, (n, 3))
+        e = 0.0
+        for i in range(n - 1):
+            d0 = x0[i] - x0[i + 1:]
+            d0 -= L * np.round(d0 / L)
+            dt_ = xt[i] - xt[i + 1:]
+            dt_ -= L * np.round(dt_ / L)
+            r0 = np.sqrt((d0 * d0).sum(1))
+            r1 = np.sqrt((dt_ * dt_).sum(1))
+            sel = (r0 >= rl) & (r1 < rc)
+            rr = r1[sel]
+            e += float(np.sum(synth.COULOMB_F * qv * qv * special.erfc(beta * rr) / rr - vc))
+        missed.append(e)
+    e_mc = float(np.mean(missed))
+    bound = drift.drift_rate(rb, T=T, dt=dt, nstlist=nst, masses=[mass], charges=[qv], c6c12=np.zeros((1, 1, 2)),
+                             counts=[n], volume=L ** 3, rc=rc, beta=beta, f=synth.COULOMB_F) * n * nst * dt
+    assert e_mc > 0
+    assert 0.95 < bound / e_mc < 1.3, (bound, e_mc, missed)
