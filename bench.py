@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shape", default="8x8")
-    ap.add_argument("--variant", default="direct", choices=["direct", "compact", "super"])
+    ap.add_argument("--variant", default="direct", choices=["direct", "super"])
     ap.add_argument("--list-order", default="canonical", choices=["canonical", "distance"])
     ap.add_argument("--coulomb", default="ewald", choices=["ewald", "rf", "table"],
                     help="Coulomb correction: Ewald (analytic), reaction field (eps_rf 78), Ewald from a table")
@@ -239,8 +239,7 @@ def main():
     f = torch.zeros((box.n, 3), dtype=torch.float32, device=dev)
     e = torch.zeros(2, dtype=torch.float64, device=dev)
     ctx = mxn.nb_create(0)
-    mxn.nb_set_force_variant(ctx, {"direct": mxn.NB_FORCE_DIRECT, "compact": mxn.NB_FORCE_COMPACT,
-                                   "super": mxn.NB_FORCE_SUPER}[args.variant])
+    mxn.nb_set_force_variant(ctx, {"direct": mxn.NB_FORCE_DIRECT, "super": mxn.NB_FORCE_SUPER}[args.variant])
     coulomb = {"ewald": mxn.NB_COULOMB_EWALD, "rf": mxn.NB_COULOMB_RF, "table": mxn.NB_COULOMB_EWALD_TABLE}[args.coulomb]
     params = mxn.make_params(w.rc, w.beta, synth.COULOMB_F, lj, True, coulomb, 78.0)
     state = {"grid": None, "lst": None}

@@ -20,7 +20,7 @@
  *   - Work is enqueued on the context's HIP stream and is asynchronous unless
  *     stated otherwise.  Errors found on the host are returned immediately as
  *     a negative nb_status; errors found by kernels (non-finite coordinates,
- *     list capacity overflow) are latched on the device and returned by the
+ *     list capacity overflow, LJ types out of range) are latched on the device and returned by the
  *     next nb_sync on that context.  nb_last_error() describes the most recent
  *     non-OK status of the calling thread.  No C++ exception crosses the ABI.
  *   - Periodic orthorhombic boxes only, every edge longer than 2 * rlist.
@@ -76,7 +76,7 @@ typedef struct { int m, n; } nb_shape;
  *               force and potential interpolated linearly from a table in LDS
  *               (spacing 1 pm; Sec. 3.2 "linear table interpolation").
  *             RF and the table are supported by the direct force kernel on single
- *             systems; the compact kernel, batches and nb_recount take Ewald only.
+ *             systems; batches and nb_recount take Ewald only.
  *   eps_rf    reaction field: relative permittivity beyond rc (>= 1, or 0) */
 enum { NB_COULOMB_EWALD = 0, NB_COULOMB_RF = 1, NB_COULOMB_EWALD_TABLE = 2 };
 typedef struct {
@@ -116,7 +116,10 @@ const char *nb_last_error(void);
  *   n       number of particles (>= 1)
  *   xyzq    DEVICE float[4n]: x, y, z, q in original order (x may lie outside
  *           the box; each particle is wrapped and its image count recorded)
- *   type    DEVICE int[n]: LJ type in [0, ntypes)
+ *   type    DEVICE int[n]: LJ type in [0, ntypes).  A negative type latches
+ *           NB_ERR_ARG for nb_sync; so does a type >= ntypes, found by the
+ *           first nb_forces, nb_batch_forces, nb_recount or nb_rdf call that
+ *           is given ntypes (the results of that call are then wrong)
  *   shape   cluster shape
  *   grid    in/out: *grid == NULL creates a grid, otherwise it is reused
  *           (storage grows as needed).
@@ -221,7 +224,8 @@ int nb_pairlist_prune(nb_ctx *ctx, const nb_list *outer, const float *xyzq_now, 
  * of real particles of the list closer than r_max (optionally skipping
  * force-field exclusions) is counted in bin k of its type pair:
  *   hist[(lo * ntypes + hi) * nbins + k] += 1,  lo <= hi the two types
- * (clamped to [0, ntypes)); the (hi, lo) half stays untouched.  The bin is
+ * (a type outside [0, ntypes) latches NB_ERR_ARG, as for nb_forces); the
+ * (hi, lo) half stays untouched.  The bin is
  * decided in FP32: k is the largest with e_k <= r2, e_k = (float)((k dr)^2)
  * computed in FP64 with dr = r_max / nbins, and r2 the squared FP32
  * distance of the pair in its listed image.  Counts are exact (integer).
@@ -290,8 +294,6 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
  *   NB_FORCE_DIRECT (default): every listed pair is visited in lock-step with
  *     a per-lane cut-off branch (the cut-off conditional of the paper's GPU
  *     kernel); passes whose pairs are all beyond rc skip the interaction.
- *   NB_FORCE_COMPACT: in-range pairs of each work item are first compacted
- *     through LDS into full wavefront passes.
  *   NB_FORCE_SUPER: the super-cluster layout of the paper's GPU kernel
  *     (Sec. 2.3 and 3.2): 8 (or 4) consecutive i-clusters share one list
  *     of j-clusters, each with a bit per i-cluster it reaches, so each
@@ -303,7 +305,7 @@ int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float
  *     per super-cluster) or 1024 (4); other lists use the direct kernel.
  * Results agree to rounding; the choice is a tuning knob.  Each variant's
  * forces are reproducible bit for bit for a given list and positions. */
-enum { NB_FORCE_DIRECT = 0, NB_FORCE_COMPACT = 1, NB_FORCE_SUPER = 2 };
+enum { NB_FORCE_DIRECT = 0, NB_FORCE_SUPER = 2 };
 int nb_set_force_variant(nb_ctx *ctx, int variant);
 
 /* Super-cluster layout: i-clusters per super-cluster (4 or 8, or 0 for the
@@ -429,9 +431,12 @@ enum { NB_BUFFER_ANALYTIC = 0, NB_BUFFER_MLP = 1, NB_BUFFER_AUTO = 2 };
  * FP64.  MLP / AUTO: the learned predictor attached with nb_buffer_set_mlp
  * (its inference kernel on the context's stream, synchronous), giving
  * min(prediction + margin, analytic buffer); outside the model's feature
- * ranges, for a non-finite prediction, or (AUTO) without a model, the
- * analytic buffer is returned and *used_fallback = 1.  MLP without a model:
- * NB_ERR_STATE.
+ * ranges, outside its training domain (nb_mlp_set_domain: a query with a
+ * stricter target, another time step, another beta * rc or other charges or
+ * LJ parameters than the model's labels were generated for, or a model with
+ * no recorded domain), for a non-finite prediction, or (AUTO) without a
+ * model, the analytic buffer is returned and *used_fallback = 1.  MLP
+ * without a model: NB_ERR_STATE.
  *   ctx        may be NULL for ANALYTIC
  *   rb_out     nm;  drift_out  analytic drift estimate at *rb_out
  */
@@ -464,6 +469,12 @@ int nb_mlp_train_step(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, 
 /* Gradient of the batch loss (DEVICE float[NB_MLP_PARAMS]) without updating the model. */
 int nb_mlp_grad(nb_ctx *ctx, nb_mlp *mlp, const float *X, const float *y, int batch, float *grad, float *loss);
 int nb_mlp_infer(nb_ctx *ctx, const nb_mlp *mlp, const float *X, int batch, float *y);
+/* Record the conditions the model's labels were generated for: q->target,
+ * q->dt, q->beta * q->rc (relative tolerance 5e-3), and the per-type charges
+ * and C6/C12 table (relative 1e-9); the other fields of q are ignored.  The
+ * learned modes of nb_buffer_estimate answer only queries inside this domain
+ * (Sec. 5: the buffer is chosen for a given drift target and potential). */
+int nb_mlp_set_domain(nb_mlp *mlp, const nb_buffer_query *q);
 /* Attach (mlp != NULL) or detach the predictor used by nb_buffer_estimate;
  * margin (nm) is added to its prediction. */
 int nb_buffer_set_mlp(nb_ctx *ctx, const nb_mlp *mlp, double margin);

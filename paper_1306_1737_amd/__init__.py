@@ -32,12 +32,12 @@ EXPORTS = [
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
     "nb_list_stats", "nb_set_force_variant", "nb_set_super_cluster", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
-    "nb_buffer_set_mlp",
+    "nb_buffer_set_mlp", "nb_mlp_set_domain",
     "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
     "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
-NB_FORCE_DIRECT, NB_FORCE_COMPACT, NB_FORCE_SUPER = 0, 1, 2
+NB_FORCE_DIRECT, NB_FORCE_SUPER = 0, 2
 NB_COULOMB_EWALD, NB_COULOMB_RF, NB_COULOMB_EWALD_TABLE = 0, 1, 2
 NB_RDF_SKIP_EXCLUDED = 1
 NB_TIMER_FORCE_KERNEL, NB_TIMER_FORCE_CALL, NB_TIMER_GRID_SORT, NB_TIMER_PAIRLIST, NB_TIMER_COUNT = 0, 1, 2, 3, 4
@@ -115,7 +115,7 @@ def lib():
             "nb_mlp_create": ([vp, vp, vp, vp, pvp], i), "nb_mlp_free": ([vp], None),
             "nb_mlp_get_params": ([vp, vp], i), "nb_mlp_train_step": ([vp, vp, vp, vp, i, f, vp], i),
             "nb_mlp_grad": ([vp, vp, vp, vp, i, vp, vp], i), "nb_mlp_infer": ([vp, vp, vp, i, vp], i),
-            "nb_buffer_set_mlp": ([vp, vp, d], i),
+            "nb_buffer_set_mlp": ([vp, vp, d], i), "nb_mlp_set_domain": ([vp, ctypes.POINTER(nb_buffer_query)], i),
             "nb_batch_create": ([vp, i, vp, vp, vp, vp, pvp], i), "nb_batch_free": ([vp], None),
             "nb_batch_set_group": ([vp, i], i), "nb_batch_forces": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
             "nb_batch_capture": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
@@ -312,14 +312,20 @@ def nb_recount(ctx, grid, lst, xyzq_t, params, c_bb, db, nbins, hist):
 
 # ------------------------------------------------------- buffer estimate
 
-def nb_buffer_estimate(ctx, *, T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape,
-                       target, mode=NB_BUFFER_ANALYTIC):
+def _query(T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape, target):
+    """nb_buffer_query and the arrays it points to (kept alive by the caller)."""
     import numpy as np
     mass = np.ascontiguousarray(mass, np.float64); charge = np.ascontiguousarray(charge, np.float64)
     c6c12 = np.ascontiguousarray(c6c12, np.float64); count = np.ascontiguousarray(count, np.float64)
     q = nb_buffer_query(float(T), float(dt), int(nstlist), int(mass.shape[0]), mass.ctypes.data, charge.ctypes.data,
                         c6c12.ctypes.data, count.ctypes.data, float(volume), float(rc), float(beta),
                         float(coulomb_f), nb_shape(*shape), float(target))
+    return q, (mass, charge, c6c12, count)
+
+
+def nb_buffer_estimate(ctx, *, T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape,
+                       target, mode=NB_BUFFER_ANALYTIC):
+    q, keep = _query(T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape, target)
     rb, drift, fb = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
     _check(lib().nb_buffer_estimate(ctx, ctypes.byref(q), int(mode), ctypes.byref(rb), ctypes.byref(drift),
                                     ctypes.byref(fb)))
@@ -390,6 +396,16 @@ def nb_mlp_grad(ctx, mlp, X, y, grad, loss=None):
 
 def nb_mlp_infer(ctx, mlp, X, y):
     _check(lib().nb_mlp_infer(ctx, mlp, _ptr(X), int(X.shape[0]), _ptr(y)))
+
+
+def nb_mlp_set_domain(mlp, *, dt, charge, c6c12, rc, beta, target, T=300.0, nstlist=10, mass=(1.0,),
+                      count=None, volume=1.0, coulomb_f=138.935458, shape=(8, 8)):
+    """Record the conditions the model's labels were generated for (target, dt, beta*rc, charges, LJ)."""
+    nt = len(charge)
+    mass = list(mass) * nt if len(mass) == 1 else mass
+    count = [1.0] * nt if count is None else count
+    q, keep = _query(T, dt, nstlist, mass, charge, c6c12, count, volume, rc, beta, coulomb_f, shape, target)
+    _check(lib().nb_mlp_set_domain(mlp, ctypes.byref(q)))
 
 
 def nb_buffer_set_mlp(ctx, mlp, margin):

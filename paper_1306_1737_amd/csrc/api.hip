@@ -143,6 +143,9 @@ int nb_sync(nb_ctx *c) {
     if (flags) MXN_HIP(hipMemset(c->d_flags, 0, sizeof(int)));
     if (flags & FLAG_NONFINITE) return fail(NB_ERR_NONFINITE, "non-finite or out-of-range coordinate or charge");
     if (flags & FLAG_OVERFLOW) return fail(NB_ERR_OVERFLOW, "pair-list capacity exceeded: rebuild the list");
+    if (flags & FLAG_TYPE)
+        return fail(NB_ERR_ARG, "an LJ type outside [0, ntypes): such particles were computed with a valid row "
+                                "and their results are wrong");
     if (flags & FLAG_FORCE_RANGE)
         return fail(NB_ERR_NONFINITE, "a force term is non-finite or beyond the summation range (|F| >= 2^36 "
                                       "kJ/mol/nm, overlapping particles): those forces are NaN");
@@ -494,7 +497,7 @@ int nb_set_search_parts(nb_ctx *c, int parts) {
 
 int nb_set_force_variant(nb_ctx *c, int variant) {
     if (!c) return fail(NB_ERR_ARG, "nb_set_force_variant: ctx is null");
-    if (variant != NB_FORCE_COMPACT && variant != NB_FORCE_DIRECT && variant != NB_FORCE_SUPER)
+    if (variant != NB_FORCE_DIRECT && variant != NB_FORCE_SUPER)
         return fail(NB_ERR_ARG, "nb_set_force_variant: unknown variant");
     c->force_variant = variant;
     return NB_OK;
@@ -527,8 +530,6 @@ int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_n
         return fail(NB_ERR_ARG, "nb_forces: unknown coulomb type");
     if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
         return fail(NB_ERR_ARG, "nb_forces: eps_rf must be >= 1, or 0 for a conducting boundary");
-    if (p->coulomb != NB_COULOMB_EWALD && c->force_variant == NB_FORCE_COMPACT)
-        return fail(NB_ERR_UNSUPPORTED, "nb_forces: reaction field and the Ewald table need the direct or super-cluster kernel");
     if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
         return fail(NB_ERR_UNSUPPORTED, "nb_forces: beta*rc > 4 is outside the fitted Ewald range");
     MXN_HIP(hipSetDevice(c->device));
@@ -549,7 +550,7 @@ int nb_rdf(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now,
     if (rdf_lds_bytes(nbins, ntypes) > 64 * 1024)
         return fail(NB_ERR_UNSUPPORTED, "nb_rdf: the histogram (ntypes^2 * nbins) and edges exceed 64 KB of LDS");
     MXN_HIP(hipSetDevice(c->device));
-    int rc = launch_gather(c, g, xyzq_now);
+    int rc = launch_gather(c, g, xyzq_now, ntypes);
     return rc ? rc : launch_rdf(c, g, l, r_max, nbins, ntypes, (flags & NB_RDF_SKIP_EXCLUDED) ? 1 : 0, hist);
 }
 
@@ -1045,6 +1046,37 @@ int nb_mlp_infer(nb_ctx *c, const nb_mlp *m, const float *X, int batch, float *y
     return launch_mlp_infer(c, m, X, batch, y);
 }
 
+int nb_mlp_set_domain(nb_mlp *m, const nb_buffer_query *q) {
+    if (!m) return fail(NB_ERR_ARG, "nb_mlp_set_domain: model is null");
+    CHECK(validate_query(q));
+    if (!(q->target > 0.0)) return fail(NB_ERR_ARG, "nb_mlp_set_domain: target must be > 0");
+    m->dom_target = q->target;
+    m->dom_dt = q->dt;
+    m->dom_brc = q->beta * q->rc;
+    m->dom_ntypes = q->ntypes;
+    m->dom_charge.assign(q->charge, q->charge + q->ntypes);
+    m->dom_c6c12.assign(q->c6c12, q->c6c12 + 2 * q->ntypes * q->ntypes);
+    m->has_domain = true;
+    return NB_OK;
+}
+
+// A query the model may answer: its labels were generated for the same time
+// step, Ewald accuracy (beta * rc) and interaction parameters, and for a
+// drift target no looser than the query's (a buffer meeting a stricter
+// target also meets a looser one).
+static bool mlp_domain_ok(const nb_mlp *m, const nb_buffer_query &q) {
+    auto close = [](double a, double b, double rel) { return std::fabs(a - b) <= rel * std::fmax(std::fabs(a), std::fabs(b)); };
+    if (!m->has_domain) return false;
+    if (q.target < m->dom_target * (1.0 - 1e-12)) return false;
+    if (!close(q.dt, m->dom_dt, 1e-9) || !close(q.beta * q.rc, m->dom_brc, 5e-3)) return false;
+    if (q.ntypes != m->dom_ntypes) return false;
+    for (int a = 0; a < q.ntypes; ++a)
+        if (!close(q.charge[a], m->dom_charge[a], 1e-9)) return false;
+    for (int k = 0; k < 2 * q.ntypes * q.ntypes; ++k)
+        if (!close(q.c6c12[k], m->dom_c6c12[k], 1e-9)) return false;
+    return true;
+}
+
 int nb_buffer_set_mlp(nb_ctx *c, const nb_mlp *m, double margin) {
     if (!c) return fail(NB_ERR_ARG, "nb_buffer_set_mlp: ctx is null");
     if (m && m->ctx != c) return fail(NB_ERR_STATE, "nb_buffer_set_mlp: model belongs to another context");
@@ -1093,7 +1125,7 @@ int nb_buffer_estimate(nb_ctx *c, const nb_buffer_query *q, int mode, double *rb
         if (!c) return fail(NB_ERR_ARG, "nb_buffer_estimate: the learned modes need a context");
         if (!c->mlp && mode == NB_BUFFER_MLP) return fail(NB_ERR_STATE, "nb_buffer_estimate: no model attached");
         float f[8];
-        bool in_range = c->mlp && buffer_features(*q, f);
+        bool in_range = c->mlp && mlp_domain_ok(c->mlp, *q) && buffer_features(*q, f);
         if (in_range)
             for (int i = 0; i < 5; ++i)
                 if (!(f[i] >= c->mlp->lo_h[i] && f[i] <= c->mlp->hi_h[i])) in_range = false;   // outside training data

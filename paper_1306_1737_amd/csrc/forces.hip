@@ -100,6 +100,7 @@ __global__ void k_gather(ForceArgs a) {
         float4 p = a.xyzq_now[o];
         const int im = a.img_s[s];
         if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(a.flags, mxn::FLAG_NONFINITE);
+        if (a.nt > 0 && a.type_s[s] >= a.nt) atomicOr(a.flags, mxn::FLAG_TYPE);
         p.x -= (float)((im & 1023) - 512) * a.Lx;
         p.y -= (float)(((im >> 10) & 1023) - 512) * a.Ly;
         p.z -= (float)(((im >> 20) & 1023) - 512) * a.Lz;
@@ -861,196 +862,6 @@ __global__ __launch_bounds__(256) void k_stats(ForceArgs a, unsigned long long *
     }
 }
 
-// LDS communication between the lanes of one wavefront
-__device__ inline void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ inline int lane_rank(unsigned long long bal) {
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-}
-
-template <int N>
-constexpr int wave_lds_bytes() {
-    return mxn::item_entries(N) * N * 32 + 128 * 4;
-}
-
-// Compacted variant (default).  A wavefront stages its work item's j-particles
-// in LDS (position moved into the i-cluster's image, charge, type, mask and a
-// per-slot bitmask of the i-particles within rc).  Then for each i-particle it
-// compacts the in-range j-slots into a 64-entry queue and evaluates the pair
-// interactions only in full (or final partial) 64-lane passes: the i-force
-// stays in registers (one i-particle per pass), the j-forces go to per-slot
-// LDS accumulators that are conflict-free within a pass, and at the end each
-// j-slot stores its force into the per-entry buffer (coalesced).  Compared with
-// evaluating every listed pair in lock-step, this skips the pairs beyond rc
-// (about two thirds of an 8x8 list at rlist = rc + 0.1 nm) at the cost of LDS
-// staging.
-template <int M, int N, bool ENER, bool VIR, bool ACC64>
-__global__ __launch_bounds__(256) void k_forces_c(ForceArgs a) {
-    constexpr int JMAX = mxn::item_entries(N) * N;
-    constexpr unsigned FULL = (1u << M) - 1u;
-    const long total = a.totals[2];
-    if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
-    extern __shared__ float4 smem[];
-    float4 *svec = smem;
-    float4 *ljt = smem + 32;
-    for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
-    fill_ljt(a, ljt);
-    __syncthreads();
-
-    using acc_t = typename std::conditional<ACC64, double, float>::type;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const EwPoly ew = ew_poly(a);
-    char *wb = reinterpret_cast<char *>(smem + 32 + a.nt * a.nt + 1) + (size_t)wave * wave_lds_bytes<N>();
-    float4 *jd = reinterpret_cast<float4 *>(wb);
-    int *jinfo = reinterpret_cast<int *>(wb + JMAX * 16);
-    float *fjx = reinterpret_cast<float *>(wb + JMAX * 20);
-    float *fjy = fjx + JMAX, *fjz = fjy + JMAX;
-    int *pend = reinterpret_cast<int *>(wb + JMAX * 32);
-
-    const long item = xcd_item(total, 4, wave);
-    if (item < 0) return;
-    const int4 it = a.items[item];
-    const int ci = __builtin_amdgcn_readfirstlane(it.x);
-    const int js = __builtin_amdgcn_readfirstlane(it.y);
-    const int je = __builtin_amdgcn_readfirstlane(it.z);
-    const int nslot = (je - js) * N;
-
-    // stage the item's j-particles
-    for (int base = 0; base < nslot; base += 64) {
-        const int jidx = base + lane;
-        const bool valid = jidx < nslot;
-        const nb_jentry en = a.entries[js + (valid ? jidx : 0) / N];
-        const int jslot = en.cj * N + (jidx % N);
-        const float4 pj = a.xs_now[jslot];
-        const int tjr = a.type_s[jslot];
-        const int tj = min(max(tjr, 0), a.nt - 1);
-        const float4 sv = svec[en.shift];
-        const float xj = pj.x - sv.x, yj = pj.y - sv.y, zj = pj.z - sv.z;
-        const unsigned long long m64 = ((unsigned long long)en.mhi << 32) | en.mlo;
-        const unsigned mb = (unsigned)(m64 >> ((jidx % N) * M)) & FULL;
-        unsigned act = tjr < 0 ? 0u : FULL;   // dummies (type -1) never interact
-        if (en.shift == 13) {   // self or overlapping cluster pair: only slot(i) < slot(j)
-            const int t = jslot - ci * M;
-            act &= t >= M ? FULL : (t <= 0 ? 0u : (1u << t) - 1u);
-        }
-        unsigned inr = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const float4 pik = a.xs_now[ci * M + k];
-            const float dx = pik.x - xj, dy = pik.y - yj, dz = pik.z - zj;
-            const bool ireal = a.type_s[ci * M + k] >= 0;
-            inr |= (unsigned)(ireal && dx * dx + dy * dy + dz * dz < a.rc2) << k;
-        }
-        inr &= act;
-        if (valid) {
-            jd[jidx] = make_float4(xj, yj, zj, pj.w);
-            jinfo[jidx] = tj | (int)(mb << 8) | (int)(inr << 16);
-            fjx[jidx] = 0.0f;
-            fjy[jidx] = 0.0f;
-            fjz[jidx] = 0.0f;
-        }
-    }
-    wave_lds_sync();
-
-    acc_t elj = 0, ec = 0;
-    acc_t viri[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) viri[k] = 0;
-    for (int k = 0; k < M; ++k) {
-        const float4 pik = a.xs_now[ci * M + k];
-        const float qik = pik.w * a.coulomb_f;
-        const int tt = a.type_s[ci * M + k];
-        const int tik = lj_ioff(a, tt);
-        float fx = 0.0f, fy = 0.0f, fz = 0.0f, el = 0.0f, ecl = 0.0f;
-        auto pass = [&](int pidx) {
-            if (pidx < 0) return;
-            const float4 pj = jd[pidx];
-            const int info = jinfo[pidx];
-            const float dx = pik.x - pj.x, dy = pik.y - pj.y, dz = pik.z - pj.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const bool bit = (info >> (8 + k)) & 1;
-            const float fsc = pair_term<ENER, 0>(a, ew, ljt, nullptr, r2, qik * pj.w, bit, tik + ((info & 255) << 4), el, ecl);
-            fx = fmaf(fsc, dx, fx);
-            fy = fmaf(fsc, dy, fy);
-            fz = fmaf(fsc, dz, fz);
-            atomicAdd(fjx + pidx, -fsc * dx);
-            atomicAdd(fjy + pidx, -fsc * dy);
-            atomicAdd(fjz + pidx, -fsc * dz);
-        };
-        int P = 0;
-        for (int base = 0; base < nslot; base += 64) {
-            const int jidx = base + lane;
-            const bool in = jidx < nslot && ((jinfo[jidx] >> (16 + k)) & 1);
-            const unsigned long long bal = __ballot(in);
-            if (in) pend[P + lane_rank(bal)] = jidx;
-            P += __popcll(bal);
-            if (P >= 64) {
-                wave_lds_sync();
-                pass(pend[lane]);
-                const int rem = P - 64;
-                const int carry = lane < rem ? pend[64 + lane] : 0;
-                wave_lds_sync();
-                if (lane < rem) pend[lane] = carry;
-                P = rem;
-            }
-        }
-        if (P > 0) {
-            wave_lds_sync();
-            pass(lane < P ? pend[lane] : -1);
-        }
-        wave_lds_sync();
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
-        if (lane == 0) {
-            a.fi[item * M + k] = make_float4(fx, fy, fz, 0.0f);
-            if (VIR) {
-                viri[0] += (acc_t)pik.x * (acc_t)fx; viri[1] += (acc_t)pik.x * (acc_t)fy; viri[2] += (acc_t)pik.x * (acc_t)fz;
-                viri[3] += (acc_t)pik.y * (acc_t)fx; viri[4] += (acc_t)pik.y * (acc_t)fy; viri[5] += (acc_t)pik.y * (acc_t)fz;
-                viri[6] += (acc_t)pik.z * (acc_t)fx; viri[7] += (acc_t)pik.z * (acc_t)fy; viri[8] += (acc_t)pik.z * (acc_t)fz;
-            }
-        }
-        if (ENER) {
-            elj += (acc_t)el;
-            ec += (acc_t)ecl;
-        }
-    }
-
-    // j-forces: one coalesced store per slot (zero where nothing interacted)
-    acc_t vir[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) vir[k] = 0;
-    for (int base = 0; base < nslot; base += 64) {
-        const int jidx = base + lane;
-        if (jidx < nslot) {
-            const float gx = fjx[jidx], gy = fjy[jidx], gz = fjz[jidx];
-            float *o = a.fj + ((long)a.jpos[js + jidx / N] * N + jidx % N) * 3;
-            o[0] = gx;
-            o[1] = gy;
-            o[2] = gz;
-            if (VIR) {
-                const float4 pj = jd[jidx];
-                vir[0] += (acc_t)(pj.x * gx); vir[1] += (acc_t)(pj.x * gy); vir[2] += (acc_t)(pj.x * gz);
-                vir[3] += (acc_t)(pj.y * gx); vir[4] += (acc_t)(pj.y * gy); vir[5] += (acc_t)(pj.y * gz);
-                vir[6] += (acc_t)(pj.z * gx); vir[7] += (acc_t)(pj.z * gy); vir[8] += (acc_t)(pj.z * gz);
-            }
-        }
-    }
-    if (ENER || VIR) {
-        acc_t out[kNAcc];
-        out[0] = ENER ? wave_sum(elj) * (acc_t)kLJScale : (acc_t)0;
-        out[1] = ENER ? wave_sum(ec) : (acc_t)0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[2 + k] = VIR ? wave_sum(vir[k]) + viri[k] : (acc_t)0;
-        if (lane == 0)
-            for (int k = 0; k < kNAcc; ++k) a.partials[(size_t)k * a.pstride + item] = (double)out[k];
-    }
-}
-
 template <int M, int N>
 void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
     const int R = std::min(nb, kReduceParts);
@@ -1067,15 +878,13 @@ void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
 
 template <int M, int N, bool E, bool V, bool D>
 void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t st) {
-    if (variant != NB_FORCE_COMPACT) {   // direct (also for lists the super-cluster kernel does not take)
-        if (a.elec == NB_COULOMB_RF)
-            k_forces<M, N, E, V, D, 1><<<nb, 256, lds, st>>>(a);
-        else if (a.elec == NB_COULOMB_EWALD_TABLE)
-            k_forces<M, N, E, V, D, 2><<<nb, 256, lds + (size_t)a.ntab * sizeof(float2), st>>>(a);
-        else
-            k_forces<M, N, E, V, D, 0><<<nb, 256, lds, st>>>(a);
-    } else
-        k_forces_c<M, N, E, V, D><<<nb, 256, lds + 4 * wave_lds_bytes<N>(), st>>>(a);
+    (void)variant;   // direct (also for lists the super-cluster kernel does not take)
+    if (a.elec == NB_COULOMB_RF)
+        k_forces<M, N, E, V, D, 1><<<nb, 256, lds, st>>>(a);
+    else if (a.elec == NB_COULOMB_EWALD_TABLE)
+        k_forces<M, N, E, V, D, 2><<<nb, 256, lds + (size_t)a.ntab * sizeof(float2), st>>>(a);
+    else
+        k_forces<M, N, E, V, D, 0><<<nb, 256, lds, st>>>(a);
 }
 
 template <int S, bool E, bool V, bool D>
@@ -1153,6 +962,7 @@ struct BatchArgs {
     double *energy, *virial;
     int accumulate;
     int *flags;
+    int nt;                            // LJ types: particles of a type >= nt are reported
 };
 
 __device__ inline int find_rep(const long *off, int n, long x) {
@@ -1201,6 +1011,7 @@ __global__ void k_batch_gather(BatchArgs b) {
         float4 p = d.xyzq_now[o];
         const int im = d.img_s[s];
         if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(b.flags, mxn::FLAG_NONFINITE);
+        if (d.type_s[s] >= b.nt) atomicOr(b.flags, mxn::FLAG_TYPE);
         p.x -= (float)((im & 1023) - 512) * d.Lx;
         p.y -= (float)(((im >> 10) & 1023) - 512) * d.Ly;
         p.z -= (float)(((im >> 20) & 1023) - 512) * d.Lz;
@@ -1290,8 +1101,10 @@ int launch_batch_shape(const ForceArgs &a, const BatchArgs &b, unsigned flags, l
 
 namespace mxn {
 
-int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now) {
+int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now, int nt) {
     ForceArgs a{};
+    a.type_s = (const int *)g->type_s.p;
+    a.nt = nt;
     a.nslots = (const int *)g->nslots.p;
     a.perm = (const int *)g->perm.p;
     a.img_s = (const int *)g->img_s.p;
@@ -1521,6 +1334,7 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
     b.virial = virial;
     b.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
     b.flags = ctx->d_flags;
+    b.nt = p->ntypes;
     k_batch_prefix<<<1, 1024, 0, st>>>(b);
     k_batch_gather<<<(int)((bt->total_slots + 255) / 256), 256, 0, st>>>(b);
     const size_t lds = ((size_t)p->ntypes * p->ntypes + 1) * sizeof(float4);

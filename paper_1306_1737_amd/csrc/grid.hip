@@ -142,6 +142,7 @@ struct SortArgs {
     const float4 *atom_xw;
     float4 *xs, *xs_now, *colbb;
     int *type_s, *perm, *img_s, *slot_of;
+    int *flags;
 };
 
 // One workgroup per column: rank every particle by (z, original index) among
@@ -181,7 +182,9 @@ __device__ inline void col_sort_body(const SortArgs &a, int c) {
             float4 p = a.atom_xw[orig];
             a.xs[slot] = p;
             a.xs_now[slot] = p;
-            a.type_s[slot] = max(a.type[orig], 0);   // negative types clamp to 0; -1 marks dummies
+            const int t = a.type[orig];
+            if (t < 0) atomicOr(a.flags, mxn::FLAG_TYPE);   // reported by nb_sync; -1 marks dummies
+            a.type_s[slot] = max(t, 0);
             a.perm[slot] = orig;
             a.img_s[slot] = a.atom_img[orig];
             a.slot_of[orig] = slot;
@@ -459,7 +462,7 @@ static SortArgs make_sort(const nb_grid *g, const int *type) {
     return SortArgs{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
                     (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
                     (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p,
-                    (int *)g->slot_of.p};
+                    (int *)g->slot_of.p, g->ctx->d_flags};
 }
 
 size_t grid_job_size() { return sizeof(GridJob); }

@@ -26,7 +26,7 @@ int fail(int status, const std::string &msg);
     } while (0)
 
 // bits latched by kernels in ctx->d_flags
-enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_FORCE_RANGE = 4 };
+enum : int { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_FORCE_RANGE = 4, FLAG_TYPE = 8 };
 
 // work items of the force kernel hold at most this many j-entries of one i-cluster
 // Entries per force work item: four wavefront passes of 64/N entries each.
@@ -167,6 +167,12 @@ struct nb_mlp {
     nb_ctx *ctx = nullptr;
     mxn::DevBuf params, m, v, step, lo, hi;
     double lo_h[8] = {0}, hi_h[8] = {0};
+    // the conditions the model's labels were generated for (nb_mlp_set_domain):
+    // drift target, time step, beta * rc and the interaction parameters per type
+    bool has_domain = false;
+    double dom_target = 0, dom_dt = 0, dom_brc = 0;
+    int dom_ntypes = 0;
+    std::vector<double> dom_charge, dom_c6c12;
 };
 
 namespace mxn {
@@ -223,7 +229,9 @@ void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
 // second stage of a two-stage list: `in` gets outer's entries with a pair within r
 // at the grid's gathered positions (xs_now)
 int launch_prune(nb_list *in, const nb_list *outer, float r);
-int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now);
+// coordinate gather into the grid's slot order; with nt > 0 it also latches
+// FLAG_TYPE for a particle whose LJ type is not below nt
+int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now, int nt = 0);
 // super-cluster view of an 8x8 list: i-clusters per super-cluster (0: none) and the build
 constexpr int kSciPerItem = 16;
 int sci_size(const nb_list *l, int want);

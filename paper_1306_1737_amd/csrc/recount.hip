@@ -138,13 +138,12 @@ __global__ void k_zero_d(double *p, int n) {
 
 namespace mxn {
 
-int launch_gather(nb_ctx *ctx, const nb_grid *g, const float *xyzq_now);
 
 int launch_recount(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_t, const nb_params *p, float c_bb,
                    float db, int nbins, double *hist) {
     hipStream_t st = ctx->stream;
     k_zero_d<<<(nbins + 255) / 256, 256, 0, st>>>(hist, nbins);
-    int rc = launch_gather(ctx, g, xyzq_t);
+    int rc = launch_gather(ctx, g, xyzq_t, p->ntypes);
     if (rc) return rc;
     RecountArgs a{};
     a.perm = (const int *)g->perm.p;

@@ -44,7 +44,8 @@ DT = 0.002
 TARGET = 0.005                 # kJ/mol/ps per atom
 LO = np.array([280.0, 0.0, 5.0, 0.95, 0.8, 0.0, 0.0, 0.0])
 HI = np.array([360.0, 0.25, 40.0, 1.05, 1.2, 1.0, 1.0, 1.0])
-DB, NBINS = 0.002, 250         # recount bins: buffers 0 .. 0.5 nm
+DB = 0.002                     # recount bin width (nm)
+SPAN_MIN, SPAN_MAX = 0.5, 1.0  # buffers the recount covers: 0 .. span (nm), see recount_span
 ERFC_TARGET_X = 3.1234132      # erfc(x) = 1e-5: beta * rc at the paper's Ewald accuracy
 
 
@@ -62,6 +63,22 @@ def features(T, nstlist, masses, counts, volume, rc, shape):
     dens = sum(c * m for c, m in zip(counts, masses)) / (volume * synth.AVOGADRO)
     oh = [1.0 if shape == s else 0.0 for s in SHAPES]
     return np.array([T, sigma_m(T, nstlist, masses, counts), nstlist, dens, rc] + oh, np.float32)
+
+
+def recount_span(T, nstlist, masses):
+    """Largest buffer (nm) the exact recount covers for one condition.
+
+    The recount sees only the pairs of the list built at r_c + span, so the
+    missed energy of every buffer lacks the pairs that start beyond that
+    radius and still end inside r_c.  Six displacement widths of the
+    lightest pair, sqrt(2 kB T t^2 / m_min), put that tail many orders of
+    magnitude below the energy at the label (at 360 K and nstlist 40, the
+    widest condition, the width is 0.19 nm and the span is capped at 1 nm,
+    2.9 widths beyond the largest labels); narrow conditions keep 0.5 nm.
+    """
+    t = (nstlist - 1) * DT
+    s = math.sqrt(2.0 * synth.KB * T * t * t / min(masses))
+    return min(SPAN_MAX, max(SPAN_MIN, DB * math.ceil(6.0 * s / DB - 1e-9)))
 
 
 def label_from_hist(hist, n_atoms, nstlist, target=TARGET, db=DB):
@@ -97,11 +114,15 @@ class BoxPool:
                 mxn.nb_grid_free(g)
 
 
-def recount_hist(ctx, d, shape, rc, beta, masses, T, nstlist, seed, lj, rb_max=DB * NBINS):
-    """Exact missed-energy histogram for one displacement draw (bins of DB up to rb_max)."""
+def recount_hist(ctx, d, shape, rc, beta, masses, T, nstlist, seed, lj, rb_max=None):
+    """Exact missed-energy histogram for one displacement draw (bins of DB up to rb_max, by default
+    recount_span of the condition)."""
     import torch as th
     b = d["box"]
     g = d["grids"][shape]
+    if rb_max is None:
+        rb_max = recount_span(T, nstlist, masses)
+    nbins = int(round(rb_max / DB))
     spacing = (max(shape) / (b.n / b.box.prod())) ** (1.0 / 3.0)
     c_bb = np.float32(0.5 * spacing)
     rl = np.float32(rc + rb_max)
@@ -113,8 +134,8 @@ def recount_hist(ctx, d, shape, rc, beta, masses, T, nstlist, seed, lj, rb_max=D
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0xD15]))
     disp = rng.standard_normal((b.n, 3)) * np.sqrt(synth.KB * T * t * t / m_atom)[:, None]
     xt = th.from_numpy(b.xyzq((b.xyz.astype(np.float64) + disp).astype(np.float32))).to(d["xyzq"].device)
-    hist = th.zeros(NBINS, dtype=th.float64, device=xt.device)
-    mxn.nb_recount(ctx, g, lst, xt, mxn.make_params(rc, beta, synth.COULOMB_F, lj), float(c_bb), DB, NBINS, hist)
+    hist = th.zeros(nbins, dtype=th.float64, device=xt.device)
+    mxn.nb_recount(ctx, g, lst, xt, mxn.make_params(rc, beta, synth.COULOMB_F, lj), float(c_bb), DB, nbins, hist)
     return hist.cpu().numpy()
 
 
@@ -167,6 +188,9 @@ def train(ctx, X, y, epochs=150, batch=256, lr=3e-3, seed=11, val_frac=0.1, log=
     nval = max(1, int(val_frac * len(y)))
     va, tr = idx[:nval], idx[nval:]
     m = mxn.nb_mlp_create(ctx, init_params(), LO, HI)
+    # the labels' domain: drift target, time step, Ewald accuracy and SPC/E parameters of generate()
+    mxn.nb_mlp_set_domain(m, dt=DT, charge=[synth.Q_O, synth.Q_H], c6c12=synth.lj_table_spce(), rc=1.0,
+                          beta=beta_for(1.0), target=TARGET)
     Xtr = torch.from_numpy(X[tr]).to(dev)
     ytr = torch.from_numpy(y[tr]).to(dev)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
@@ -229,7 +253,7 @@ def evaluate(ctx, m, margin, n_mol=32000, L=9.86, temps=(280, 300, 330, 360), ns
                          coulomb_f=synth.COULOMB_F, shape=shape, target=TARGET)
                 rb_a, _, _ = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_ANALYTIC, **q)
                 rb_m, _, fb = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **q)
-                hist = np.zeros(NBINS)
+                hist = 0.0
                 for r in range(reps):
                     hist += recount_hist(ctx, d, shape, rc, beta, masses, float(T), nst, seed * 7919 + r, lj)
                 hist /= reps
@@ -237,7 +261,7 @@ def evaluate(ctx, m, margin, n_mol=32000, L=9.86, temps=(280, 300, 330, 360), ns
                 drift = np.abs(e_miss) / (box.n * nst * DT)
 
                 def drift_at(rb):
-                    k = min(int(math.floor(rb / DB + 1e-9)), NBINS - 1)
+                    k = min(int(math.floor(rb / DB + 1e-9)), len(drift) - 1)
                     return float(drift[k])
 
                 xs = [torch.from_numpy(box.xyzq(x)).to(dev) for x in synth.free_flight(box.xyz, vel, DT, nst)]

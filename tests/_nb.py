@@ -52,6 +52,11 @@ def rel_rms(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
 
 
+def max_atom_err(f, fr):
+    """Largest per-particle force error, relative to the RMS reference force."""
+    return float(np.sqrt(((f - fr) ** 2).sum(1)).max() / np.sqrt((fr ** 2).sum(1).mean()))
+
+
 def default_rbb(box, shape, rlist):
     rho = box.n / box.box.prod()
     return max(0.0, rlist - 0.5 * (max(shape) / rho) ** (1 / 3))

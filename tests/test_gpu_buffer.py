@@ -154,8 +154,22 @@ def test_buffer_estimate_learned_mode_and_fallback():
         rb_auto, _, fb_auto = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_AUTO, **q)
         assert fb_auto and rb_auto == rb_a
         mxn.nb_buffer_set_mlp(ctx, m, 0.002)
+        # a model with no recorded training domain answers nothing
+        rb_nd, _, fb_nd = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **q)
+        assert fb_nd and rb_nd == rb_a
+        mxn.nb_mlp_set_domain(m, dt=0.002, charge=[synth.Q_O, synth.Q_H], c6c12=synth.lj_table_spce(), rc=1.0,
+                              beta=3.12, target=0.005)
         rb_m, _, fb_m = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **q)
         assert not fb_m and rb_m == pytest.approx(min(pred + 0.002, rb_a), rel=1e-6)
+        # a looser target keeps the learned answer; a stricter one, another time step, another Ewald accuracy or
+        # other interaction parameters fall back to the analytic bound of that query
+        assert not mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **dict(q, target=0.01))[2]
+        lj2 = synth.lj_table_spce().copy(); lj2[0, 0, 1] *= 1.1
+        for other in (dict(q, target=0.0005), dict(q, dt=0.001), dict(q, beta=2.5), dict(q, charge=[-0.82, 0.41]),
+                      dict(q, c6c12=lj2)):
+            rb_x, _, fb_x = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **other)
+            rb_xa, _, _ = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_ANALYTIC, **other)
+            assert fb_x and rb_x == rb_xa
         q_ood = dict(q, T=400.0)                                          # outside the training range
         rb_o, _, fb_o = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_MLP, **q_ood)
         rb_oa, _, _ = mxn.nb_buffer_estimate(ctx, mode=mxn.NB_BUFFER_ANALYTIC, **q_ood)

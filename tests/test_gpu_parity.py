@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests._nb import F, GpuSystem, default_rbb, rel_rms
+from tests._nb import F, GpuSystem, default_rbb, max_atom_err, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -188,7 +188,7 @@ def _oracle_forces(box, rc, beta, xyz=None, mode="brute"):
                          synth.lj_table_spce(), rc, beta, F, shift=True, mode=mode)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_forces_energies_virial(c1, shape, variant):
     rc, rlist, beta = 0.9, 0.9, 3.47
@@ -209,7 +209,7 @@ def test_forces_energies_virial(c1, shape, variant):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_forces_buffered_after_motion(c1, shape, variant):
     """List built at rlist = rc + 0.1 from step-0 positions, forces at step 9 of ballistic motion (300 K, 2 fs)."""
@@ -241,7 +241,7 @@ def test_accumulate_flag(c1):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 @pytest.mark.parametrize("shape", [(4, 8), (8, 4), (8, 8)])
 def test_forces_reproducible_across_rebuilds(c1, shape, variant):
     """The j-forces of a j-cluster are summed in fixed point, so the forces do not depend on the order in
@@ -269,7 +269,7 @@ def test_forces_reproducible_across_rebuilds(c1, shape, variant):
         s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2], ids=["direct", "compact", "super"])
+@pytest.mark.parametrize("variant", [0, 2], ids=["direct", "super"])
 def test_tiny_and_ragged(ragged, variant):
     """One water in a box; and a ragged 291-atom box, all shapes."""
     one = synth.water_box(1, 2.5, seed=1)
@@ -285,9 +285,11 @@ def test_tiny_and_ragged(ragged, variant):
                 s.close()
 
 
-def test_production_box_sampled():
-    """The 96k-atom, 8x8, rc 1.0 / rlist 1.1 workload the benchmark times: list on sampled i-clusters,
-    forces on sampled atoms, total energy and virial against the cell-list oracle."""
+def test_production_box():
+    """The 96k-atom, 8x8, rc 1.0 / rlist 1.1 workload the benchmark times: the whole cluster-pair list
+    (about a million entries) bit-exact against the oracle's; forces on sampled atoms, and on all atoms
+    with the worst per-particle error bounded too (a missing or extra close pair shows there even where the
+    RMS over 96k atoms would hide it); total energy and virial against the cell-list oracle."""
     box = synth.water_box(32000, 9.86, seed=1306)
     rc, rlist, beta, shape = 1.0, 1.1, 3.12, (8, 8)
     rbb = np.float32(default_rbb(box, shape, rlist))
@@ -295,22 +297,19 @@ def test_production_box_sampled():
     try:
         gpu = s.mxn.nb_list_export_canonical(s.lst)
         g = oracle.grid_sort(box.xyz, box.box, *shape)
-        nci = g["n_slots"] // 8
-        for c0 in (0, nci // 2, nci - 40):
-            ref = oracle.pairlist(g, box.box, np.float32(rlist), rbb, box.excl_off, box.excl_idx, c0, c0 + 40)
-            sel = gpu[(gpu["ci"] >= c0) & (gpu["ci"] < c0 + 40)]
-            _cmp_lists(sel, ref)
+        ref = oracle.pairlist(g, box.box, np.float32(rlist), rbb, box.excl_off, box.excl_idx)
+        assert len(ref) > 900000
+        _cmp_lists(gpu, ref)
         f, e, v = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
-        s.mxn.nb_set_force_variant(s.ctx, s.mxn.NB_FORCE_COMPACT)
-        fd, ed, vd = s.forces(rc, beta, s.mxn.NB_ENERGY | s.mxn.NB_VIRIAL)
-        assert rel_rms(fd, f) <= 1e-6
-        np.testing.assert_allclose(ed, e, rtol=1e-7)
         sub = np.random.default_rng(0).choice(box.n, 3000, replace=False).astype(np.int32)
         fs, _ = oracle.forces_subset(box.xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx,
                                      synth.lj_table_spce(), rc, beta, F, sub)
         assert rel_rms(f[sub], fs) <= 1e-5
         fr, er, vr = _oracle_forces(box, rc, beta, mode="binned")
         assert rel_rms(f, fr) <= 1e-5
+        worst = max_atom_err(f, fr)
+        print("\n[production] force rel RMS %.3e, worst particle %.3e of the RMS force" % (rel_rms(f, fr), worst))
+        assert worst <= 1e-4
         np.testing.assert_allclose(e, er, rtol=1e-5)
         assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
     finally:
@@ -347,6 +346,25 @@ def test_error_paths(c1):
             mxn.nb_sync(s.ctx)
         assert ei.value.status == mxn.NB_ERR_NONFINITE
         mxn.nb_grid_free(g2)
+        # LJ types outside [0, ntypes) are reported at nb_sync, not clamped silently
+        big = s.type.clone()
+        big[7] = 5
+        g3 = mxn.nb_grid_sort(s.ctx, c1.box, s.xyzq, big, (4, 4))
+        l3 = mxn.nb_pairlist_build(s.ctx, g3, 0.9, -1.0, s.eo, s.ei)
+        mxn.nb_forces(s.ctx, g3, l3, s.xyzq, mxn.make_params(0.9, 3.47, F, s.lj), 0, f)
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_sync(s.ctx)
+        assert ei.value.status == mxn.NB_ERR_ARG
+        neg = s.type.clone()
+        neg[3] = -1
+        g4 = mxn.nb_grid_sort(s.ctx, c1.box, s.xyzq, neg, (4, 4))
+        with pytest.raises(mxn.NbError) as ei:
+            mxn.nb_sync(s.ctx)
+        assert ei.value.status == mxn.NB_ERR_ARG
+        mxn.nb_sync(s.ctx)
+        mxn.nb_list_free(l3)
+        mxn.nb_grid_free(g3)
+        mxn.nb_grid_free(g4)
         # a list built before the grid's last sort is rejected
         s.grid = mxn.nb_grid_sort(s.ctx, c1.box, s.xyzq, s.type, (4, 4), s.grid)
         with pytest.raises(mxn.NbError) as ei:
