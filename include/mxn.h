@@ -90,10 +90,39 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 
+/* Device memory for the library's handles, supplied by the caller (for
+ * example PyTorch's caching allocator, so that one pool backs the caller's
+ * tensors and the library's grids, lists and scratch).
+ *   alloc(bytes, stream, user)  returns device memory on the context's device
+ *                               usable in stream order on `stream` (the
+ *                               context's stream at the time), or NULL when
+ *                               out of memory (the call then fails with
+ *                               NB_ERR_OOM)
+ *   free(ptr, stream, user)     takes back a block, with the stream it was
+ *                               allocated on; work the library enqueued on
+ *                               that stream may still use it (stream order)
+ * Blocks are requested when a handle grows (the first grid sort, list build
+ * or force call of a size, nb_batch_create, nb_mlp_create, ...) and returned
+ * when it is freed or grows again; never inside a captured graph.  After
+ * nb_set_stream, synchronise the old stream before freeing handles whose
+ * blocks came from it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} nb_allocator;
+
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the null stream).  *ctx receives the handle. */
-int nb_create(nb_ctx **ctx, int device, void *hip_stream);
+ * (a hipStream_t; NULL = the null stream).  *ctx receives the handle.
+ *   allocator  HOST, copied: device memory of every handle of this context
+ *              (and of the context itself) comes from it; NULL: hipMalloc.
+ * Handles must be freed before their context (nb_destroy). */
+int nb_create(nb_ctx **ctx, int device, void *hip_stream, const nb_allocator *allocator);
 void nb_destroy(nb_ctx *ctx);
+/* Live device bytes held by this context and its handles: through the
+ * caller's allocator and through hipMalloc (zero when an allocator was
+ * given).  HOST outputs; either may be NULL. */
+int nb_memory_info(const nb_ctx *ctx, size_t *via_allocator, size_t *via_hip);
 /* Change the stream subsequent calls enqueue on. */
 int nb_set_stream(nb_ctx *ctx, void *hip_stream);
 /* Wait for the stream; return the first latched kernel error (and clear it). */
@@ -378,6 +407,41 @@ int nb_batch_bind_topology(nb_batch *batch, const int *const *type, const int *c
 int nb_batch_rebuild(nb_ctx *ctx, nb_batch *batch);
 int nb_batch_capture_cycle(nb_ctx *ctx, nb_batch *batch, int nsteps, const nb_params *p, unsigned flags,
                            double *energy, double *virial);
+
+/*
+ * Autotuner for batched replicas.  The paper chooses the cluster shape M x N
+ * to fit the SIMD width and the cost of the hardware (Sec. 2.2, Sec. 3.1); here
+ * the fastest (shape, work items per workgroup) pair for a given set of
+ * replicas is measured.  For each candidate shape every replica is grid-sorted
+ * and its list built at rlist (rbb default), the lists are bound to one batch
+ * (search unsplit, as nb_batch_bind_topology) and, for each candidate group,
+ * the batched force launch (nb_batch_forces with `flags`) is run twice
+ * untimed and `reps` times between HIP events on the context's stream.
+ * Synchronous; every grid, list, batch and buffer it made is freed again.
+ *   r          replicas: box edges (HOST double[3 n_rep]), particle counts
+ *              (HOST int[n_rep]) and, per replica, DEVICE pointers to
+ *              positions/charges, types and the exclusion CSR (HOST arrays of
+ *              n_rep pointers, as for nb_grid_sort and nb_pairlist_build)
+ *   rlist      list radius; every replica box edge must exceed 2 rlist
+ *   p, flags   interaction parameters and NB_ENERGY / NB_VIRIAL, as timed
+ *   shapes, n_shapes, groups, n_groups   candidates (groups: 1, 2, 4 or 8)
+ *   reps       timed launches per candidate (>= 1)
+ *   best, best_group  HOST outputs: the fastest candidate
+ *   ms_table   HOST float[n_shapes * n_groups] (may be NULL): mean ms per
+ *              launch, row = shape, column = group
+ */
+typedef struct {
+    int n_rep;
+    const double *box;
+    const int *n;
+    const float *const *xyzq;
+    const int *const *type;
+    const int *const *excl_off;
+    const int *const *excl_idx;
+} nb_replicas;
+int nb_autotune(nb_ctx *ctx, const nb_replicas *r, float rlist, const nb_params *p, unsigned flags,
+                const nb_shape *shapes, int n_shapes, const int *groups, int n_groups, int reps, nb_shape *best,
+                int *best_group, float *ms_table);
 
 /* ---------------------------------------------------------- exact recount */
 

@@ -26,7 +26,7 @@ NB_BUFFER_ANALYTIC, NB_BUFFER_MLP, NB_BUFFER_AUTO = 0, 1, 2
 
 # symbols declared in include/mxn.h (checked by the ABI test)
 EXPORTS = [
-    "nb_create", "nb_destroy", "nb_set_stream", "nb_sync", "nb_last_error",
+    "nb_create", "nb_destroy", "nb_memory_info", "nb_set_stream", "nb_sync", "nb_last_error",
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_pairlist_prune", "nb_rdf", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
     "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
@@ -34,7 +34,7 @@ EXPORTS = [
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp", "nb_mlp_set_domain",
     "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
-    "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle",
+    "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle", "nb_autotune",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
 NB_FORCE_DIRECT, NB_FORCE_SUPER = 0, 2
@@ -50,6 +50,14 @@ class NbError(RuntimeError):
         self.status = status
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class nb_allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class nb_shape(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int)]
 
@@ -58,6 +66,11 @@ class nb_params(ctypes.Structure):
     _fields_ = [("rc", ctypes.c_float), ("beta", ctypes.c_float), ("coulomb_f", ctypes.c_float),
                 ("ntypes", ctypes.c_int), ("c6c12", ctypes.c_void_p), ("shift_energies", ctypes.c_int),
                 ("coulomb", ctypes.c_int), ("eps_rf", ctypes.c_float)]
+
+
+class nb_replicas(ctypes.Structure):
+    _fields_ = [("n_rep", ctypes.c_int), ("box", ctypes.c_void_p), ("n", ctypes.c_void_p), ("xyzq", ctypes.c_void_p),
+                ("type", ctypes.c_void_p), ("excl_off", ctypes.c_void_p), ("excl_idx", ctypes.c_void_p)]
 
 
 class nb_grid_info_t(ctypes.Structure):
@@ -94,7 +107,9 @@ def lib():
             ctypes.c_double, ctypes.c_uint
         pvp = ctypes.POINTER(ctypes.c_void_p)
         sig = {
-            "nb_create": ([pvp, i, vp], i), "nb_destroy": ([vp], None), "nb_set_stream": ([vp, vp], i),
+            "nb_create": ([pvp, i, vp, ctypes.POINTER(nb_allocator)], i), "nb_destroy": ([vp], None),
+            "nb_set_stream": ([vp, vp], i), "nb_memory_info": ([vp, ctypes.POINTER(ctypes.c_size_t),
+                                                               ctypes.POINTER(ctypes.c_size_t)], i),
             "nb_sync": ([vp], i), "nb_last_error": ([], ctypes.c_char_p),
             "nb_grid_sort": ([vp, vp, i, vp, vp, nb_shape, pvp], i), "nb_grid_free": ([vp], None),
             "nb_grid_info": ([vp, ctypes.POINTER(nb_grid_info_t)], i),
@@ -122,6 +137,8 @@ def lib():
             "nb_batch_replay": ([vp, vp], i),
             "nb_batch_bind_topology": ([vp, vp, vp, vp], i), "nb_batch_rebuild": ([vp, vp], i),
             "nb_batch_capture_cycle": ([vp, vp, i, ctypes.POINTER(nb_params), u, vp, vp], i),
+            "nb_autotune": ([vp, ctypes.POINTER(nb_replicas), f, ctypes.POINTER(nb_params), u, vp, i, vp, i, i,
+                             ctypes.POINTER(nb_shape), ctypes.POINTER(ctypes.c_int), vp], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -165,14 +182,50 @@ def _need(t, dtype, numel, name):
 
 # ---------------------------------------------------------------- context
 
-def nb_create(device=0, stream=None):
+_allocators = {}   # context address -> the nb_allocator (and its callbacks) it was created with
+
+
+def torch_allocator(device=0):
+    """An nb_allocator backed by PyTorch's caching allocator: the library's grids, lists and scratch come from
+    the same pool as the caller's tensors (allocation on the library's stream, stream-ordered reuse)."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=int(stream or 0))
+        except RuntimeError:   # out of memory: the library reports NB_ERR_OOM
+            return None
+
+    def _free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return nb_allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+
+
+def nb_create(device=0, stream=None, allocator="torch"):
+    """allocator: "torch" (PyTorch's caching allocator, the default), an nb_allocator, or None (hipMalloc)."""
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be 'torch', an nb_allocator or None")
+        allocator = torch_allocator(device)
     h = ctypes.c_void_p()
-    _check(lib().nb_create(ctypes.byref(h), int(device), _stream(stream)))
+    _check(lib().nb_create(ctypes.byref(h), int(device), _stream(stream),
+                           ctypes.byref(allocator) if allocator is not None else None))
+    if allocator is not None:
+        _allocators[h.value] = allocator
     return h
 
 
 def nb_destroy(ctx):
     lib().nb_destroy(ctx)
+    _allocators.pop(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx, None)
+
+
+def nb_memory_info(ctx):
+    """(bytes held through the caller's allocator, bytes held through hipMalloc) by the context's handles."""
+    a, h = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().nb_memory_info(ctx, ctypes.byref(a), ctypes.byref(h)))
+    return a.value, h.value
 
 
 def nb_set_stream(ctx, stream=None):
@@ -464,3 +517,25 @@ def nb_batch_rebuild(ctx, batch):
 def nb_batch_capture_cycle(ctx, batch, nsteps, params, flags, energy=None, virial=None):
     _check(lib().nb_batch_capture_cycle(ctx, batch, int(nsteps), ctypes.byref(params), int(flags), _ptr(energy),
                                         _ptr(virial)))
+
+
+# -------------------------------------------------------------- autotuner
+
+def nb_autotune(ctx, boxes, xyzq, types, excl_off, excl_idx, rlist, params, flags, shapes, groups, reps=5):
+    """Fastest (shape, group) of the batched force launch over the replicas, measured by the library.
+
+    boxes: (n_rep, 3) box edges; xyzq, types, excl_off, excl_idx: per-replica CUDA tensors.  Returns
+    ((m, n), group, table) with table[shape, group] the mean milliseconds per batched launch."""
+    import numpy as np
+    nr = len(xyzq)
+    box = np.ascontiguousarray(np.asarray(boxes, np.float64).reshape(nr, 3))
+    n = np.ascontiguousarray([t.shape[0] for t in xyzq], np.int32)
+    arrs = [(ctypes.c_void_p * nr)(*[t.data_ptr() for t in ts]) for ts in (xyzq, types, excl_off, excl_idx)]
+    rep = nb_replicas(nr, box.ctypes.data, n.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) for a in arrs])
+    shp = (nb_shape * len(shapes))(*[nb_shape(*sh) for sh in shapes])
+    grp = (ctypes.c_int * len(groups))(*[int(g) for g in groups])
+    best, bg = nb_shape(), ctypes.c_int()
+    table = np.zeros(len(shapes) * len(groups), np.float32)
+    _check(lib().nb_autotune(ctx, ctypes.byref(rep), float(rlist), ctypes.byref(params), int(flags), shp, len(shapes),
+                             grp, len(groups), int(reps), ctypes.byref(best), ctypes.byref(bg), _ptr(table)))
+    return (best.m, best.n), bg.value, table.reshape(len(shapes), len(groups))

@@ -1,19 +1,18 @@
 """Autotuner for batched replicas: cluster shape x work items per workgroup.
 
-For a set of replica boxes it builds the grids and lists of every candidate
-cluster shape (4x4, 4x8, 8x4, 8x8; the paper tunes M and N to the hardware,
-Sec. 2.2 and 3.1), binds them to one batch and times the batched force
-launch with 1, 2, 4 and 8 work items (wavefronts) per workgroup.  The fastest pair is
-cached in a JSON file keyed by device, number of replicas, total size
-(rounded to a power of two) and the cut-offs.  Timing uses wall-clock around
-synchronised repetitions; every kernel runs in the library.
+The measurement is the library's nb_autotune: for a set of replica boxes it
+builds the grids and lists of every candidate cluster shape (4x4, 4x8, 8x4,
+8x8; the paper tunes M and N to the hardware, Sec. 2.2 and 3.1), binds them
+to one batch and times the batched force launch with 1, 2, 4 and 8 work
+items (wavefronts) per workgroup with HIP events.  This module keeps the
+results in a JSON cache keyed by device, number of replicas, total size
+(rounded to a power of two) and the cut-offs.
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-import time
 
 import numpy as np
 
@@ -52,17 +51,6 @@ def free_replicas(reps):
         mxn.nb_grid_free(r["grid"])
 
 
-def time_batch(ctx, batch, params, energy, reps=5, warmup=2):
-    for _ in range(warmup):
-        mxn.nb_batch_forces(ctx, batch, params, mxn.NB_ENERGY, energy)
-    mxn.nb_sync(ctx)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        mxn.nb_batch_forces(ctx, batch, params, mxn.NB_ENERGY, energy)
-    mxn.nb_sync(ctx)
-    return (time.perf_counter() - t0) * 1e3 / reps
-
-
 def tune_batch(ctx, boxes, rc, rlist, beta, reps=5, cache=DEFAULT_CACHE, shapes=SHAPES, groups=GROUPS):
     """Best (shape, group) for the batch, from the cache or by measurement."""
     import torch
@@ -78,17 +66,12 @@ def tune_batch(ctx, boxes, rc, rlist, beta, reps=5, cache=DEFAULT_CACHE, shapes=
     dev = torch.device("cuda:0")
     lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
     params = mxn.make_params(rc, beta, synth.COULOMB_F, lj)
-    energy = torch.zeros(2 * len(boxes), dtype=torch.float64, device=dev)
-    table = []
-    for shape in shapes:
-        rs = build_replicas(ctx, boxes, shape, rlist)
-        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in rs], [r["lst"] for r in rs], [r["xyzq"] for r in rs],
-                                    [r["f"] for r in rs])
-        for g in groups:
-            mxn.nb_batch_set_group(batch, g)
-            table.append(dict(shape=list(shape), group=g, ms=time_batch(ctx, batch, params, energy, reps)))
-        mxn.nb_batch_free(batch)
-        free_replicas(rs)
+    up = [(torch.from_numpy(b.xyzq()).to(dev), torch.from_numpy(b.type).to(dev),
+           torch.from_numpy(b.excl_off).to(dev), torch.from_numpy(b.excl_idx).to(dev)) for b in boxes]
+    _, _, ms = mxn.nb_autotune(ctx, [b.box for b in boxes], *[[u[k] for u in up] for k in range(4)], rlist, params,
+                               mxn.NB_ENERGY, shapes, groups, reps)
+    table = [dict(shape=list(sh), group=g, ms=float(ms[i, j])) for i, sh in enumerate(shapes)
+             for j, g in enumerate(groups)]
     best = min(table, key=lambda row: row["ms"])
     res = dict(key=key, shape=best["shape"], group=best["group"], ms=best["ms"], table=table, cached=False)
     if cache:

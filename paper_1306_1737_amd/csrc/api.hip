@@ -20,25 +20,48 @@ int fail(int status, const std::string &msg) {
     return status;
 }
 
-int ensure(DevBuf &b, size_t bytes) {
+int ensure(const nb_ctx *c, DevBuf &b, size_t bytes) {
     if (bytes <= b.bytes && b.p) return NB_OK;
-    if (b.p) hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-    size_t want = bytes ? bytes : 16;
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        return fail(NB_ERR_OOM, std::string("hipMalloc of ") + std::to_string(want) + " bytes: " + hipGetErrorString(e));
+    if (!c) return fail(NB_ERR_STATE, "internal: device buffer without a context");
+    release(b);
+    const size_t want = bytes ? (bytes + 255) / 256 * 256 : 256;
+    if (c->alloc.alloc) {
+        void *p = c->alloc.alloc(want, (void *)c->stream, c->alloc.user);
+        if (!p)
+            return fail(NB_ERR_OOM, std::string("the caller's allocator returned no memory for ") + std::to_string(want) +
+                                        " bytes");
+        b.p = p;
+        b.al = c->alloc;
+        b.stream = (void *)c->stream;
+        c->mem->via_allocator += want;
+    } else {
+        hipError_t e = hipMalloc(&b.p, want);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return fail(NB_ERR_OOM, std::string("hipMalloc of ") + std::to_string(want) + " bytes: " + hipGetErrorString(e));
+        }
+        b.al = nb_allocator{};
+        b.stream = nullptr;
+        c->mem->via_hip += want;
     }
     b.bytes = want;
+    b.mem = c->mem;
     return NB_OK;
 }
 
 void release(DevBuf &b) {
-    if (b.p) hipFree(b.p);
+    if (b.p) {
+        if (b.al.free) {
+            b.al.free(b.p, b.stream, b.al.user);
+            if (b.mem) b.mem->via_allocator -= b.bytes;
+        } else {
+            hipFree(b.p);
+            if (b.mem) b.mem->via_hip -= b.bytes;
+        }
+    }
     b.p = nullptr;
     b.bytes = 0;
+    b.mem.reset();
 }
 
 static hipEvent_t take_event(nb_ctx *c) {
@@ -86,8 +109,10 @@ extern "C" {
 
 const char *nb_last_error(void) { return g_last_error.c_str(); }
 
-int nb_create(nb_ctx **ctx, int device, void *hip_stream) {
+int nb_create(nb_ctx **ctx, int device, void *hip_stream, const nb_allocator *allocator) {
     if (!ctx) return fail(NB_ERR_ARG, "nb_create: ctx is null");
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(NB_ERR_ARG, "nb_create: an allocator needs both alloc and free");
     *ctx = nullptr;
     int ndev = 0;
     MXN_HIP(hipGetDeviceCount(&ndev));
@@ -97,11 +122,18 @@ int nb_create(nb_ctx **ctx, int device, void *hip_stream) {
     if (!c) return fail(NB_ERR_OOM, "nb_create: host allocation");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    hipError_t e = hipMalloc(&c->d_flags, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int));
+    if (allocator) c->alloc = *allocator;
+    int rc = ensure(c, c->flags_buf, sizeof(int));
+    if (rc != NB_OK) {
+        delete c;
+        return rc;
+    }
+    c->d_flags = (int *)c->flags_buf.p;
+    hipError_t e = hipMemsetAsync(c->d_flags, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_pinned, 16 * sizeof(int));
     if (e != hipSuccess) {
-        if (c->d_flags) hipFree(c->d_flags);
+        release(c->flags_buf);
         delete c;
         return fail(NB_ERR_HIP, std::string("nb_create: ") + hipGetErrorString(e));
     }
@@ -123,9 +155,18 @@ void nb_destroy(nb_ctx *c) {
     release(c->blockpart);
     release(c->etab);
     release(c->rdf_edge);
-    if (c->d_flags) hipFree(c->d_flags);
+    release(c->mlp_io);
+    release(c->stats_buf);
+    release(c->flags_buf);
     if (c->h_pinned) hipHostFree(c->h_pinned);
     delete c;
+}
+
+int nb_memory_info(const nb_ctx *c, size_t *via_allocator, size_t *via_hip) {
+    if (!c) return fail(NB_ERR_ARG, "nb_memory_info: ctx is null");
+    if (via_allocator) *via_allocator = c->mem->via_allocator.load();
+    if (via_hip) *via_hip = c->mem->via_hip.load();
+    return NB_OK;
 }
 
 int nb_set_stream(nb_ctx *c, void *hip_stream) {
@@ -208,29 +249,29 @@ int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const
     g->slots_cap = (int)cap;
     const size_t nc = (size_t)g->ncol, ns = (size_t)cap, na = (size_t)n;
     int rc = NB_OK;
-    rc = rc ? rc : ensure(g->col_count, nc * 4);
-    rc = rc ? rc : ensure(g->col_start, (nc + 1) * 4);
-    rc = rc ? rc : ensure(g->col_fill, nc * 4);
-    rc = rc ? rc : ensure(g->col_hist, nc * (size_t)hist_blocks(n) * 4);
-    rc = rc ? rc : ensure(g->colbb, nc * 16);
-    rc = rc ? rc : ensure(g->atom_col, na * 4);
-    rc = rc ? rc : ensure(g->atom_xw, na * 16);
-    rc = rc ? rc : ensure(g->atom_img, na * 4);
-    rc = rc ? rc : ensure(g->slot_of, na * 4);
-    rc = rc ? rc : ensure(g->bucket, ns * 4);
-    rc = rc ? rc : ensure(g->xs, ns * 16);
-    rc = rc ? rc : ensure(g->xs_now, ns * 16);
-    rc = rc ? rc : ensure(g->type_s, ns * 4);
-    rc = rc ? rc : ensure(g->perm, ns * 4);
-    rc = rc ? rc : ensure(g->img_s, ns * 4);
-    rc = rc ? rc : ensure(g->bbi_lo, ns / g->m * 16);
-    rc = rc ? rc : ensure(g->bbi_hi, ns / g->m * 16);
+    rc = rc ? rc : ensure(g->ctx, g->col_count, nc * 4);
+    rc = rc ? rc : ensure(g->ctx, g->col_start, (nc + 1) * 4);
+    rc = rc ? rc : ensure(g->ctx, g->col_fill, nc * 4);
+    rc = rc ? rc : ensure(g->ctx, g->col_hist, nc * (size_t)hist_blocks(n) * 4);
+    rc = rc ? rc : ensure(g->ctx, g->colbb, nc * 16);
+    rc = rc ? rc : ensure(g->ctx, g->atom_col, na * 4);
+    rc = rc ? rc : ensure(g->ctx, g->atom_xw, na * 16);
+    rc = rc ? rc : ensure(g->ctx, g->atom_img, na * 4);
+    rc = rc ? rc : ensure(g->ctx, g->slot_of, na * 4);
+    rc = rc ? rc : ensure(g->ctx, g->bucket, ns * 4);
+    rc = rc ? rc : ensure(g->ctx, g->xs, ns * 16);
+    rc = rc ? rc : ensure(g->ctx, g->xs_now, ns * 16);
+    rc = rc ? rc : ensure(g->ctx, g->type_s, ns * 4);
+    rc = rc ? rc : ensure(g->ctx, g->perm, ns * 4);
+    rc = rc ? rc : ensure(g->ctx, g->img_s, ns * 4);
+    rc = rc ? rc : ensure(g->ctx, g->bbi_lo, ns / g->m * 16);
+    rc = rc ? rc : ensure(g->ctx, g->bbi_hi, ns / g->m * 16);
     if (g->nn != g->m) {
-        rc = rc ? rc : ensure(g->bbj_lo, ns / g->nn * 16);
-        rc = rc ? rc : ensure(g->bbj_hi, ns / g->nn * 16);
+        rc = rc ? rc : ensure(g->ctx, g->bbj_lo, ns / g->nn * 16);
+        rc = rc ? rc : ensure(g->ctx, g->bbj_hi, ns / g->nn * 16);
     }
-    rc = rc ? rc : ensure(g->nslots, 16);
-    rc = rc ? rc : ensure(g->shiftvec, 32 * 16);
+    rc = rc ? rc : ensure(g->ctx, g->nslots, 16);
+    rc = rc ? rc : ensure(g->ctx, g->shiftvec, 32 * 16);
     if (rc == NB_OK) {
         ScopedTimer tm(c, NB_TIMER_GRID_SORT);
         rc = launch_grid_sort(g, xyzq, type);
@@ -351,10 +392,10 @@ int nb_pairlist_build(nb_ctx *c, const nb_grid *g, float rlist, float rbb, const
     const int nci_cap = g->slots_cap / g->m;
     int rc = NB_OK;
     const size_t nreg = (size_t)nci_cap * kMaxSearchParts + 1;
-    rc = rc ? rc : ensure(l->part_count, nreg * 4);
-    rc = rc ? rc : ensure(l->part_start, nreg * 4);
-    rc = rc ? rc : ensure(l->part_istart, nreg * 4);
-    rc = rc ? rc : ensure(l->totals, 16);
+    rc = rc ? rc : ensure(l->ctx, l->part_count, nreg * 4);
+    rc = rc ? rc : ensure(l->ctx, l->part_start, nreg * 4);
+    rc = rc ? rc : ensure(l->ctx, l->part_istart, nreg * 4);
+    rc = rc ? rc : ensure(l->ctx, l->totals, 16);
     // entry and item capacities are set by the reserving (synchronous) build
     if (rc == NB_OK) {
         ScopedTimer tm(c, NB_TIMER_PAIRLIST);
@@ -562,14 +603,13 @@ int nb_list_stats(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xy
         return fail(NB_ERR_STATE, "nb_list_stats: grid/list/context mismatch");
     if (!(rc > 0.0f)) return fail(NB_ERR_ARG, "nb_list_stats: rc must be > 0");
     MXN_HIP(hipSetDevice(c->device));
-    unsigned long long *d = nullptr;
-    MXN_HIP(hipMalloc(&d, 4 * sizeof(unsigned long long)));
+    CHECK(ensure(c, c->stats_buf, 4 * sizeof(unsigned long long)));
+    unsigned long long *d = (unsigned long long *)c->stats_buf.p;
     hipError_t e = hipMemsetAsync(d, 0, 4 * sizeof(unsigned long long), c->stream);
     int rc_ = e == hipSuccess ? launch_stats(c, g, l, xyzq_now, rc, d) : NB_ERR_HIP;
     unsigned long long h[4] = {0, 0, 0, 0};
     if (rc_ == NB_OK) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    hipFree(d);
     if (rc_ != NB_OK) return rc_;
     if (e != hipSuccess) return fail(NB_ERR_HIP, hipGetErrorString(e));
     long ne = 0;
@@ -641,11 +681,11 @@ static int batch_refresh(nb_batch *b, const float *const *xyzq_now, float *const
     }
     if (!changed) return NB_OK;
     if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch: replica storage changed since capture: capture again");
-    CHECK(ensure(b->desc, ds * b->n_rep));
-    CHECK(ensure(b->slot_off, sizeof(long) * (b->n_rep + 1)));
-    CHECK(ensure(b->atom_off, sizeof(long) * (b->n_rep + 1)));
-    CHECK(ensure(b->item_off, sizeof(long) * (b->n_rep + 1)));
-    CHECK(ensure(b->partials, sizeof(double) * 11 * (size_t)pb));
+    CHECK(ensure(b->ctx, b->desc, ds * b->n_rep));
+    CHECK(ensure(b->ctx, b->slot_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->ctx, b->atom_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->ctx, b->item_off, sizeof(long) * (b->n_rep + 1)));
+    CHECK(ensure(b->ctx, b->partials, sizeof(double) * 11 * (size_t)pb));
     MXN_HIP(hipMemcpy(b->desc.p, host.data(), ds * b->n_rep, hipMemcpyHostToDevice));
     b->desc_host = host;
     MXN_HIP(hipMemcpy(b->slot_off.p, so.data(), sizeof(long) * (b->n_rep + 1), hipMemcpyHostToDevice));
@@ -849,11 +889,11 @@ static int rebuild_refresh(nb_batch *b) {
     for (int k = 0; k < LS; ++k) loff[k * (n + 1) + n] = ltot[k];
     if (gj == b->gjobs_host && lj == b->ljobs_host && gtot == b->gtotal && ltot == b->ltotal) return NB_OK;
     if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch: replica storage changed since capture: capture again");
-    CHECK(ensure(b->gjobs, gj.size()));
-    CHECK(ensure(b->ljobs, lj.size()));
-    CHECK(ensure(b->goff, goff.size() * sizeof(int)));
-    CHECK(ensure(b->loff, loff.size() * sizeof(int)));
-    CHECK(ensure(b->scans, sj.size() * sizeof(ScanJob)));
+    CHECK(ensure(b->ctx, b->gjobs, gj.size()));
+    CHECK(ensure(b->ctx, b->ljobs, lj.size()));
+    CHECK(ensure(b->ctx, b->goff, goff.size() * sizeof(int)));
+    CHECK(ensure(b->ctx, b->loff, loff.size() * sizeof(int)));
+    CHECK(ensure(b->ctx, b->scans, sj.size() * sizeof(ScanJob)));
     MXN_HIP(hipMemcpy(b->gjobs.p, gj.data(), gj.size(), hipMemcpyHostToDevice));
     MXN_HIP(hipMemcpy(b->ljobs.p, lj.data(), lj.size(), hipMemcpyHostToDevice));
     MXN_HIP(hipMemcpy(b->goff.p, goff.data(), goff.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -892,6 +932,82 @@ int nb_batch_rebuild(nb_ctx *c, nb_batch *b) {
     MXN_HIP(hipSetDevice(c->device));
     CHECK(rebuild_refresh(b));
     return launch_rebuild(c, b);
+}
+
+// ------------------------------------------------------------- autotuner
+
+// Times the batched force launch of the replicas for every (shape, work
+// items per workgroup) candidate: each shape gets its own grids and lists
+// (bound to one batch with the search unsplit, as in a batched cycle), each
+// group two untimed launches and `reps` launches between HIP events on the
+// context's stream.  Everything is freed again before returning.
+int nb_autotune(nb_ctx *c, const nb_replicas *r, float rlist, const nb_params *p, unsigned flags,
+                const nb_shape *shapes, int n_shapes, const int *groups, int n_groups, int reps, nb_shape *best,
+                int *best_group, float *ms_table) {
+    if (!c || !r || !p || !shapes || !groups || !best || !best_group) return fail(NB_ERR_ARG, "nb_autotune: null argument");
+    if (r->n_rep < 1 || !r->box || !r->n || !r->xyzq || !r->type || !r->excl_off || !r->excl_idx)
+        return fail(NB_ERR_ARG, "nb_autotune: incomplete replica description");
+    if (n_shapes < 1 || n_groups < 1 || reps < 1) return fail(NB_ERR_ARG, "nb_autotune: need candidates and reps >= 1");
+    if (flags & ~(unsigned)(NB_ENERGY | NB_VIRIAL)) return fail(NB_ERR_ARG, "nb_autotune: flags: NB_ENERGY, NB_VIRIAL");
+    MXN_HIP(hipSetDevice(c->device));
+    const int nr = r->n_rep;
+    long atoms = 0;
+    for (int k = 0; k < nr; ++k) {
+        if (r->n[k] < 1 || !r->xyzq[k] || !r->type[k] || !r->excl_off[k] || !r->excl_idx[k])
+            return fail(NB_ERR_ARG, "nb_autotune: bad replica " + std::to_string(k));
+        atoms += r->n[k];
+    }
+    DevBuf fbuf, ebuf;
+    int rc = ensure(c, fbuf, (size_t)atoms * 3 * sizeof(float));
+    rc = rc ? rc : ensure(c, ebuf, (size_t)nr * 11 * sizeof(double));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (rc == NB_OK && (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess))
+        rc = fail(NB_ERR_HIP, "nb_autotune: event creation");
+    std::vector<float *> fptr(nr);
+    for (long k = 0, off = 0; k < nr; off += 3L * r->n[k], ++k) fptr[k] = (float *)fbuf.p + off;
+    double *energy = (double *)ebuf.p, *virial = energy + 2 * nr;
+    float best_ms = INFINITY;
+    for (int si = 0; si < n_shapes && rc == NB_OK; ++si) {
+        std::vector<nb_grid *> gr(nr, nullptr);
+        std::vector<nb_list *> li(nr, nullptr);
+        nb_batch *b = nullptr;
+        for (int k = 0; k < nr && rc == NB_OK; ++k) {
+            rc = nb_grid_sort(c, r->box + 3 * k, r->n[k], r->xyzq[k], r->type[k], shapes[si], &gr[k]);
+            rc = rc ? rc : nb_pairlist_build(c, gr[k], rlist, -1.0f, r->excl_off[k], r->excl_idx[k], 0, &li[k]);
+        }
+        rc = rc ? rc : nb_batch_create(c, nr, gr.data(), li.data(), r->xyzq, fptr.data(), &b);
+        rc = rc ? rc : nb_batch_bind_topology(b, r->type, r->excl_off, r->excl_idx);
+        for (int gi = 0; gi < n_groups && rc == NB_OK; ++gi) {
+            rc = nb_batch_set_group(b, groups[gi]);
+            for (int w = 0; w < 2 && rc == NB_OK; ++w) rc = nb_batch_forces(c, b, p, flags, energy, virial);
+            if (rc == NB_OK && hipEventRecord(ev0, c->stream) != hipSuccess) rc = fail(NB_ERR_HIP, "nb_autotune: event");
+            for (int w = 0; w < reps && rc == NB_OK; ++w) rc = nb_batch_forces(c, b, p, flags, energy, virial);
+            if (rc == NB_OK && hipEventRecord(ev1, c->stream) != hipSuccess) rc = fail(NB_ERR_HIP, "nb_autotune: event");
+            rc = rc ? rc : nb_sync(c);
+            float ms = 0.0f;
+            if (rc == NB_OK && hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) rc = fail(NB_ERR_HIP, "nb_autotune: timing");
+            if (rc == NB_OK) {
+                ms /= (float)reps;
+                if (ms_table) ms_table[si * n_groups + gi] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    *best = shapes[si];
+                    *best_group = groups[gi];
+                }
+            }
+        }
+        if (b) nb_batch_free(b);
+        for (int k = 0; k < nr; ++k) {
+            if (li[k]) nb_list_free(li[k]);
+            if (gr[k]) nb_grid_free(gr[k]);
+        }
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    hipStreamSynchronize(c->stream);
+    release(fbuf);
+    release(ebuf);
+    return rc;
 }
 
 int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *p, unsigned flags, double *energy,
@@ -974,12 +1090,12 @@ int nb_mlp_create(nb_ctx *c, const float *params, const double lo[8], const doub
         lof[i] = (float)lo[i];
         hif[i] = (float)hi[i];
     }
-    int rc = ensure(m->params, kMlpParams * 4);
-    rc = rc ? rc : ensure(m->m, kMlpParams * 4);
-    rc = rc ? rc : ensure(m->v, kMlpParams * 4);
-    rc = rc ? rc : ensure(m->step, 16);
-    rc = rc ? rc : ensure(m->lo, 32);
-    rc = rc ? rc : ensure(m->hi, 32);
+    int rc = ensure(m->ctx, m->params, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->ctx, m->m, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->ctx, m->v, kMlpParams * 4);
+    rc = rc ? rc : ensure(m->ctx, m->step, 16);
+    rc = rc ? rc : ensure(m->ctx, m->lo, 32);
+    rc = rc ? rc : ensure(m->ctx, m->hi, 32);
     hipError_t e = hipSuccess;
     if (rc == NB_OK) {
         e = hipMemcpy(m->params.p, params, kMlpParams * 4, hipMemcpyHostToDevice);
@@ -1131,7 +1247,7 @@ int nb_buffer_estimate(nb_ctx *c, const nb_buffer_query *q, int mode, double *rb
                 if (!(f[i] >= c->mlp->lo_h[i] && f[i] <= c->mlp->hi_h[i])) in_range = false;   // outside training data
         if (in_range) {
             MXN_HIP(hipSetDevice(c->device));
-            CHECK(ensure(c->mlp_io, 64));
+            CHECK(ensure(c, c->mlp_io, 64));
             float y = NAN;
             MXN_HIP(hipMemcpyAsync(c->mlp_io.p, f, sizeof f, hipMemcpyHostToDevice, c->stream));
             CHECK(launch_mlp_infer(c, c->mlp, (const float *)c->mlp_io.p, 1, (float *)c->mlp_io.p + 8));

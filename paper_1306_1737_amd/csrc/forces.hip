@@ -1171,7 +1171,7 @@ static int ensure_ewald_table(nb_ctx *ctx, float beta, float rc, int *ntab) {
         }
         h[(size_t)i] = make_float2((float)G, (float)H);
     }
-    int rc_ = ensure(ctx->etab, (size_t)n * sizeof(float2));
+    int rc_ = ensure(ctx, ctx->etab, (size_t)n * sizeof(float2));
     if (rc_) return rc_;
     MXN_HIP(hipMemcpyAsync(ctx->etab.p, h.data(), (size_t)n * sizeof(float2), hipMemcpyHostToDevice, ctx->stream));
     MXN_HIP(hipStreamSynchronize(ctx->stream));   // h is released on return
@@ -1208,7 +1208,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     }
     const long cap_items = S ? l->sci_cap_items : l->cap_items;
     if (need_acc) {
-        int rc = ensure(ctx->partials, (size_t)(cap_items + 4) * kNAcc * sizeof(double));
+        int rc = ensure(ctx, ctx->partials, (size_t)(cap_items + 4) * kNAcc * sizeof(double));
         if (rc) return rc;
     }
     const long pstride = cap_items + 4;
@@ -1273,7 +1273,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     // fold launch: one wavefront per j-cluster; with energies it also reduces the partials
     const int nfold = (g->slots_cap / g->nn + 3) / 4;
     if (need_acc) {
-        int rc = ensure(ctx->blockpart, (size_t)kReduceParts * kNAcc * sizeof(double));
+        int rc = ensure(ctx, ctx->blockpart, (size_t)kReduceParts * kNAcc * sizeof(double));
         if (rc) return rc;
         a.blockpart = (double *)ctx->blockpart.p;
         a.energy = energy;

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -37,11 +39,22 @@ inline int hist_blocks(int n) { return n < 1 ? 1 : (n + kHistAtoms - 1) / kHistA
 constexpr int kMaxSearchParts = 8;   // wavefronts that may share the pair search of one i-cluster
 constexpr int kMaxTypes = 32;
 
+// Live device bytes of one context's handles, by source (nb_memory_info).
+struct MemCount {
+    std::atomic<size_t> via_allocator{0}, via_hip{0};
+};
+
+// A device buffer owned by a handle.  It remembers the allocator (and the
+// stream) it came from, so that it is returned to the same one.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    nb_allocator al{};          // al.alloc == nullptr: hipMalloc / hipFree
+    void *stream = nullptr;     // stream given to al.alloc, passed back to al.free
+    std::shared_ptr<MemCount> mem;
 };
-int ensure(DevBuf &b, size_t bytes);   // grow-only device allocation
+// grow-only device allocation through the context's allocator (hipMalloc without one)
+int ensure(const ::nb_ctx *c, DevBuf &b, size_t bytes);
 void release(DevBuf &b);
 
 }  // namespace mxn
@@ -59,6 +72,10 @@ struct nb_mlp;
 struct nb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    nb_allocator alloc{};       // caller's device allocator (alloc == nullptr: hipMalloc)
+    std::shared_ptr<mxn::MemCount> mem = std::make_shared<mxn::MemCount>();
+    mxn::DevBuf flags_buf;      // holds d_flags
+    mxn::DevBuf stats_buf;      // nb_list_stats counters
     int *d_flags = nullptr;     // latched kernel errors
     int *h_pinned = nullptr;    // pinned host scratch (16 ints)
     mxn::DevBuf partials;       // per-work-item energy/virial partials

@@ -908,23 +908,23 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         if (size * nregions > (1L << 31) - 1) return fail(NB_ERR_OOM, "nb_pairlist_build: list larger than 2^31 entries");
         const long ce = size * nregions;
         if (ce > l->cap_entries) {
-            int rc = ensure(l->entries, (size_t)ce * sizeof(nb_jentry));
+            int rc = ensure(l->ctx, l->entries, (size_t)ce * sizeof(nb_jentry));
             if (rc) return rc;
             l->cap_entries = ce;
         }
         const long cit = ce / item_entries(g->nn) + nregions + 256;   // each region: at most count/per-item + 1 items
         if (cit > l->cap_items) {
-            int rc = ensure(l->items, (size_t)cit * sizeof(int4));
+            int rc = ensure(l->ctx, l->items, (size_t)cit * sizeof(int4));
             if (rc) return rc;
             l->cap_items = cit;
         }
         // j-cluster view and force-call buffers for this capacity; the counters start cleared
         const long njc = g->slots_cap / g->nn;
-        int rc = ensure(l->jcount, (size_t)(njc + 1) * 4);
-        rc = rc ? rc : ensure(l->jstart, (size_t)(njc + 1) * 4);
-        rc = rc ? rc : ensure(l->jrank, (size_t)l->cap_entries * 4);
-        rc = rc ? rc : ensure(l->fj, (size_t)l->cap_entries * g->nn * 12);
-        rc = rc ? rc : ensure(l->fi, (size_t)l->cap_items * g->m * 16);
+        int rc = ensure(l->ctx, l->jcount, (size_t)(njc + 1) * 4);
+        rc = rc ? rc : ensure(l->ctx, l->jstart, (size_t)(njc + 1) * 4);
+        rc = rc ? rc : ensure(l->ctx, l->jrank, (size_t)l->cap_entries * 4);
+        rc = rc ? rc : ensure(l->ctx, l->fj, (size_t)l->cap_entries * g->nn * 12);
+        rc = rc ? rc : ensure(l->ctx, l->fi, (size_t)l->cap_items * g->m * 16);
         if (rc) return rc;
         MXN_HIP(hipMemsetAsync(l->jcount.p, 0, (size_t)(njc + 1) * 4, st));
         k_region_starts<<<(nregions + 256) / 256, 256, 0, st>>>(nregions, (int)size, (int *)l->part_start.p);
@@ -934,11 +934,11 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         l->resv_size = size;
     }
     if (by_distance) {   // the fill pass writes canonical order and keys; the sort orders each region
-        int rc = ensure(l->entries_canon, (size_t)l->cap_entries * sizeof(nb_jentry));
+        int rc = ensure(l->ctx, l->entries_canon, (size_t)l->cap_entries * sizeof(nb_jentry));
         if (rc) return rc;
-        rc = ensure(l->keys, (size_t)l->cap_entries * sizeof(float));
+        rc = ensure(l->ctx, l->keys, (size_t)l->cap_entries * sizeof(float));
         if (rc) return rc;
-        rc = ensure(l->jrank_canon, (size_t)l->cap_entries * 4);
+        rc = ensure(l->ctx, l->jrank_canon, (size_t)l->cap_entries * 4);
         if (rc) return rc;
     }
     a.entries = (nb_jentry *)(by_distance ? l->entries_canon.p : l->entries.p);
@@ -987,16 +987,16 @@ int launch_sci_view(const nb_list *l, int S, int per_item) {
     const long njc = g->slots_cap / g->nn;
     const long cap_items = l->cap_entries / per_item + ngroups + 256;
     void *old_jc = l->sci_jcount.p, *old_tot = l->sci_totals.p;
-    int rc = ensure(l->sci_ent, (size_t)l->cap_entries * sizeof(int4));
-    rc = rc ? rc : ensure(l->sci_mask, (size_t)l->cap_entries * S * sizeof(uint2));
-    rc = rc ? rc : ensure(l->sci_count, (size_t)(ngroups + 1) * 4);
-    rc = rc ? rc : ensure(l->sci_base, (size_t)(ngroups + 1) * 4);
-    rc = rc ? rc : ensure(l->sci_istart, (size_t)(ngroups + 1) * 4);
-    rc = rc ? rc : ensure(l->sci_items, (size_t)cap_items * sizeof(int4));
-    rc = rc ? rc : ensure(l->sci_jcount, (size_t)(njc + 1) * 4);
-    rc = rc ? rc : ensure(l->sci_jstart, (size_t)(njc + 1) * 4);
-    rc = rc ? rc : ensure(l->sci_totals, 16);
-    rc = rc ? rc : ensure(l->sci_fi, (size_t)cap_items * S * 8 * sizeof(float4));
+    int rc = ensure(l->ctx, l->sci_ent, (size_t)l->cap_entries * sizeof(int4));
+    rc = rc ? rc : ensure(l->ctx, l->sci_mask, (size_t)l->cap_entries * S * sizeof(uint2));
+    rc = rc ? rc : ensure(l->ctx, l->sci_count, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->ctx, l->sci_base, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->ctx, l->sci_istart, (size_t)(ngroups + 1) * 4);
+    rc = rc ? rc : ensure(l->ctx, l->sci_items, (size_t)cap_items * sizeof(int4));
+    rc = rc ? rc : ensure(l->ctx, l->sci_jcount, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(l->ctx, l->sci_jstart, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(l->ctx, l->sci_totals, 16);
+    rc = rc ? rc : ensure(l->ctx, l->sci_fi, (size_t)cap_items * S * 8 * sizeof(float4));
     if (rc) return rc;
     if (l->sci_jcount.p != old_jc || l->sci_njc != njc) {   // counters start cleared; the scan clears them after use
         MXN_HIP(hipMemsetAsync(l->sci_jcount.p, 0, (size_t)(njc + 1) * 4, st));
@@ -1044,17 +1044,17 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     const long njc = g->slots_cap / g->nn;
     const size_t nreg = (size_t)outer->resv_nci * kMaxSearchParts + 1;
     void *old_jc = in->jcount.p, *old_tot = in->totals.p;
-    int rc = ensure(in->part_count, nreg * 4);
-    rc = rc ? rc : ensure(in->part_start, nreg * 4);
-    rc = rc ? rc : ensure(in->part_istart, nreg * 4);
-    rc = rc ? rc : ensure(in->totals, 16);
-    rc = rc ? rc : ensure(in->entries, (size_t)outer->cap_entries * sizeof(nb_jentry));
-    rc = rc ? rc : ensure(in->items, (size_t)outer->cap_items * sizeof(int4));
-    rc = rc ? rc : ensure(in->jcount, (size_t)(njc + 1) * 4);
-    rc = rc ? rc : ensure(in->jstart, (size_t)(njc + 1) * 4);
-    rc = rc ? rc : ensure(in->jrank, (size_t)outer->cap_entries * 4);
-    rc = rc ? rc : ensure(in->fj, (size_t)outer->cap_entries * g->nn * 12);
-    rc = rc ? rc : ensure(in->fi, (size_t)outer->cap_items * g->m * 16);
+    int rc = ensure(in->ctx, in->part_count, nreg * 4);
+    rc = rc ? rc : ensure(in->ctx, in->part_start, nreg * 4);
+    rc = rc ? rc : ensure(in->ctx, in->part_istart, nreg * 4);
+    rc = rc ? rc : ensure(in->ctx, in->totals, 16);
+    rc = rc ? rc : ensure(in->ctx, in->entries, (size_t)outer->cap_entries * sizeof(nb_jentry));
+    rc = rc ? rc : ensure(in->ctx, in->items, (size_t)outer->cap_items * sizeof(int4));
+    rc = rc ? rc : ensure(in->ctx, in->jcount, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(in->ctx, in->jstart, (size_t)(njc + 1) * 4);
+    rc = rc ? rc : ensure(in->ctx, in->jrank, (size_t)outer->cap_entries * 4);
+    rc = rc ? rc : ensure(in->ctx, in->fj, (size_t)outer->cap_entries * g->nn * 12);
+    rc = rc ? rc : ensure(in->ctx, in->fi, (size_t)outer->cap_items * g->m * 16);
     if (rc) return rc;
     if (in->jcount.p != old_jc || in->resv_nci != outer->resv_nci)
         MXN_HIP(hipMemsetAsync(in->jcount.p, 0, (size_t)(njc + 1) * 4, st));

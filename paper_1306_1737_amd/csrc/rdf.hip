@@ -119,7 +119,7 @@ int launch_rdf(nb_ctx *ctx, const nb_grid *g, const nb_list *l, float r_max, int
         std::vector<float> e((size_t)nbins + 1);
         const double dr = (double)r_max / nbins;
         for (int k = 0; k <= nbins; ++k) e[(size_t)k] = (float)((k * dr) * (k * dr));
-        int rc = ensure(ctx->rdf_edge, e.size() * sizeof(float));
+        int rc = ensure(ctx, ctx->rdf_edge, e.size() * sizeof(float));
         if (rc) return rc;
         MXN_HIP(hipMemcpyAsync(ctx->rdf_edge.p, e.data(), e.size() * sizeof(float), hipMemcpyHostToDevice, st));
         MXN_HIP(hipStreamSynchronize(st));   // e is released on return

@@ -98,7 +98,10 @@ def test_autotuner_choice_is_valid_and_cached(tmp_path):
     try:
         boxes = [synth.water_box(nw, synth.box_edge_for(nw), seed=900 + k) for k, nw in enumerate(SIZES)]
         cache = tmp_path / "tune.json"
+        held = mxn.nb_memory_info(ctx)
         res = autotune.tune_batch(ctx, boxes, rc=1.0, rlist=1.1, beta=3.12, reps=3, cache=str(cache))
+        assert mxn.nb_memory_info(ctx) == held   # nb_autotune frees every grid, list, batch and buffer it made
+        assert all(0 < row["ms"] < 1e3 for row in res["table"])
         assert tuple(res["shape"]) in autotune.SHAPES and res["group"] in autotune.GROUPS
         assert len(res["table"]) == len(autotune.SHAPES) * len(autotune.GROUPS)
         best = min(res["table"], key=lambda row: row["ms"])

@@ -308,7 +308,8 @@ def test_production_box():
         fr, er, vr = _oracle_forces(box, rc, beta, mode="binned")
         assert rel_rms(f, fr) <= 1e-5
         worst = max_atom_err(f, fr)
-        print("\n[production] force rel RMS %.3e, worst particle %.3e of the RMS force" % (rel_rms(f, fr), worst))
+        print("\n[production] force rel RMS %.3e, worst particle %.3e (of its force, floored at the RMS force)"
+              % (rel_rms(f, fr), worst))
         assert worst <= 1e-4
         np.testing.assert_allclose(e, er, rtol=1e-5)
         assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
