@@ -319,6 +319,30 @@ enum {
 int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial);
 
+/*
+ * nb_forces for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, checks and results as nb_forces with the direct force
+ * kernel (bit for bit: forces, energies and virial), but the energy/virial
+ * partials of the work items and their block sums live in a static device
+ * array of the library (NB_NOALLOC_SCRATCH_BYTES on every GPU the library
+ * runs on, held until the process ends) instead of context memory, so the
+ * call allocates, frees and uploads nothing and records no timers.
+ * Requirements and limits:
+ *   - the list has had a synchronous build (which sizes its storage);
+ *   - the energy partials fit: (work-item capacity + 4) * 88 bytes, rounded up
+ *     to 256, plus 22528 bytes, at most NB_NOALLOC_SCRATCH_BYTES (about
+ *     190 000 work items, e.g. the 96 000-atom 8x8 list); NB_ERR_UNSUPPORTED
+ *     otherwise, as for NB_COULOMB_EWALD_TABLE (it needs a device table);
+ *   - the context's force-kernel variant is ignored (direct kernel).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, contexts
+ * or threads) race and must be serialised by the caller.
+ */
+enum { NB_NOALLOC_SCRATCH_BYTES = 16 << 20 };
+int nb_forces_noalloc(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now,
+                      const nb_params *p, unsigned flags, float *f, double *energy, double *virial);
+
 /* Force-kernel variant used by nb_forces on this context.
  *   NB_FORCE_DIRECT (default): every listed pair is visited in lock-step with
  *     a per-lane cut-off branch (the cut-off conditional of the paper's GPU

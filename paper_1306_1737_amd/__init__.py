@@ -29,7 +29,7 @@ EXPORTS = [
     "nb_create", "nb_destroy", "nb_memory_info", "nb_set_stream", "nb_sync", "nb_last_error",
     "nb_grid_sort", "nb_grid_free", "nb_grid_info", "nb_grid_export",
     "nb_pairlist_build", "nb_pairlist_prune", "nb_rdf", "nb_list_free", "nb_list_info", "nb_list_export_canonical",
-    "nb_forces", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
+    "nb_forces", "nb_forces_noalloc", "nb_buffer_estimate", "nb_timing_enable", "nb_timing_read",
     "nb_list_stats", "nb_set_force_variant", "nb_set_super_cluster", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp", "nb_mlp_set_domain",
@@ -120,6 +120,7 @@ def lib():
             "nb_list_info": ([vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)], i),
             "nb_list_export_canonical": ([vp, vp, ctypes.c_long, ctypes.POINTER(ctypes.c_long)], i),
             "nb_forces": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), u, vp, vp, vp], i),
+            "nb_forces_noalloc": ([vp, vp, vp, vp, ctypes.POINTER(nb_params), u, vp, vp, vp], i),
             "nb_buffer_estimate": ([vp, ctypes.POINTER(nb_buffer_query), i, ctypes.POINTER(d), ctypes.POINTER(d),
                                     ip], i),
             "nb_timing_enable": ([vp, i], i), "nb_timing_read": ([vp, vp, vp], i),
@@ -353,6 +354,12 @@ def nb_set_search_parts(ctx, parts):
 def nb_forces(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=None):
     _check(lib().nb_forces(ctx, grid, lst, _ptr(xyzq_now), ctypes.byref(params), int(flags), _ptr(f), _ptr(energy),
                            _ptr(virial)))
+
+
+def nb_forces_noalloc(ctx, grid, lst, xyzq_now, params, flags, f, energy=None, virial=None):
+    """nb_forces without any device allocation (static library scratch; see include/mxn.h)."""
+    _check(lib().nb_forces_noalloc(ctx, grid, lst, _ptr(xyzq_now), ctypes.byref(params), int(flags), _ptr(f),
+                                   _ptr(energy), _ptr(virial)))
 
 
 # --------------------------------------------------------------- recount

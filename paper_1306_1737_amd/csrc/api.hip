@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -76,7 +77,7 @@ static hipEvent_t take_event(nb_ctx *c) {
 }
 
 ScopedTimer::ScopedTimer(nb_ctx *c, int w) : ctx(c), which(w) {
-    if (!((ctx->timing >> which) & 1)) return;
+    if (which < 0 || !((ctx->timing >> which) & 1)) return;
     hipEvent_t start = take_event(ctx);
     stop = take_event(ctx);
     if (!start || !stop) {
@@ -129,6 +130,24 @@ int nb_create(nb_ctx **ctx, int device, void *hip_stream, const nb_allocator *al
         return rc;
     }
     c->d_flags = (int *)c->flags_buf.p;
+    {
+        // the static scratch of nb_forces_noalloc: its address on this device, looked up once per device
+        static std::mutex mu;
+        static void *addr[64] = {};
+        static int status[64] = {};
+        std::lock_guard<std::mutex> lock(mu);
+        if (device < 64) {
+            if (!addr[device] && status[device] == 0) {
+                status[device] = noalloc_scratch_address(&addr[device]) == NB_OK ? 1 : -1;
+                if (status[device] < 0) c->noalloc_error = nb_last_error();
+            }
+            c->noalloc_scratch = addr[device];
+            if (!c->noalloc_scratch && c->noalloc_error.empty())
+                c->noalloc_error = "the static scratch address could not be looked up on this device";
+        } else {
+            c->noalloc_error = "devices beyond 63 have no static scratch";
+        }
+    }
     hipError_t e = hipMemsetAsync(c->d_flags, 0, sizeof(int), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_pinned, 16 * sizeof(int));
@@ -554,28 +573,45 @@ int nb_set_super_cluster(nb_ctx *c, int clusters, int entries) {
     return NB_OK;
 }
 
+static int forces_check(const char *who, nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now,
+                        const nb_params *p, unsigned flags, float *f, double *energy, double *virial) {
+    const std::string w(who);
+    if (!c || !g || !l || !xyzq_now || !p || !f) return fail(NB_ERR_ARG, w + ": null argument");
+    if (g->ctx != c || l->ctx != c || l->grid != g) return fail(NB_ERR_STATE, w + ": grid/list/context mismatch");
+    if (l->grid_generation != g->generation)
+        return fail(NB_ERR_STATE, w + ": the list was built before the grid's last sort: rebuild it");
+    if (flags & ~(unsigned)(NB_ENERGY | NB_VIRIAL | NB_ACC_FP32 | NB_ACCUMULATE))
+        return fail(NB_ERR_ARG, w + ": unknown flag");
+    if ((flags & NB_ENERGY) && !energy) return fail(NB_ERR_ARG, w + ": energy output is null");
+    if ((flags & NB_VIRIAL) && !virial) return fail(NB_ERR_ARG, w + ": virial output is null");
+    if (!p->c6c12 || p->ntypes < 1 || p->ntypes > kMaxTypes) return fail(NB_ERR_ARG, w + ": ntypes must be 1..32");
+    if (!(p->rc > 0.0f) || !(p->rc <= l->rlist)) return fail(NB_ERR_ARG, w + ": need 0 < rc <= rlist");
+    if (!(p->beta >= 0.0f) || !std::isfinite(p->coulomb_f)) return fail(NB_ERR_ARG, w + ": bad beta/coulomb_f");
+    if (p->coulomb < NB_COULOMB_EWALD || p->coulomb > NB_COULOMB_EWALD_TABLE)
+        return fail(NB_ERR_ARG, w + ": unknown coulomb type");
+    if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
+        return fail(NB_ERR_ARG, w + ": eps_rf must be >= 1, or 0 for a conducting boundary");
+    if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
+        return fail(NB_ERR_UNSUPPORTED, w + ": beta*rc > 4 is outside the fitted Ewald range");
+    return NB_OK;
+}
+
 int nb_forces(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial) {
-    if (!c || !g || !l || !xyzq_now || !p || !f) return fail(NB_ERR_ARG, "nb_forces: null argument");
-    if (g->ctx != c || l->ctx != c || l->grid != g) return fail(NB_ERR_STATE, "nb_forces: grid/list/context mismatch");
-    if (l->grid_generation != g->generation)
-        return fail(NB_ERR_STATE, "nb_forces: the list was built before the grid's last sort: rebuild it");
-    if (flags & ~(unsigned)(NB_ENERGY | NB_VIRIAL | NB_ACC_FP32 | NB_ACCUMULATE))
-        return fail(NB_ERR_ARG, "nb_forces: unknown flag");
-    if ((flags & NB_ENERGY) && !energy) return fail(NB_ERR_ARG, "nb_forces: energy output is null");
-    if ((flags & NB_VIRIAL) && !virial) return fail(NB_ERR_ARG, "nb_forces: virial output is null");
-    if (!p->c6c12 || p->ntypes < 1 || p->ntypes > kMaxTypes) return fail(NB_ERR_ARG, "nb_forces: ntypes must be 1..32");
-    if (!(p->rc > 0.0f) || !(p->rc <= l->rlist)) return fail(NB_ERR_ARG, "nb_forces: need 0 < rc <= rlist");
-    if (!(p->beta >= 0.0f) || !std::isfinite(p->coulomb_f)) return fail(NB_ERR_ARG, "nb_forces: bad beta/coulomb_f");
-    if (p->coulomb < NB_COULOMB_EWALD || p->coulomb > NB_COULOMB_EWALD_TABLE)
-        return fail(NB_ERR_ARG, "nb_forces: unknown coulomb type");
-    if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
-        return fail(NB_ERR_ARG, "nb_forces: eps_rf must be >= 1, or 0 for a conducting boundary");
-    if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
-        return fail(NB_ERR_UNSUPPORTED, "nb_forces: beta*rc > 4 is outside the fitted Ewald range");
+    CHECK(forces_check("nb_forces", c, g, l, xyzq_now, p, flags, f, energy, virial));
     MXN_HIP(hipSetDevice(c->device));
     ScopedTimer tm(c, NB_TIMER_FORCE_CALL);
     return launch_forces(c, g, l, xyzq_now, p, flags, f, energy, virial);
+}
+
+int nb_forces_noalloc(nb_ctx *c, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
+                      unsigned flags, float *f, double *energy, double *virial) {
+    CHECK(forces_check("nb_forces_noalloc", c, g, l, xyzq_now, p, flags, f, energy, virial));
+    if (!c->noalloc_scratch) return fail(NB_ERR_HIP, "nb_forces_noalloc: " + c->noalloc_error);
+    if (l->cap_items < 1 || !l->fj.p || !l->fi.p)
+        return fail(NB_ERR_STATE, "nb_forces_noalloc: the list has not had a synchronous build");
+    MXN_HIP(hipSetDevice(c->device));
+    return launch_forces(c, g, l, xyzq_now, p, flags, f, energy, virial, c->noalloc_scratch);
 }
 
 // ------------------------------------------------------------ pair histogram

@@ -1193,12 +1193,28 @@ void set_ewald_poly(ForceArgs &a, float beta) {
     }
 }
 
+// Device memory that exists from load time on, for nb_forces_noalloc: the per-work-item energy/virial
+// partials and, after them, the per-share sums of their reduction.  One copy per GPU, held until the
+// process ends; every call on a GPU shares it (calls that overlap in time on one GPU race).
+static __device__ __align__(256) unsigned char scratch[NB_NOALLOC_SCRATCH_BYTES];
+
+// The array's device address on the current device (host code uses this, never the array's name).
+int noalloc_scratch_address(void **ptr) {
+    *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(NB_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    return NB_OK;
+}
+
 int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
-                  unsigned flags, float *f, double *energy, double *virial) {
+                  unsigned flags, float *f, double *energy, double *virial, void *noalloc) {
     hipStream_t st = ctx->stream;
     const bool need_acc = flags & (NB_ENERGY | NB_VIRIAL);
-    // super-cluster view: (re)built by the first call after a list build
-    const int S = ctx->force_variant == NB_FORCE_SUPER ? sci_size(l, ctx->sci_clusters) : 0;
+    // super-cluster view: (re)built by the first call after a list build (not for the allocation-free call)
+    const int S = !noalloc && ctx->force_variant == NB_FORCE_SUPER ? sci_size(l, ctx->sci_clusters) : 0;
     if (S) {
         const int per = ctx->sci_per_item > 0 ? ctx->sci_per_item : kSciPerItem;
         if (!l->sci_valid || l->sci_volatile || l->sci_S != S || l->sci_per_item != per) {
@@ -1207,11 +1223,19 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         }
     }
     const long cap_items = S ? l->sci_cap_items : l->cap_items;
-    if (need_acc) {
-        int rc = ensure(ctx, ctx->partials, (size_t)(cap_items + 4) * kNAcc * sizeof(double));
+    const long pstride = cap_items + 4;
+    const size_t part_bytes = (size_t)pstride * kNAcc * sizeof(double);
+    const size_t block_off = (part_bytes + 255) / 256 * 256;
+    if (noalloc) {
+        if (block_off + (size_t)kReduceParts * kNAcc * sizeof(double) > (size_t)NB_NOALLOC_SCRATCH_BYTES)
+            return fail(NB_ERR_UNSUPPORTED, "nb_forces_noalloc: the list's " + std::to_string(cap_items) +
+                                                " work items need more energy partials than the static scratch holds");
+        if (p->coulomb == NB_COULOMB_EWALD_TABLE)
+            return fail(NB_ERR_UNSUPPORTED, "nb_forces_noalloc: the Ewald table variant needs a device table");
+    } else if (need_acc) {
+        int rc = ensure(ctx, ctx->partials, part_bytes);
         if (rc) return rc;
     }
-    const long pstride = cap_items + 4;
     ForceArgs a{};
     a.nslots = (const int *)g->nslots.p;
     a.perm = (const int *)g->perm.p;
@@ -1265,7 +1289,7 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
         a.totals = (const int *)l->sci_totals.p;
         a.sci = S;
     }
-    a.partials = (double *)ctx->partials.p;
+    a.partials = noalloc ? (double *)noalloc : (double *)ctx->partials.p;
     a.pstride = pstride;
     a.f_out = f;
     a.accumulate = (flags & NB_ACCUMULATE) ? 1 : 0;
@@ -1273,9 +1297,13 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     // fold launch: one wavefront per j-cluster; with energies it also reduces the partials
     const int nfold = (g->slots_cap / g->nn + 3) / 4;
     if (need_acc) {
-        int rc = ensure(ctx, ctx->blockpart, (size_t)kReduceParts * kNAcc * sizeof(double));
-        if (rc) return rc;
-        a.blockpart = (double *)ctx->blockpart.p;
+        if (noalloc) {
+            a.blockpart = (double *)((char *)noalloc + block_off);
+        } else {
+            int rc = ensure(ctx, ctx->blockpart, (size_t)kReduceParts * kNAcc * sizeof(double));
+            if (rc) return rc;
+            a.blockpart = (double *)ctx->blockpart.p;
+        }
         a.energy = energy;
         a.virial = virial;
         a.ener = (flags & NB_ENERGY) ? 1 : 0;
@@ -1288,8 +1316,8 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     if (nb == 0) nb = 8;
     const size_t lds = (32 + (size_t)p->ntypes * p->ntypes + 1) * sizeof(float4);
     {
-        ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
-        const int var = ctx->force_variant;
+        ScopedTimer tm(ctx, noalloc ? -1 : NB_TIMER_FORCE_KERNEL);
+        const int var = noalloc ? NB_FORCE_DIRECT : ctx->force_variant;
         if (S == 8) launch_sci<8>(a, l, flags, nb, lds, st);
         else if (S == 4) launch_sci<4>(a, l, flags, nb, lds, st);
         else if (g->m == 4 && g->nn == 4) launch_shape<4, 4>(a, flags, nb, lds, var, st);

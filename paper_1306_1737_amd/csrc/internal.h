@@ -77,6 +77,8 @@ struct nb_ctx {
     mxn::DevBuf flags_buf;      // holds d_flags
     mxn::DevBuf stats_buf;      // nb_list_stats counters
     int *d_flags = nullptr;     // latched kernel errors
+    void *noalloc_scratch = nullptr;   // device address of nb_forces_noalloc's static scratch (set at creation)
+    std::string noalloc_error;         // why it is null
     int *h_pinned = nullptr;    // pinned host scratch (16 ints)
     mxn::DevBuf partials;       // per-work-item energy/virial partials
     mxn::DevBuf blockpart;      // sums of the partials over contiguous shares of the work items
@@ -227,8 +229,11 @@ int launch_mlp_infer(nb_ctx *ctx, const nb_mlp *mlp, const float *X, int batch, 
 // kernel launchers (grid.hip, pairlist.hip, forces.hip)
 int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type);
 int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool sync, bool by_distance);
+// noalloc: the device address of the static scratch (nb_forces_noalloc), or null
 int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, const nb_params *p,
-                  unsigned flags, float *f, double *energy, double *virial);
+                  unsigned flags, float *f, double *energy, double *virial, void *noalloc = nullptr);
+// device address of nb_forces_noalloc's static scratch on the current device
+int noalloc_scratch_address(void **ptr);
 // event-pair timing on the context stream (no-ops unless enabled)
 struct ScopedTimer {
     nb_ctx *ctx;
