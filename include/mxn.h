@@ -309,12 +309,16 @@ enum {
  *   energy   DEVICE double[2] (E_LJ, E_Coulomb), written when NB_ENERGY
  *   virial   DEVICE double[9] row-major sum of r_ij (x) F_i, when NB_VIRIAL
  *
- * Forces are summed per particle in fixed point (multiples of 2^-16
- * kJ mol^-1 nm^-1, exact while the sums stay below 1.4e11), so they do not
- * depend on the order of the partial sums: for a given list and positions
- * they are reproducible bit for bit.  A partial force of 2^36 kJ mol^-1 nm^-1
- * or more (overlapping particles) or a non-finite one makes that particle's
- * force NaN and latches NB_ERR_NONFINITE for nb_sync.
+ * Forces are summed per particle in fixed point (each partial force rounded
+ * to a multiple of 2^-16 kJ mol^-1 nm^-1).  Every addition is exact while a
+ * particle's running sum stays below 2^53 units (1.4e11 kJ mol^-1 nm^-1),
+ * which holds whenever its partial forces are below 2^26 (6.7e7) and number
+ * at most 2^11; then the forces do not depend on the order of the partial
+ * sums, and for a given list and positions they are reproducible bit for
+ * bit.  Partial forces up to 2^36 are accepted (close contacts), and a sum
+ * of such terms beyond 2^53 units may round.  A partial force of 2^36
+ * kJ mol^-1 nm^-1 or more (overlapping particles) or a non-finite one makes
+ * that particle's force NaN and latches NB_ERR_NONFINITE for nb_sync.
  */
 int nb_forces(nb_ctx *ctx, const nb_grid *grid, const nb_list *list, const float *xyzq_now, const nb_params *p,
               unsigned flags, float *f, double *energy, double *virial);
