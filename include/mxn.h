@@ -409,6 +409,17 @@ int nb_batch_create(nb_ctx *ctx, int n_rep, nb_grid *const *grids, nb_list *cons
 void nb_batch_free(nb_batch *batch);
 /* Work items (wavefronts) per workgroup of the batched force kernel: 1, 2, 4 or 8 (default 4). */
 int nb_batch_set_group(nb_batch *batch, int items_per_group);
+/*
+ * Wavefronts of the batched force kernel's main launch, which takes one work
+ * item per wavefront.  0 (default): a quarter more than the replicas' work
+ * items at their lists' last synchronous builds (plus 256), at most the
+ * lists' capacity.  A second launch strides over the items beyond the main
+ * launch's share (lists grown by later asynchronous or batched rebuilds), so
+ * any value gives the same forces, bit for bit; a value above the total
+ * only launches workgroups that exit at once.  Fails with NB_ERR_ARG for a
+ * negative count and NB_ERR_STATE once the batch is captured.
+ */
+int nb_batch_set_grid(nb_batch *batch, long waves);
 int nb_batch_forces(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy, double *virial);
 int nb_batch_capture(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy,
                      double *virial);

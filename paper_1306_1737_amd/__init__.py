@@ -33,7 +33,7 @@ EXPORTS = [
     "nb_list_stats", "nb_set_force_variant", "nb_set_super_cluster", "nb_set_search_parts", "nb_recount",
     "nb_mlp_create", "nb_mlp_free", "nb_mlp_get_params", "nb_mlp_train_step", "nb_mlp_grad", "nb_mlp_infer",
     "nb_buffer_set_mlp", "nb_mlp_set_domain",
-    "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_forces", "nb_batch_capture",
+    "nb_batch_create", "nb_batch_free", "nb_batch_set_group", "nb_batch_set_grid", "nb_batch_forces", "nb_batch_capture",
     "nb_batch_replay", "nb_batch_bind_topology", "nb_batch_rebuild", "nb_batch_capture_cycle", "nb_autotune",
 ]
 NB_MLP_FEATURES, NB_MLP_PARAMS = 8, 4801
@@ -133,7 +133,7 @@ def lib():
             "nb_mlp_grad": ([vp, vp, vp, vp, i, vp, vp], i), "nb_mlp_infer": ([vp, vp, vp, i, vp], i),
             "nb_buffer_set_mlp": ([vp, vp, d], i), "nb_mlp_set_domain": ([vp, ctypes.POINTER(nb_buffer_query)], i),
             "nb_batch_create": ([vp, i, vp, vp, vp, vp, pvp], i), "nb_batch_free": ([vp], None),
-            "nb_batch_set_group": ([vp, i], i), "nb_batch_forces": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
+            "nb_batch_set_group": ([vp, i], i), "nb_batch_set_grid": ([vp, ctypes.c_long], i), "nb_batch_forces": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
             "nb_batch_capture": ([vp, vp, ctypes.POINTER(nb_params), u, vp, vp], i),
             "nb_batch_replay": ([vp, vp], i),
             "nb_batch_bind_topology": ([vp, vp, vp, vp], i), "nb_batch_rebuild": ([vp, vp], i),
@@ -493,6 +493,10 @@ def nb_batch_free(batch):
 
 def nb_batch_set_group(batch, items_per_group):
     _check(lib().nb_batch_set_group(batch, int(items_per_group)))
+
+
+def nb_batch_set_grid(batch, waves):
+    _check(lib().nb_batch_set_grid(batch, int(waves)))
 
 
 def nb_batch_forces(ctx, batch, params, flags, energy=None, virial=None):

@@ -786,6 +786,13 @@ int nb_batch_set_group(nb_batch *b, int waves) {
     return NB_OK;
 }
 
+int nb_batch_set_grid(nb_batch *b, long waves) {
+    if (!b || waves < 0) return fail(NB_ERR_ARG, "nb_batch_set_grid: null batch or negative wavefront count");
+    if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_set_grid: batch already captured");
+    b->grid_waves = waves;
+    return NB_OK;
+}
+
 static int batch_check(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial) {
     if (!c || !b || !p || !p->c6c12) return fail(NB_ERR_ARG, "nb_batch: null argument");
     if (b->ctx != c) return fail(NB_ERR_STATE, "nb_batch: batch belongs to another context");

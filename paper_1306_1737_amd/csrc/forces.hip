@@ -438,10 +438,11 @@ template <int M, int N, bool ENER, bool VIR, bool ACC64, int ELEC>
 __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     const long total = a.totals[2];
     if (xcd_block_first(total, 4) < 0) return;   // whole workgroup past the end
+    // tables at fixed LDS addresses: the LJ row of a pair is one add from its type offsets
+    __shared__ float4 ljt[1 + mxn::kMaxTypes * mxn::kMaxTypes];   // LJ rows by type pair (fill_ljt)
+    __shared__ float4 svec[32];                                   // 27 image shift vectors
     extern __shared__ float4 smem[];
-    float4 *svec = smem;        // 27 image shift vectors
-    float4 *ljt = smem + 32;    // LJ rows by type pair (fill_ljt)
-    float2 *tab = reinterpret_cast<float2 *>(smem + 32 + a.nt * a.nt + 1);   // Ewald table (ELEC == 2)
+    float2 *tab = reinterpret_cast<float2 *>(smem);   // Ewald table (ELEC == 2)
     for (int t = threadIdx.x; t < 27; t += blockDim.x) svec[t] = a.shiftvec[t];
     fill_ljt(a, ljt);
     if (ELEC == 2)
@@ -879,12 +880,13 @@ void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
 template <int M, int N, bool E, bool V, bool D>
 void launch_k(const ForceArgs &a, int nb, size_t lds, int variant, hipStream_t st) {
     (void)variant;   // direct (also for lists the super-cluster kernel does not take)
+    (void)lds;       // its LJ and shift tables are static LDS; only the Ewald table is dynamic
     if (a.elec == NB_COULOMB_RF)
-        k_forces<M, N, E, V, D, 1><<<nb, 256, lds, st>>>(a);
+        k_forces<M, N, E, V, D, 1><<<nb, 256, 0, st>>>(a);
     else if (a.elec == NB_COULOMB_EWALD_TABLE)
-        k_forces<M, N, E, V, D, 2><<<nb, 256, lds + (size_t)a.ntab * sizeof(float2), st>>>(a);
+        k_forces<M, N, E, V, D, 2><<<nb, 256, (size_t)a.ntab * sizeof(float2), st>>>(a);
     else
-        k_forces<M, N, E, V, D, 0><<<nb, 256, lds, st>>>(a);
+        k_forces<M, N, E, V, D, 0><<<nb, 256, 0, st>>>(a);
 }
 
 template <int S, bool E, bool V, bool D>
@@ -1019,9 +1021,21 @@ __global__ void k_batch_gather(BatchArgs b) {
     }
 }
 
-// One launch over the concatenated work items of all replicas, one
-// wavefront per item (split between the XCDs like the single-system kernel);
-// the replica of an item is found by binary search in the item prefix.
+// Work item idx of the concatenated items of all replicas; the replica is found by binary search in the
+// item prefix.
+template <int M, int N, bool ENER, bool VIR>
+__device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, long idx, int lane) {
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
+    const RepDesc &d = b.rep[r];
+    const SysView v =
+        make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
+    force_item<M, N, ENER, VIR, true, 0, false>(a, v, ljt, nullptr, d.shiftvec, (int)(idx - b.item_off[r]), lane);
+}
+
+// One launch over the concatenated work items of all replicas, one wavefront per item, split between the
+// XCDs like the single-system kernel: wavefront k of XCD x takes item x * per + k.  The grid is sized from
+// the replicas' item counts at their last synchronous list builds, so it may hold fewer than per
+// wavefronts per XCD; k_batch_tail takes the items beyond.
 template <int M, int N, bool ENER, bool VIR>
 __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) {
     const long total = b.item_off[b.n_rep];
@@ -1029,14 +1043,27 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
     extern __shared__ float4 ljt[];
     fill_ljt(a, ljt);
     __syncthreads();
-    const int lane = threadIdx.x & 63;
     const long idx = xcd_item(total, b.waves, threadIdx.x >> 6);
     if (idx < 0) return;
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
-    const RepDesc &d = b.rep[r];
-    const SysView v =
-        make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
-    force_item<M, N, ENER, VIR, true, 0, false>(a, v, ljt, nullptr, d.shiftvec, (int)(idx - b.item_off[r]), lane);
+    batch_item<M, N, ENER, VIR>(a, b, ljt, idx, threadIdx.x & 63);
+}
+
+// Items k >= covered of each XCD's share (covered: the main launch's wavefronts per XCD), strided over
+// this launch's wavefronts; nothing to do, and an immediate exit, while the estimate holds.  A separate
+// kernel because the loop costs registers (and occupancy) that the one-item kernel does not need.
+template <int M, int N, bool ENER, bool VIR>
+__global__ __launch_bounds__(512) void k_batch_tail(ForceArgs a, BatchArgs b, long covered) {
+    const long total = b.item_off[b.n_rep];
+    const long per = (total + 7) / 8;
+    const long k0 = covered + (long)(blockIdx.x / 8) * b.waves;
+    if (k0 >= per) return;   // uniform over the workgroup
+    extern __shared__ float4 ljt[];
+    fill_ljt(a, ljt);
+    __syncthreads();
+    const long x0 = (long)(blockIdx.x % 8) * per, x1 = min(x0 + per, total);
+    const long stride = (long)(gridDim.x / 8) * b.waves;
+    for (long idx = x0 + k0 + (threadIdx.x >> 6); idx < x1; idx += stride)
+        batch_item<M, N, ENER, VIR>(a, b, ljt, idx, threadIdx.x & 63);
 }
 
 // one wavefront per j-cluster of every replica (the replicas' slot capacities
@@ -1080,22 +1107,24 @@ __global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs b, int ener, int
 }
 
 template <int M, int N, bool E, bool V>
-int launch_batch_forces_k(const ForceArgs &a, const BatchArgs &b, long cap_items, size_t lds, hipStream_t st) {
-    // enough workgroups for every XCD to hold an eighth of the capacity
-    const long per = (cap_items + 7) / 8;
+int launch_batch_forces_k(const ForceArgs &a, const BatchArgs &b, long est_items, size_t lds, hipStream_t st) {
+    // enough workgroups for every XCD to hold an eighth of the estimated items; the tail launch
+    // (32 workgroups per XCD) takes whatever lies beyond
+    const long per = (est_items + 7) / 8;
     const long nb = 8 * std::max(1L, (per + b.waves - 1) / b.waves);
     k_batch_forces<M, N, E, V><<<(unsigned)nb, 64 * b.waves, lds, st>>>(a, b);
+    k_batch_tail<M, N, E, V><<<8 * 32, 64 * b.waves, lds, st>>>(a, b, (nb / 8) * b.waves);
     return NB_OK;
 }
 
 template <int M, int N>
-int launch_batch_shape(const ForceArgs &a, const BatchArgs &b, unsigned flags, long cap_items, size_t lds,
+int launch_batch_shape(const ForceArgs &a, const BatchArgs &b, unsigned flags, long est_items, size_t lds,
                        hipStream_t st) {
     const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL;
-    if (E && V) return launch_batch_forces_k<M, N, true, true>(a, b, cap_items, lds, st);
-    if (E) return launch_batch_forces_k<M, N, true, false>(a, b, cap_items, lds, st);
-    if (V) return launch_batch_forces_k<M, N, false, true>(a, b, cap_items, lds, st);
-    return launch_batch_forces_k<M, N, false, false>(a, b, cap_items, lds, st);
+    if (E && V) return launch_batch_forces_k<M, N, true, true>(a, b, est_items, lds, st);
+    if (E) return launch_batch_forces_k<M, N, true, false>(a, b, est_items, lds, st);
+    if (V) return launch_batch_forces_k<M, N, false, true>(a, b, est_items, lds, st);
+    return launch_batch_forces_k<M, N, false, false>(a, b, est_items, lds, st);
 }
 }  // namespace
 
@@ -1366,12 +1395,21 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
     k_batch_prefix<<<1, 1024, 0, st>>>(b);
     k_batch_gather<<<(int)((bt->total_slots + 255) / 256), 256, 0, st>>>(b);
     const size_t lds = ((size_t)p->ntypes * p->ntypes + 1) * sizeof(float4);
+    // main-launch wavefronts: a quarter more than the replicas' items at their last synchronous builds
+    // (or the count set by nb_batch_set_grid)
+    long est = 0;
+    for (const nb_list *l : bt->lists) {
+        if (l->est_items <= 0) { est = bt->pstride; break; }
+        est += l->est_items + l->est_items / 4;
+    }
+    est = std::min(bt->pstride, est + 256);
+    if (bt->grid_waves > 0) est = bt->grid_waves;
     {
         ScopedTimer tm(ctx, NB_TIMER_FORCE_KERNEL);
-        if (bt->m == 4 && bt->nn == 4) launch_batch_shape<4, 4>(a, b, flags, bt->pstride, lds, st);
-        else if (bt->m == 4 && bt->nn == 8) launch_batch_shape<4, 8>(a, b, flags, bt->pstride, lds, st);
-        else if (bt->m == 8 && bt->nn == 4) launch_batch_shape<8, 4>(a, b, flags, bt->pstride, lds, st);
-        else launch_batch_shape<8, 8>(a, b, flags, bt->pstride, lds, st);
+        if (bt->m == 4 && bt->nn == 4) launch_batch_shape<4, 4>(a, b, flags, est, lds, st);
+        else if (bt->m == 4 && bt->nn == 8) launch_batch_shape<4, 8>(a, b, flags, est, lds, st);
+        else if (bt->m == 8 && bt->nn == 4) launch_batch_shape<8, 4>(a, b, flags, est, lds, st);
+        else launch_batch_shape<8, 8>(a, b, flags, est, lds, st);
     }
     const int nfold = (int)((bt->total_slots / bt->nn + 3) / 4);
     if (bt->m == 4 && bt->nn == 4) k_batch_fold<4, 4><<<nfold, 256, 0, st>>>(b);

@@ -145,6 +145,7 @@ struct nb_list {
     int resv_parts = 0;        // search parts of the reserved layout (0: none yet)
     int resv_nci = 0;          // i-cluster capacity of the reserved layout
     long resv_size = 0;        // entries per region of the reserved layout
+    long est_items = 0;        // work items of the last synchronous build (sizes the force-kernel grid)
     long last_entries = 0;     // host copy after a synchronous build
     long grid_generation = -1;
     // Super-cluster view (8x8 lists; the grouped force kernel): a cache built
@@ -162,6 +163,7 @@ struct nb_list {
 struct nb_batch {
     nb_ctx *ctx = nullptr;
     int n_rep = 0, m = 0, nn = 0, waves = 4, ncu = 1;
+    long grid_waves = 0;   // main force-launch wavefronts (0: from the lists' item estimates)
     long total_slots = 0, total_atoms = 0, pstride = 0;
     std::vector<nb_grid *> grids;
     std::vector<nb_list *> lists;

@@ -402,17 +402,28 @@ __global__ __launch_bounds__(64) void k_sort_entries(const int *part_start, cons
 }
 
 // Largest entry count of any region (one workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_max_count(const int *in, int n, int *out) {
-    __shared__ int m[1024];
-    int v = 0;
-    for (int i = threadIdx.x; i < n; i += 1024) v = max(v, in[i]);
+// out[0]: the largest region count; out[1]: the work items the counts make (per_item entries each)
+__global__ __launch_bounds__(1024) void k_max_count(const int *in, int n, int per_item, int *out) {
+    __shared__ int m[1024], c[1024];
+    int v = 0, it = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        v = max(v, in[i]);
+        it += (in[i] + per_item - 1) / per_item;
+    }
     m[threadIdx.x] = v;
+    c[threadIdx.x] = it;
     __syncthreads();
     for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) m[threadIdx.x] = max(m[threadIdx.x], m[threadIdx.x + s]);
+        if (threadIdx.x < s) {
+            m[threadIdx.x] = max(m[threadIdx.x], m[threadIdx.x + s]);
+            c[threadIdx.x] += c[threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = m[0];
+    if (threadIdx.x == 0) {
+        out[0] = m[0];
+        out[1] = c[0];
+    }
 }
 
 // Uniform regions: region g starts at g * size (g = 0 .. n).
@@ -899,8 +910,9 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, false, nblocks, st);
         else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, false, nblocks, st);
         else run<8, 8>(l, a, false, nblocks, st);
-        k_max_count<<<1, 1024, 0, st>>>((const int *)l->part_count.p, nregions, (int *)l->totals.p);
-        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        k_max_count<<<1, 1024, 0, st>>>((const int *)l->part_count.p, nregions, item_entries(g->nn),
+                                         (int *)l->totals.p);
+        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         MXN_HIP(hipMemsetAsync((int *)l->totals.p + 3, 0, sizeof(int), st));
         MXN_HIP(hipStreamSynchronize(st));
         const long mx = ctx->h_pinned[0];
@@ -932,6 +944,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         l->resv_nci = nci_cap;
         l->last_entries = ce;
         l->resv_size = size;
+        l->est_items = ctx->h_pinned[1];
     }
     if (by_distance) {   // the fill pass writes canonical order and keys; the sort orders each region
         int rc = ensure(l->ctx, l->entries_canon, (size_t)l->cap_entries * sizeof(nb_jentry));
@@ -1068,6 +1081,7 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     in->resv_parts = outer->resv_parts;
     in->resv_nci = outer->resv_nci;
     in->last_entries = outer->last_entries;
+    in->est_items = outer->est_items;
     in->resv_size = outer->resv_size;
     in->sci_valid = false;
     MXN_HIP(hipMemcpyAsync(in->part_start.p, outer->part_start.p, (size_t)(nregions + 1) * 4, hipMemcpyDeviceToDevice,

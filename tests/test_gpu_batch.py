@@ -90,6 +90,65 @@ def test_batch_matches_per_replica_and_graph_replays(shape):
         mxn.nb_destroy(ctx)
 
 
+def test_batch_grid_size_does_not_change_results():
+    """The main launch takes one item per wavefront over a grid sized from the lists' item estimates and a
+    second launch strides over the rest: any main-grid size (a single workgroup per XCD, the default, far
+    more than the items) gives bit-identical forces and energies, also from a captured graph."""
+    import torch
+    import paper_1306_1737_amd as mxn
+    dev = torch.device("cuda:0")
+    ctx = mxn.nb_create(0)
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(1.0, 3.12, F, lj)
+        reps = _replicas(torch, mxn, ctx, (8, 8))
+        n = len(reps)
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+
+        def run(grid, group):
+            mxn.nb_batch_set_group(batch, group)
+            mxn.nb_batch_set_grid(batch, grid)
+            for r in reps:
+                r["f"].fill_(float("nan"))
+            energy.zero_()
+            mxn.nb_batch_forces(ctx, batch, p, mxn.NB_ENERGY, energy)
+            mxn.nb_sync(ctx)
+            return [r["f"].cpu().numpy().copy() for r in reps], energy.cpu().numpy().copy()
+
+        ref_f, ref_e = run(0, 4)
+        assert all(np.all(np.isfinite(f)) for f in ref_f)
+        for grid, group in ((1, 4), (1, 1), (8 * 8, 8), (999, 2), (10 ** 7, 4)):
+            f, e = run(grid, group)
+            for k in range(n):
+                np.testing.assert_array_equal(f[k], ref_f[k], err_msg="grid %d group %d replica %d" % (grid, group, k))
+            np.testing.assert_array_equal(e, ref_e)
+        with pytest.raises(mxn.NbError):
+            mxn.nb_batch_set_grid(batch, -1)
+        # a graph captured with the smallest main grid: nearly every item from the strided launch
+        mxn.nb_batch_set_group(batch, 4)
+        mxn.nb_batch_set_grid(batch, 1)
+        mxn.nb_batch_capture(ctx, batch, p, mxn.NB_ENERGY, energy)
+        with pytest.raises(mxn.NbError):
+            mxn.nb_batch_set_grid(batch, 0)
+        for rep in range(3):
+            for r in reps:
+                r["f"].fill_(float("nan"))
+            energy.zero_()
+            torch.cuda.synchronize()
+            mxn.nb_batch_replay(ctx, batch)
+            mxn.nb_sync(ctx)
+            for k, r in enumerate(reps):
+                np.testing.assert_array_equal(r["f"].cpu().numpy(), ref_f[k])
+            np.testing.assert_array_equal(energy.cpu().numpy(), ref_e)
+        mxn.nb_batch_free(batch)
+        for r in reps:
+            mxn.nb_list_free(r["lst"]); mxn.nb_grid_free(r["grid"])
+    finally:
+        mxn.nb_destroy(ctx)
+
+
 def test_autotuner_choice_is_valid_and_cached(tmp_path):
     import torch
     import paper_1306_1737_amd as mxn
@@ -187,4 +246,64 @@ def test_batched_rebuild_and_cycle_graph(shape):
         for r in reps:
             mxn.nb_list_free(r["lst"]); mxn.nb_grid_free(r["grid"])
     finally:
+        mxn.nb_destroy(ctx)
+
+
+def test_batched_256_replicas_against_oracle():
+    """The batched configuration at its real size: 256 water boxes of 1 500-24 000 atoms (log-uniform, seeded),
+    rc 1.0 / rlist 1.1 nm, 8x8, one batched launch for all replicas (and the captured cycle graph).  A sample of
+    replicas (the smallest, the largest and six others) is checked against the FP64 oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    import paper_1306_1737_amd as mxn
+    sizes = synth.batched_sizes(256)
+
+    def gen(k):
+        return synth.water_box(int(sizes[k]), synth.box_edge_for(int(sizes[k])), seed=5000 + k)
+
+    with ThreadPoolExecutor(16) as pool:
+        boxes = list(pool.map(gen, range(len(sizes))))
+    dev = torch.device("cuda:0")
+    ctx = mxn.nb_create(0)
+    reps = []
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(1.0, 3.12, F, lj)
+        for b in boxes:
+            r = dict(box=b, xyzq=torch.from_numpy(b.xyzq()).to(dev), type=torch.from_numpy(b.type).to(dev),
+                     eo=torch.from_numpy(b.excl_off).to(dev), ei=torch.from_numpy(b.excl_idx).to(dev),
+                     f=torch.zeros((b.n, 3), dtype=torch.float32, device=dev))
+            r["grid"] = mxn.nb_grid_sort(ctx, b.box, r["xyzq"], r["type"], (8, 8))
+            r["lst"] = mxn.nb_pairlist_build(ctx, r["grid"], 1.1, -1.0, r["eo"], r["ei"])
+            reps.append(r)
+        n = len(reps)
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        mxn.nb_batch_bind_topology(batch, [r["type"] for r in reps], [r["eo"] for r in reps],
+                                   [r["ei"] for r in reps])
+        energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        mxn.nb_batch_forces(ctx, batch, p, mxn.NB_ENERGY, energy)
+        mxn.nb_sync(ctx)
+        f_batch = [r["f"].cpu().numpy().astype(np.float64) for r in reps]
+        e_batch = energy.cpu().numpy().reshape(n, 2)
+        # the whole cycle (batched rebuild + 10 force steps) as one graph: same results on the same positions
+        mxn.nb_batch_capture_cycle(ctx, batch, 10, p, mxn.NB_ENERGY, energy)
+        for _ in range(2):
+            mxn.nb_batch_replay(ctx, batch)
+            mxn.nb_sync(ctx)
+            np.testing.assert_array_equal(energy.cpu().numpy().reshape(n, 2), e_batch)
+        order = np.argsort(sizes)
+        sample = sorted(set([int(order[0]), int(order[-1])] +
+                            [int(k) for k in np.random.default_rng(7).choice(n, 6, replace=False)]))
+        for k in sample:
+            b = boxes[k]
+            fr, er, _ = oracle.forces(b.xyz, b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(), 1.0,
+                                      3.12, F, mode="binned")
+            assert rel_rms(f_batch[k], fr) <= 1e-5, (k, b.n)
+            np.testing.assert_allclose(e_batch[k], er, rtol=1e-5)
+        mxn.nb_batch_free(batch)
+    finally:
+        for r in reps:
+            mxn.nb_list_free(r["lst"])
+            mxn.nb_grid_free(r["grid"])
         mxn.nb_destroy(ctx)
