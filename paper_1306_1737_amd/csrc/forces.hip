@@ -1001,10 +1001,23 @@ __global__ __launch_bounds__(1024) void k_batch_prefix(BatchArgs b) {
     if (t == 1023) b.item_off[b.n_rep] = run[1023];
 }
 
+// The replica of each thread's element x in [first, first + blockDim): the binary search runs once per
+// workgroup, for first (x < the total, off[n] > first), then each thread steps forward from it (a
+// workgroup spans one replica or a few).  Every thread of the workgroup must call it.
+__device__ inline int block_rep(const long *off, int n, long first, long x) {
+    __shared__ int rep0;
+    if (threadIdx.x == 0) rep0 = find_rep(off, n, first);
+    __syncthreads();
+    int r = rep0;
+    while (r + 1 < n && off[r + 1] <= x) ++r;
+    return r;
+}
+
 __global__ void k_batch_gather(BatchArgs b) {
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= b.slot_off[b.n_rep]) return;
-    const int r = find_rep(b.slot_off, b.n_rep, g);
+    const long total = b.slot_off[b.n_rep], g0 = (long)blockIdx.x * blockDim.x, g = g0 + threadIdx.x;
+    if (g0 >= total) return;   // whole workgroup past the end
+    const int r = block_rep(b.slot_off, b.n_rep, g0, min(g, total - 1));
+    if (g >= total) return;
     const RepDesc &d = b.rep[r];
     const int s = (int)(g - b.slot_off[r]);
     if (s >= *d.nslots) return;
@@ -1024,8 +1037,7 @@ __global__ void k_batch_gather(BatchArgs b) {
 // Work item idx of the concatenated items of all replicas; the replica is found by binary search in the
 // item prefix.
 template <int M, int N, bool ENER, bool VIR>
-__device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, long idx, int lane) {
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx));
+__device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, long idx, int r, int lane) {
     const RepDesc &d = b.rep[r];
     const SysView v =
         make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
@@ -1039,13 +1051,24 @@ __device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const 
 template <int M, int N, bool ENER, bool VIR>
 __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) {
     const long total = b.item_off[b.n_rep];
-    if (xcd_block_first(total, b.waves) < 0) return;   // whole workgroup past the end
+    const long first = xcd_block_first(total, b.waves);
+    if (first < 0) return;   // whole workgroup past the end
     extern __shared__ float4 ljt[];
+    __shared__ int rep0;
+    // the replica of the workgroup's first item, by binary search in the item prefix (one thread, while
+    // the others fill the LJ table); each wavefront then steps forward from it, usually not at all
+    if (threadIdx.x == 0) {
+        const long per = (total + 7) / 8;
+        rep0 = find_rep(b.item_off, b.n_rep, min((long)(blockIdx.x % 8) * per + first, total - 1));
+    }
     fill_ljt(a, ljt);
     __syncthreads();
     const long idx = xcd_item(total, b.waves, threadIdx.x >> 6);
     if (idx < 0) return;
-    batch_item<M, N, ENER, VIR>(a, b, ljt, idx, threadIdx.x & 63);
+    const long x = __builtin_amdgcn_readfirstlane(idx);
+    int r = rep0;
+    while (r + 1 < b.n_rep && b.item_off[r + 1] <= x) ++r;
+    batch_item<M, N, ENER, VIR>(a, b, ljt, x, r, threadIdx.x & 63);
 }
 
 // Items k >= covered of each XCD's share (covered: the main launch's wavefronts per XCD), strided over
@@ -1063,16 +1086,20 @@ __global__ __launch_bounds__(512) void k_batch_tail(ForceArgs a, BatchArgs b, lo
     const long x0 = (long)(blockIdx.x % 8) * per, x1 = min(x0 + per, total);
     const long stride = (long)(gridDim.x / 8) * b.waves;
     for (long idx = x0 + k0 + (threadIdx.x >> 6); idx < x1; idx += stride)
-        batch_item<M, N, ENER, VIR>(a, b, ljt, idx, threadIdx.x & 63);
+        batch_item<M, N, ENER, VIR>(a, b, ljt, idx,
+                                    __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx)),
+                                    threadIdx.x & 63);
 }
 
 // one wavefront per j-cluster of every replica (the replicas' slot capacities
 // are multiples of N, so wavefront w covers global slots w*N .. w*N + N - 1)
 template <int M, int N>
 __global__ __launch_bounds__(256) void k_batch_fold(BatchArgs b) {
+    const long total = b.slot_off[b.n_rep], first = (long)blockIdx.x * 4 * N;
     const long g0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * N;
-    if (g0 >= b.slot_off[b.n_rep]) return;
-    const int r = find_rep(b.slot_off, b.n_rep, g0);
+    if (first >= total) return;   // whole workgroup past the end
+    const int r = __builtin_amdgcn_readfirstlane(block_rep(b.slot_off, b.n_rep, first, min(g0, total - 1)));
+    if (g0 >= total) return;
     const RepDesc &d = b.rep[r];
     const FoldView v{(gptr<const int>)d.nslots, (gptr<const int>)d.perm,   (gptr<const int>)d.totals,
                      (gptr<const int>)d.jstart, (gptr<const int>)d.part_istart,
