@@ -9,8 +9,11 @@
 #include <cstring>
 
 #include "internal.h"
+#include "scan.h"
 
 namespace {
+
+using mxn::scan_body;
 
 constexpr int kImgBias = 512;
 
@@ -143,11 +146,33 @@ struct SortArgs {
     float4 *xs, *xs_now, *colbb;
     int *type_s, *perm, *img_s, *slot_of;
     int *flags;
+    int m, nn;                                   // i- and j-cluster sizes
+    float4 *bbi_lo, *bbi_hi, *bbj_lo, *bbj_hi;   // cluster bounding boxes
 };
+
+// Bounding box of each cluster of `size` slots among clusters [c0, c1), one thread per cluster
+// (dummies skipped: a cluster of dummies only keeps the empty box, lo = +inf, hi = -inf).
+__device__ inline void cluster_boxes(const float4 *xs, const int *perm, int size, int c0, int c1, float4 *lo,
+                                     float4 *hi, int t, int nt) {
+    for (int cl = c0 + t; cl < c1; cl += nt) {
+        float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+        float4 h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+        for (int s = cl * size; s < cl * size + size; ++s) {
+            if (perm[s] < 0) continue;
+            const float4 p = xs[s];
+            l.x = fminf(l.x, p.x); l.y = fminf(l.y, p.y); l.z = fminf(l.z, p.z);
+            h.x = fmaxf(h.x, p.x); h.y = fmaxf(h.y, p.y); h.z = fmaxf(h.z, p.z);
+        }
+        lo[cl] = l;
+        hi[cl] = h;
+    }
+}
 
 // One workgroup per column: rank every particle by (z, original index) among
 // the column's particles (keys streamed through LDS in tiles), write the
-// sorted slot arrays, pad with dummies and reduce the column's x/y extent.
+// sorted slot arrays, pad with dummies, reduce the column's x/y extent and
+// form the bounding boxes of the column's clusters (column starts are
+// multiples of both cluster sizes, so no cluster straddles two columns).
 constexpr int kSortThreads = 256;
 constexpr int kSortTile = 1024;
 
@@ -214,155 +239,32 @@ __device__ inline void col_sort_body(const SortArgs &a, int c) {
         __syncthreads();
     }
     if (tid == 0) a.colbb[c] = make_float4(red[0][0], red[1][0], red[2][0], red[3][0]);
+    // the slots written above are visible to the workgroup after the reduction's barriers
+    cluster_boxes(a.xs, a.perm, a.m, start / a.m, end / a.m, a.bbi_lo, a.bbi_hi, tid, kSortThreads);
+    if (a.nn != a.m) cluster_boxes(a.xs, a.perm, a.nn, start / a.nn, end / a.nn, a.bbj_lo, a.bbj_hi, tid, kSortThreads);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_col_sort(SortArgs a) { col_sort_body(a, blockIdx.x); }
-
-// per cluster of `size` slots: min/max over real particles (inf/-inf if none)
-__device__ inline void bb_body(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi,
-                               int blk) {
-    int cl = blk * blockDim.x + threadIdx.x;
-    if (cl >= *nslots / size) return;
-    float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    float4 h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    for (int s = cl * size; s < cl * size + size; ++s) {
-        if (perm[s] < 0) continue;
-        float4 p = xs[s];
-        l.x = fminf(l.x, p.x); l.y = fminf(l.y, p.y); l.z = fminf(l.z, p.z);
-        h.x = fmaxf(h.x, p.x); h.y = fmaxf(h.y, p.y); h.z = fmaxf(h.z, p.z);
-    }
-    lo[cl] = l;
-    hi[cl] = h;
-}
-
-__global__ void k_bb(const int *nslots, int size, const float4 *xs, const int *perm, float4 *lo, float4 *hi) {
-    bb_body(nslots, size, xs, perm, lo, hi, blockIdx.x);
-}
-
-// Exclusive scan on one workgroup of 1024 threads; mode 0: values as is,
-// 1: rounded up to a multiple of p, 2: ceil(v/p).  raw_total (optional)
-// receives the sum of the untransformed values; clear (optional, the input
-// array itself) is zeroed once read.  The input goes through LDS in tiles of
-// 8192 values: each thread issues its eight coalesced loads of a tile
-// together, scans eight consecutive values from LDS, and the 1024 chunk sums
-// are scanned across the workgroup (wavefront scans, then the 16 wavefront
-// totals); a running carry joins the tiles.
-constexpr int kScanPer = 8, kScanTile = 1024 * kScanPer;
-
-// inclusive scans of (s, r) over the workgroup's 1024 threads
-__device__ inline void block_scan2(int &s, int &r, int *ws, int *wr) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int a = __shfl_up(s, o, 64), b = __shfl_up(r, o, 64);
-        if (lane >= o) {
-            s += a;
-            r += b;
-        }
-    }
-    if (lane == 63) {
-        ws[w] = s;
-        wr[w] = r;
-    }
-    __syncthreads();
-    if (w == 0) {
-        int a = lane < 16 ? ws[lane] : 0, b = lane < 16 ? wr[lane] : 0;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            const int x = __shfl_up(a, o, 64), y = __shfl_up(b, o, 64);
-            if (lane >= o) {
-                a += x;
-                b += y;
-            }
-        }
-        if (lane < 16) {
-            ws[lane] = a;
-            wr[lane] = b;
-        }
-    }
-    __syncthreads();
-    if (w > 0) {
-        s += ws[w - 1];
-        r += wr[w - 1];
-    }
-}
-
-__device__ inline void scan_body(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total,
-                                 int *clear = nullptr) {
-    __shared__ int tile[kScanTile];
-    __shared__ int ws[16], wr[16];
-    const int t = threadIdx.x;
-    auto tr = [&](int v) { return mode == 0 ? v : (mode == 1 ? (v + p - 1) / p * p : (v + p - 1) / p); };
-    int carry = 0, rcarry = 0;
-    for (int base = 0; base < n; base += kScanTile) {
-        int v[kScanPer];
-#pragma unroll
-        for (int u = 0; u < kScanPer; ++u) {
-            const int i = base + u * 1024 + t;
-            v[u] = i < n ? in[i] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kScanPer; ++u) {
-            const int i = base + u * 1024 + t;
-            tile[u * 1024 + t] = v[u];
-            if (clear && i < n) clear[i] = 0;
-        }
-        __syncthreads();
-        int s = 0, r = 0;
-#pragma unroll
-        for (int u = 0; u < kScanPer; ++u) {
-            v[u] = tile[t * kScanPer + u];
-            s += tr(v[u]);
-            r += v[u];
-        }
-        const int s0 = s;
-        block_scan2(s, r, ws, wr);
-        int run = carry + s - s0;
-        __syncthreads();   // every thread has read the wavefront totals
-#pragma unroll
-        for (int u = 0; u < kScanPer; ++u) {
-            tile[t * kScanPer + u] = run;
-            run += tr(v[u]);
-        }
-        if (t == 1023) {   // inclusive sums of the last thread: the tile's totals
-            ws[0] = s;
-            wr[0] = r;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kScanPer; ++u) {
-            const int i = base + u * 1024 + t;
-            if (i < n) out[i] = tile[u * 1024 + t];
-        }
-        carry += ws[0];
-        rcarry += wr[0];
-        __syncthreads();   // tile and ws reused by the next tile
-    }
-    if (t == 0) {
-        out[n] = carry;
-        if (total) *total = carry;
-        if (raw_total) *raw_total = rcarry;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_scan(const int *in, int *out, int n, int mode, int p, int *total,
-                                               int *raw_total) {
-    scan_body(in, out, n, mode, p, total, raw_total);
-}
-
-__global__ __launch_bounds__(1024) void k_scan_clear(int *in, int *out, int n) { scan_body(in, out, n, 0, 1, nullptr, nullptr, in); }
-
-__global__ void k_fill_int(int *p, int n, int v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 __device__ inline void shiftvec_body(float4 *sv, float Lx, float Ly, float Lz) {
     int s = threadIdx.x;
     if (s < 27) sv[s] = make_float4((float)(s / 9 - 1) * Lx, (float)((s / 3) % 3 - 1) * Ly, (float)(s % 3 - 1) * Lz, 0.0f);
 }
 
-__global__ void k_shiftvec(float4 *sv, float Lx, float Ly, float Lz) { shiftvec_body(sv, Lx, Ly, Lz); }
+// Column starts (an exclusive scan of the column counts, each rounded up to a multiple of cmax; total
+// into nslots) and the 27 image shift vectors, in one workgroup.
+__global__ __launch_bounds__(1024) void k_col_scan(const int *col_count, int *col_start, int ncol, int cmax,
+                                                   int *nslots, float4 *sv, float Lx, float Ly, float Lz) {
+    shiftvec_body(sv, Lx, Ly, Lz);
+    scan_body(col_count, col_start, ncol, 1, cmax, nslots, nullptr);
+}
+
+
+__global__ void k_fill_int(int *p, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 
 // --------------------------------------------------------------------------
 // Batched grid sort: every stage is one launch over all replicas.  A stage's
@@ -374,7 +276,7 @@ struct GridJob {
     SortArgs s;
     int ncol, nhb, cmax, m, nn, slots_cap;
     int *col_hist, *col_start, *nslots;
-    float4 *bbi_lo, *bbi_hi, *bbj_lo, *bbj_hi, *shiftvec;
+    float4 *shiftvec;
 };
 
 __device__ inline int job_of(const int *off, int n, int b) {
@@ -388,7 +290,7 @@ __device__ inline int job_of(const int *off, int n, int b) {
 }
 
 // stage offsets: off + stage * (n + 1)
-enum { GS_HIST, GS_PREFIX, GS_SCAN, GS_COLSORT, GS_BBI, GS_BBJ, GS_NSTAGES };
+enum { GS_HIST, GS_PREFIX, GS_SCAN, GS_COLSORT, GS_NSTAGES };
 
 __global__ __launch_bounds__(kHistThreads) void kb_wrap_hist(const GridJob *J, const int *off, int n) {
     const int r = job_of(off, n, blockIdx.x);
@@ -404,6 +306,7 @@ __global__ void kb_col_prefix(const GridJob *J, const int *off, int n) {
 
 __global__ __launch_bounds__(1024) void kb_col_scan(const GridJob *J) {
     const GridJob &j = J[blockIdx.x];
+    shiftvec_body(j.shiftvec, j.w.Lx, j.w.Ly, j.w.Lz);
     scan_body(j.w.col_count, j.col_start, j.ncol, 1, j.cmax, j.nslots, nullptr);
 }
 
@@ -419,21 +322,9 @@ __global__ __launch_bounds__(kSortThreads) void kb_col_sort(const GridJob *J, co
     col_sort_body(J[r].s, blockIdx.x - off[r]);
 }
 
-__global__ void kb_bb(const GridJob *J, const int *off, int n, int which) {
-    const int r = job_of(off, n, blockIdx.x);
-    const GridJob &j = J[r];
-    if (which == 0) bb_body(j.nslots, j.m, j.s.xs, j.s.perm, j.bbi_lo, j.bbi_hi, blockIdx.x - off[r]);
-    else bb_body(j.nslots, j.nn, j.s.xs, j.s.perm, j.bbj_lo, j.bbj_hi, blockIdx.x - off[r]);
-}
-
 __global__ __launch_bounds__(1024) void kb_scan(const mxn::ScanJob *J) {
     const mxn::ScanJob &j = J[blockIdx.x];
     scan_body(j.in, j.out, j.n, j.mode, j.p, j.total, j.raw_total, j.clear);
-}
-
-__global__ void kb_shiftvec(const GridJob *J) {
-    const GridJob &j = J[blockIdx.x];
-    shiftvec_body(j.shiftvec, j.w.Lx, j.w.Ly, j.w.Lz);
 }
 
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
@@ -442,15 +333,6 @@ inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 namespace mxn {
 
-void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(in, out, n, 0, 1, total, nullptr);
-}
-
-void launch_scan_clear(int *in, int *out, int n, hipStream_t s) { k_scan_clear<<<1, 1024, 0, s>>>(in, out, n); }
-
-void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(in, out, n, mode, p, total, raw_total);
-}
 
 static WrapArgs make_wrap(const nb_grid *g, const float *xyzq) {
     return WrapArgs{(const float4 *)xyzq, g->n, g->Lf[0], g->Lf[1], g->Lf[2], g->invL[0], g->invL[1], g->invL[2],
@@ -462,7 +344,8 @@ static SortArgs make_sort(const nb_grid *g, const int *type) {
     return SortArgs{(const int *)g->col_count.p, (const int *)g->col_start.p, (const int *)g->bucket.p, type,
                     (const int *)g->atom_img.p, (const float4 *)g->atom_xw.p, (float4 *)g->xs.p, (float4 *)g->xs_now.p,
                     (float4 *)g->colbb.p, (int *)g->type_s.p, (int *)g->perm.p, (int *)g->img_s.p,
-                    (int *)g->slot_of.p, g->ctx->d_flags};
+                    (int *)g->slot_of.p, g->ctx->d_flags, g->m, g->nn, (float4 *)g->bbi_lo.p, (float4 *)g->bbi_hi.p,
+                    (float4 *)g->bbj_lo.p, (float4 *)g->bbj_hi.p};
 }
 
 size_t grid_job_size() { return sizeof(GridJob); }
@@ -483,10 +366,6 @@ void fill_grid_job(void *out, const nb_grid *g, const float *xyzq, const int *ty
     j.col_hist = (int *)g->col_hist.p;
     j.col_start = (int *)g->col_start.p;
     j.nslots = (int *)g->nslots.p;
-    j.bbi_lo = (float4 *)g->bbi_lo.p;
-    j.bbi_hi = (float4 *)g->bbi_hi.p;
-    j.bbj_lo = (float4 *)g->bbj_lo.p;
-    j.bbj_hi = (float4 *)g->bbj_hi.p;
     j.shiftvec = (float4 *)g->shiftvec.p;
     std::memcpy(out, &j, sizeof j);
 }
@@ -497,8 +376,6 @@ void grid_job_blocks(const nb_grid *g, int *blocks_per_stage) {
     blocks_per_stage[GS_PREFIX] = blocks(g->ncol, 256);
     blocks_per_stage[GS_SCAN] = 1;
     blocks_per_stage[GS_COLSORT] = g->ncol;
-    blocks_per_stage[GS_BBI] = blocks(g->slots_cap / g->m, 256);
-    blocks_per_stage[GS_BBJ] = g->nn != g->m ? blocks(g->slots_cap / g->nn, 256) : 0;
 }
 
 // off: DEVICE int[GS_NSTAGES * (n_rep + 1)], each stage's exclusive prefix of the
@@ -514,9 +391,6 @@ int launch_grid_sort_batch(hipStream_t st, const void *jobs, const int *off, int
     kb_col_scan<<<n_rep, 1024, 0, st>>>(J);
     kb_bucket_hist<<<total[GS_HIST], kHistThreads, hb, st>>>(J, o + GS_HIST * stride, n_rep);
     kb_col_sort<<<total[GS_COLSORT], kSortThreads, 0, st>>>(J, o + GS_COLSORT * stride, n_rep);
-    kb_bb<<<total[GS_BBI], 256, 0, st>>>(J, o + GS_BBI * stride, n_rep, 0);
-    if (total[GS_BBJ] > 0) kb_bb<<<total[GS_BBJ], 256, 0, st>>>(J, o + GS_BBJ * stride, n_rep, 1);
-    kb_shiftvec<<<n_rep, 32, 0, st>>>(J);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
@@ -538,8 +412,8 @@ int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
         k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_count.p, ncol, 0);
         k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
     }
-    k_scan<<<1, 1024, 0, st>>>((const int *)g->col_count.p, (int *)g->col_start.p, ncol, 1, g->cmax,
-                               (int *)g->nslots.p, nullptr);
+    k_col_scan<<<1, 1024, 0, st>>>((const int *)g->col_count.p, (int *)g->col_start.p, ncol, g->cmax,
+                                   (int *)g->nslots.p, (float4 *)g->shiftvec.p, g->Lf[0], g->Lf[1], g->Lf[2]);
     if (lds_hist) {
         k_bucket_hist<<<nhb, kHistThreads, hb, st>>>(n, ncol, nhb, (const int *)g->atom_col.p,
                                                      (const int *)g->col_start.p, (const int *)g->col_hist.p,
@@ -551,14 +425,6 @@ int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
     }
     const SortArgs s = make_sort(g, type);
     k_col_sort<<<ncol, kSortThreads, 0, st>>>(s);
-    k_bb<<<blocks(g->slots_cap / g->m, 256), 256, 0, st>>>((const int *)g->nslots.p, g->m, (const float4 *)g->xs.p,
-                                                          (const int *)g->perm.p, (float4 *)g->bbi_lo.p,
-                                                          (float4 *)g->bbi_hi.p);
-    if (g->nn != g->m)
-        k_bb<<<blocks(g->slots_cap / g->nn, 256), 256, 0, st>>>((const int *)g->nslots.p, g->nn,
-                                                                (const float4 *)g->xs.p, (const int *)g->perm.p,
-                                                                (float4 *)g->bbj_lo.p, (float4 *)g->bbj_hi.p);
-    k_shiftvec<<<1, 32, 0, st>>>((float4 *)g->shiftvec.p, g->Lf[0], g->Lf[1], g->Lf[2]);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }

@@ -248,8 +248,6 @@ int launch_recount(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float 
                    float db, int nbins, double *hist);
 int launch_stats(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *xyzq_now, float rc,
                  unsigned long long *d_counts);
-// exclusive scan of n ints on one workgroup; writes out[0..n] (out[n] = total) and *total
-void launch_scan(const int *in, int *out, int n, int *total, hipStream_t s);
 // second stage of a two-stage list: `in` gets outer's entries with a pair within r
 // at the grid's gathered positions (xs_now)
 int launch_prune(nb_list *in, const nb_list *outer, float r);
@@ -264,7 +262,5 @@ int launch_sci_view(const nb_list *l, int S, int per_item);
 size_t rdf_lds_bytes(int nbins, int nt);
 int launch_rdf(nb_ctx *ctx, const nb_grid *g, const nb_list *l, float r_max, int nbins, int nt, int skip_excl,
                unsigned long long *hist);
-// exclusive scan of in[0..n) into out[0..n] that leaves in[] zeroed
-void launch_scan_clear(int *in, int *out, int n, hipStream_t s);
 
 }  // namespace mxn

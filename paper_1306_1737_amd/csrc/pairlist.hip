@@ -14,10 +14,7 @@
 
 #include "devptr.h"
 #include "internal.h"
-
-namespace mxn {
-void launch_scan_mode(const int *in, int *out, int n, int mode, int p, int *total, int *raw_total, hipStream_t s);
-}
+#include "scan.h"
 
 namespace {
 
@@ -376,16 +373,11 @@ __device__ inline void items_body(int nparts_total, int parts, int per_item, con
     const int cnt = min(part_count[g], resv), start = part_start[g], ip = part_istart[g];
     const int nit = (cnt + per_item - 1) / per_item;
     for (int k = 0; k < nit; ++k) {
-        if ((long)ip + k >= cap_items) return;   // overflow: latched by k_finalize
+        if ((long)ip + k >= cap_items) return;   // overflow: latched by finalize_body
         const int js = start + k * per_item;
         const int je = min(js + per_item, start + cnt);
         items[ip + k] = make_int4(g / parts, js, je, 0);
     }
-}
-
-__global__ void k_items(int nparts_total, int parts, int per_item, const int *part_count, const int *part_start,
-                        const int *part_istart, long cap_items, int4 *items) {
-    items_body(nparts_total, parts, per_item, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
 }
 
 // Order the entries of each (i-cluster, part) region by bounding-box distance
@@ -456,7 +448,6 @@ __device__ inline void finalize_body(int *totals, long cap_items, int *flags) {
     if (over) atomicOr(flags, mxn::FLAG_OVERFLOW);
 }
 
-__global__ void k_finalize(int *totals, long cap_items, int *flags) { finalize_body(totals, cap_items, flags); }
 
 // --------------------------------------------------------------------------
 // j-cluster view of a list.  The force kernels store each entry's j-forces
@@ -492,6 +483,24 @@ __device__ inline void jpos_body(const JPosArgs &a, int blk, int nblk) {
 constexpr int kJposBlocks = 1024;   // workgroups of the position pass (per replica in a batch: 256)
 
 __global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x, gridDim.x); }
+
+// After a fill (or prune) pass, one workgroup of 1024 threads: the regions' item offsets (a scan of
+// their entry counts in items), the usable item count (finalize_body, by the thread that wrote the
+// totals) and each j-cluster's first row (a scan of the j-cluster counters, which it clears for the next
+// build): one launch instead of three.  The items themselves are written by k_items, many workgroups.
+__global__ __launch_bounds__(1024) void k_finish(int nregions, int per_item, const int *part_count,
+                                                 int *part_istart, long cap_items, int *totals, int *flags,
+                                                 int *jcount, int *jstart, int njc) {
+    mxn::scan_body(part_count, part_istart, nregions, 2, per_item, totals + 1, totals);
+    finalize_body(totals, cap_items, flags);
+    __syncthreads();   // the LDS tile is reused by the second scan
+    mxn::scan_body(jcount, jstart, njc, 0, 1, nullptr, nullptr, jcount);
+}
+
+__global__ void k_items(int nparts_total, int parts, int per_item, const int *part_count, const int *part_start,
+                        const int *part_istart, long cap_items, int4 *items) {
+    items_body(nparts_total, parts, per_item, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
+}
 
 // --------------------------------------------------------------------------
 // Second stage of a two-stage list (Sec. 2.3: the list built from bounding
@@ -820,20 +829,19 @@ static JPosArgs make_jpos(const nb_list *l) {
 }
 
 // item offsets per region (totals[0] = entries, totals[1] = items) and the work items
-static void finish_items(nb_list *l, int nregions, int parts, hipStream_t st) {
-    const int pe = item_entries(l->grid->nn);
-    launch_scan_mode((const int *)l->part_count.p, (int *)l->part_istart.p, nregions, 2, pe, (int *)l->totals.p + 1,
-                     (int *)l->totals.p, st);
+// items, usable count and j-cluster first rows of a list after its fill or prune pass
+static void finish_list(nb_list *l, int nregions, int parts, hipStream_t st) {
+    const nb_grid *g = l->grid;
+    const int pe = item_entries(g->nn);
+    k_finish<<<1, 1024, 0, st>>>(nregions, pe, (const int *)l->part_count.p, (int *)l->part_istart.p, l->cap_items,
+                                 (int *)l->totals.p, l->ctx->d_flags, (int *)l->jcount.p, (int *)l->jstart.p,
+                                 g->slots_cap / g->nn);
     k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, pe, (const int *)l->part_count.p,
                                                   (const int *)l->part_start.p, (const int *)l->part_istart.p,
                                                   l->cap_items, (int4 *)l->items.p);
 }
-
-// usable item count (overflow check), the first row of each j-cluster and every entry's row
-static void finish_view(nb_list *l, hipStream_t st) {
-    const nb_grid *g = l->grid;
-    k_finalize<<<1, 64, 0, st>>>((int *)l->totals.p, l->cap_items, l->ctx->d_flags);
-    launch_scan_clear((int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn, st);
+// each usable entry's row in the j-cluster view (after finish_list, and after the distance sort)
+static void finish_rows(nb_list *l, hipStream_t st) {
     const int nb = (int)std::min<long>((l->cap_items + 3) / 4, kJposBlocks);
     k_jpos<<<std::max(nb, 1), 256, 0, st>>>(make_jpos(l));
 }
@@ -978,13 +986,13 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
-    finish_items(l, nregions, parts, st);
+    finish_list(l, nregions, parts, st);
     if (by_distance)
         k_sort_entries<<<nregions, 64, 0, st>>>((const int *)l->part_start.p, (const int *)l->part_count.p,
                                                 (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
                                                 (nb_jentry *)l->entries.p, (const int *)l->jrank_canon.p,
                                                 (int *)l->jrank.p);
-    finish_view(l, st);
+    finish_rows(l, st);
     l->sci_valid = false;
     MXN_HIP(hipGetLastError());
     return NB_OK;
@@ -1046,11 +1054,10 @@ int launch_sci_view(const nb_list *l, int S, int per_item) {
     a.jcount = (int *)l->sci_jcount.p;
     int *tot = (int *)l->sci_totals.p;
     k_sci_view<<<ngroups, 256, 0, st>>>(a);
-    launch_scan_mode(a.count, (int *)l->sci_istart.p, ngroups, 2, per_item, tot + 1, tot, st);
+    k_finish<<<1, 1024, 0, st>>>(ngroups, per_item, a.count, (int *)l->sci_istart.p, cap_items, tot,
+                                 l->ctx->d_flags, a.jcount, (int *)l->sci_jstart.p, (int)njc);
     k_items<<<(ngroups + 255) / 256, 256, 0, st>>>(ngroups, 1, per_item, a.count, a.base,
                                                   (const int *)l->sci_istart.p, cap_items, (int4 *)l->sci_items.p);
-    k_finalize<<<1, 64, 0, st>>>(tot, cap_items, l->ctx->d_flags);
-    launch_scan_clear(a.jcount, (int *)l->sci_jstart.p, (int)njc, st);
     const int nb = (int)std::max<long>(1, std::min<long>((cap_items + 3) / 4, kJposBlocks));
     k_sci_rows<<<nb, 256, 0, st>>>(tot, (const int4 *)l->sci_items.p, a.ent, (const int *)l->sci_jstart.p);
     MXN_HIP(hipGetLastError());
@@ -1122,8 +1129,8 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     else if (g->m == 4 && g->nn == 8) k_prune<4, 8><<<nb, 256, 0, st>>>(a);
     else if (g->m == 8 && g->nn == 4) k_prune<8, 4><<<nb, 256, 0, st>>>(a);
     else k_prune<8, 8><<<nb, 256, 0, st>>>(a);
-    finish_items(in, nregions, outer->resv_parts, st);
-    finish_view(in, st);
+    finish_list(in, nregions, outer->resv_parts, st);
+    finish_rows(in, st);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
