@@ -364,11 +364,13 @@ int nb_grid_export(nb_grid *g, int *perm, float *xyzq, int *img, int *col_start,
             delete[] lo;
             return fail(NB_ERR_HIP, hipGetErrorString(e));
         }
-        for (size_t k = 0; k < nci; ++k)
-            for (int d = 0; d < 4; ++d) {
+        for (size_t k = 0; k < nci; ++k) {   // w = 0 (on the device lo.w holds the real-slot mask)
+            for (int d = 0; d < 3; ++d) {
                 bb[8 * k + d] = lo[4 * k + d];
                 bb[8 * k + 4 + d] = lo[nci * 4 + 4 * k + d];
             }
+            bb[8 * k + 3] = bb[8 * k + 7] = 0.0f;
+        }
         delete[] lo;
     }
     return NB_OK;

@@ -151,18 +151,23 @@ struct SortArgs {
 };
 
 // Bounding box of each cluster of `size` slots among clusters [c0, c1), one thread per cluster
-// (dummies skipped: a cluster of dummies only keeps the empty box, lo = +inf, hi = -inf).
+// (dummies skipped: a cluster of dummies only keeps the empty box, lo = +inf, hi = -inf).  lo.w carries
+// the bit pattern of the cluster's real-slot mask (bit k: slot k holds a particle), so the pair search
+// reads which slots are real with the box instead of loading the permutation; hi.w is 0.
 __device__ inline void cluster_boxes(const float4 *xs, const int *perm, int size, int c0, int c1, float4 *lo,
                                      float4 *hi, int t, int nt) {
     for (int cl = c0 + t; cl < c1; cl += nt) {
         float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
         float4 h = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+        unsigned real = 0;
         for (int s = cl * size; s < cl * size + size; ++s) {
             if (perm[s] < 0) continue;
+            real |= 1u << (s - cl * size);
             const float4 p = xs[s];
             l.x = fminf(l.x, p.x); l.y = fminf(l.y, p.y); l.z = fminf(l.z, p.z);
             h.x = fmaxf(h.x, p.x); h.y = fmaxf(h.y, p.y); h.z = fmaxf(h.z, p.z);
         }
+        l.w = __uint_as_float(real);
         lo[cl] = l;
         hi[cl] = h;
     }

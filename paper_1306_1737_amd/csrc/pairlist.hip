@@ -126,11 +126,8 @@ __device__ inline void search_body(const A &a, int blk) {
         resv = a.part_start[gw + 1] - wpos;
     }
     const float4 lo = ld(a.bbi_lo + ci), hi = ld(a.bbi_hi + ci);
-    // the i-cluster (uniform across the wavefront; its positions are re-read per
-    // image shift, which keeps them out of the vector registers in between)
-    unsigned ireal = 0;
-#pragma unroll
-    for (int ia = 0; ia < M; ++ia) ireal |= (a.perm[ci * M + ia] >= 0 ? 1u : 0u) << ia;
+    // the i-cluster's real slots: the mask the grid sort stores in its box's lo.w
+    const unsigned ireal = __float_as_uint(lo.w);
     // keeps the z windows conservative against rounding: the FP32 squared distances
     // carry a relative error below 1e-6, so sqrt of that error is below 1e-3 rlist
     const float zmargin = 1e-3f + 2e-3f * a.rlist;
@@ -252,11 +249,13 @@ __device__ inline void search_body(const A &a, int blk) {
                     const int cj = __shfl(k0, own, 64) + (tt - __shfl(excl, own, 64));
                     if (ok && s == 13) ok = cj * N + N - 1 > ci * M;
                     float d2 = 0.0f;
+                    unsigned jreal = 0;   // the candidate's real slots (its box's lo.w)
                     if (ok) {
                         const float4 jl = ld(a.bbj_lo + cj), jh = ld(a.bbj_hi + cj);
                         d2 = sq3(axis_gap(jl.x, jh.x, slx, shx), axis_gap(jl.y, jh.y, sly, shy),
                                  axis_gap(jl.z, jh.z, slz, shz));
                         ok = d2 < a.rl2;
+                        jreal = __float_as_uint(jl.w);
                     }
                     bool acc = ok;
                     if (ok && !(d2 < a.rb2)) {
@@ -265,20 +264,15 @@ __device__ inline void search_body(const A &a, int blk) {
                         bool hit = false;
                         for (int b0 = 0; b0 < N && !hit; b0 += 4) {
                             float4 pj[4];
-                            int pm[4];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int sb = cj * N + b0 + u;
-                                pj[u] = ld(a.xs + sb);
-                                pm[u] = a.perm[sb];
-                            }
+                            for (int u = 0; u < 4; ++u) pj[u] = ld(a.xs + cj * N + b0 + u);
                             bool near[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {   // real and near the whole i-cluster's box
                                 const float g = sq3(axis_gap(pj[u].x, pj[u].x, slx, shx),
                                                     axis_gap(pj[u].y, pj[u].y, sly, shy),
                                                     axis_gap(pj[u].z, pj[u].z, slz, shz));
-                                near[u] = pm[u] >= 0 && g < rp2;
+                                near[u] = ((jreal >> (b0 + u)) & 1u) && g < rp2;
                             }
 #pragma unroll
                             for (int ia = 0; ia < M; ++ia) {
@@ -300,7 +294,7 @@ __device__ inline void search_body(const A &a, int blk) {
 #pragma unroll
                             for (int b = 0; b < N; ++b) {
                                 const int sb = cj * N + b;
-                                unsigned keep = a.perm[sb] >= 0 ? ireal : 0u;
+                                unsigned keep = ((jreal >> b) & 1u) ? ireal : 0u;
                                 if (s == 13) {
                                     const int tr = sb - ci * M;
                                     keep &= tr >= M ? FULL : (tr <= 0 ? 0u : (1u << tr) - 1u);
