@@ -201,7 +201,9 @@ enum {
  *   rbb       bounding-box shortcut radius (nm); < 0 selects
  *             max(0, rlist - s/2) with s the column spacing
  *   excl_off  DEVICE int[n+1], excl_idx DEVICE int[excl_off[n]]: force-field
- *             exclusions as CSR in original indices; must be symmetric
+ *             exclusions as CSR in original indices; must be symmetric.  Both
+ *             non-NULL (NB_ERR_ARG otherwise); with no exclusions excl_off is
+ *             all zero and excl_idx any valid device address (never read)
  *   flags     0, NB_LIST_ASYNC, NB_LIST_BY_DISTANCE
  *   list      in/out: NULL creates, otherwise reused
  * Storage: each (i-cluster, search part) owns an equal region of the entry

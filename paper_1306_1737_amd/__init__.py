@@ -175,6 +175,22 @@ def _stream(stream):
     return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
 
 
+_no_excl = {}   # device index -> a one-element int32 tensor standing in for an empty exclusion list
+
+
+def _excl(t):
+    """excl_idx as the library takes it: the C calls want a valid device pointer even when there are no
+    exclusions (excl_off all zero), which an empty tensor does not have; a one-element tensor that is never
+    read stands in for it."""
+    if t is None or t.numel() > 0:
+        return t
+    import torch
+    dev = t.device.index if t.device.index is not None else 0
+    if dev not in _no_excl:
+        _no_excl[dev] = torch.zeros(1, dtype=torch.int32, device=t.device)
+    return _no_excl[dev]
+
+
 def _need(t, dtype, numel, name):
     import torch
     if t.device.type != "cuda" or t.dtype != dtype or t.numel() < numel or not t.is_contiguous():
@@ -285,7 +301,7 @@ def nb_pairlist_build(ctx, grid, rlist, rbb, excl_off, excl_idx, flags=0, lst=No
     import torch
     _need(excl_off, torch.int32, 1, "excl_off")
     h = lst if lst is not None else ctypes.c_void_p()
-    _check(lib().nb_pairlist_build(ctx, grid, float(rlist), float(rbb), _ptr(excl_off), _ptr(excl_idx), int(flags),
+    _check(lib().nb_pairlist_build(ctx, grid, float(rlist), float(rbb), _ptr(excl_off), _ptr(_excl(excl_idx)), int(flags),
                                    ctypes.byref(h)))
     return h
 
@@ -516,9 +532,10 @@ def nb_batch_bind_topology(batch, types, excl_offs, excl_idxs):
     n = len(types)
     ta = (ctypes.c_void_p * n)(*[t.data_ptr() for t in types])
     oa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in excl_offs])
+    excl_idxs = [_excl(t) for t in excl_idxs]
     ia = (ctypes.c_void_p * n)(*[t.data_ptr() for t in excl_idxs])
     _check(lib().nb_batch_bind_topology(batch, ta, oa, ia))
-    batch._keep_topology = (list(types), list(excl_offs), list(excl_idxs))
+    batch._keep_topology = (list(types), list(excl_offs), excl_idxs)
 
 
 def nb_batch_rebuild(ctx, batch):
@@ -541,6 +558,7 @@ def nb_autotune(ctx, boxes, xyzq, types, excl_off, excl_idx, rlist, params, flag
     nr = len(xyzq)
     box = np.ascontiguousarray(np.asarray(boxes, np.float64).reshape(nr, 3))
     n = np.ascontiguousarray([t.shape[0] for t in xyzq], np.int32)
+    excl_idx = [_excl(t) for t in excl_idx]
     arrs = [(ctypes.c_void_p * nr)(*[t.data_ptr() for t in ts]) for ts in (xyzq, types, excl_off, excl_idx)]
     rep = nb_replicas(nr, box.ctypes.data, n.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) for a in arrs])
     shp = (nb_shape * len(shapes))(*[nb_shape(*sh) for sh in shapes])
