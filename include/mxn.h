@@ -212,8 +212,10 @@ enum {
  * entries, sizes every region to the largest count plus a quarter plus 8
  * (synchronising once), then fills the regions.  An asynchronous build
  * searches once and fills the regions, with no host synchronisation (it can
- * be captured in a graph); a region that would overflow latches
- * NB_ERR_OVERFLOW, and the next synchronous build re-sizes.
+ * be captured in a graph); a region that would overflow, or more entries
+ * than the j-force rows of the last synchronous build hold (its entry count
+ * plus a quarter), latches NB_ERR_OVERFLOW, and the next synchronous build
+ * re-sizes.
  * Order is deterministic: regions by i-cluster, each region by image shift
  * and j-cluster (canonical), or with NB_LIST_BY_DISTANCE by bounding-box
  * distance (ties in canonical order).

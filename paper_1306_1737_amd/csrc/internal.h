@@ -146,6 +146,7 @@ struct nb_list {
     int resv_nci = 0;          // i-cluster capacity of the reserved layout
     long resv_size = 0;        // entries per region of the reserved layout
     long est_items = 0;        // work items of the last synchronous build (sizes the force-kernel grid)
+    long cap_rows = 0;         // j-force rows fj holds: the last synchronous build's entries plus a quarter
     long last_entries = 0;     // host copy after a synchronous build
     long grid_generation = -1;
     // Super-cluster view (8x8 lists; the grouped force kernel): a cache built

@@ -400,28 +400,33 @@ __global__ __launch_bounds__(64) void k_sort_entries(const int *part_start, cons
     }
 }
 
-// Largest entry count of any region (one workgroup of 1024 threads).
-// out[0]: the largest region count; out[1]: the work items the counts make (per_item entries each)
+// Region counts of a count pass (one workgroup of 1024 threads).  out[0]: the largest region count;
+// out[1]: the work items the counts make (per_item entries each); out[2]: the entries (the list's
+// totals[2] is set again by its fill pass, before any force call reads it).
 __global__ __launch_bounds__(1024) void k_max_count(const int *in, int n, int per_item, int *out) {
-    __shared__ int m[1024], c[1024];
-    int v = 0, it = 0;
+    __shared__ int m[1024], c[1024], e[1024];
+    int v = 0, it = 0, en = 0;
     for (int i = threadIdx.x; i < n; i += 1024) {
         v = max(v, in[i]);
         it += (in[i] + per_item - 1) / per_item;
+        en += in[i];
     }
     m[threadIdx.x] = v;
     c[threadIdx.x] = it;
+    e[threadIdx.x] = en;
     __syncthreads();
     for (int s = 512; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             m[threadIdx.x] = max(m[threadIdx.x], m[threadIdx.x + s]);
             c[threadIdx.x] += c[threadIdx.x + s];
+            e[threadIdx.x] += e[threadIdx.x + s];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         out[0] = m[0];
         out[1] = c[0];
+        out[2] = e[0];
     }
 }
 
@@ -432,11 +437,11 @@ __global__ void k_region_starts(int n, int size, int *start) {
 }
 
 // totals: [0] entries, [1] items (from the scan), [3] region overflow; writes
-// [2] = usable item count (0 on overflow), latches the overflow flag and
-// clears [3] for the next build
-__device__ inline void finalize_body(int *totals, long cap_items, int *flags) {
+// [2] = usable item count (0 on overflow: a region, the items or the j-force
+// rows outgrown), latches the overflow flag and clears [3] for the next build
+__device__ inline void finalize_body(int *totals, long cap_items, long cap_rows, int *flags) {
     if (threadIdx.x != 0) return;
-    const bool over = totals[3] != 0 || (long)totals[1] > cap_items;
+    const bool over = totals[3] != 0 || (long)totals[1] > cap_items || (long)totals[0] > cap_rows;
     totals[2] = over ? 0 : totals[1];
     totals[3] = 0;
     if (over) atomicOr(flags, mxn::FLAG_OVERFLOW);
@@ -483,10 +488,10 @@ __global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockId
 // totals) and each j-cluster's first row (a scan of the j-cluster counters, which it clears for the next
 // build): one launch instead of three.  The items themselves are written by k_items, many workgroups.
 __global__ __launch_bounds__(1024) void k_finish(int nregions, int per_item, const int *part_count,
-                                                 int *part_istart, long cap_items, int *totals, int *flags,
-                                                 int *jcount, int *jstart, int njc) {
+                                                 int *part_istart, long cap_items, long cap_rows, int *totals,
+                                                 int *flags, int *jcount, int *jstart, int njc) {
     mxn::scan_body(part_count, part_istart, nregions, 2, per_item, totals + 1, totals);
-    finalize_body(totals, cap_items, flags);
+    finalize_body(totals, cap_items, cap_rows, flags);
     __syncthreads();   // the LDS tile is reused by the second scan
     mxn::scan_body(jcount, jstart, njc, 0, 1, nullptr, nullptr, jcount);
 }
@@ -731,7 +736,7 @@ struct ListJob {
     int nregions, per_item;
     int *part_count, *part_start, *part_istart, *totals;
     int4 *items;
-    long cap_items;
+    long cap_items, cap_rows;
     int *flags;
 };
 
@@ -762,7 +767,7 @@ __global__ void kb_items(const ListJob *J, const int *off, int n) {
 
 __global__ void kb_finalize(const ListJob *J) {
     const ListJob &j = J[blockIdx.x];
-    finalize_body(j.totals, j.cap_items, j.flags);
+    finalize_body(j.totals, j.cap_items, j.cap_rows, j.flags);
 }
 
 __global__ __launch_bounds__(256) void kb_jpos(const ListJob *J, const int *off, int n) {
@@ -828,8 +833,8 @@ static void finish_list(nb_list *l, int nregions, int parts, hipStream_t st) {
     const nb_grid *g = l->grid;
     const int pe = item_entries(g->nn);
     k_finish<<<1, 1024, 0, st>>>(nregions, pe, (const int *)l->part_count.p, (int *)l->part_istart.p, l->cap_items,
-                                 (int *)l->totals.p, l->ctx->d_flags, (int *)l->jcount.p, (int *)l->jstart.p,
-                                 g->slots_cap / g->nn);
+                                 l->cap_rows, (int *)l->totals.p, l->ctx->d_flags, (int *)l->jcount.p,
+                                 (int *)l->jstart.p, g->slots_cap / g->nn);
     k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, pe, (const int *)l->part_count.p,
                                                   (const int *)l->part_start.p, (const int *)l->part_istart.p,
                                                   l->cap_items, (int4 *)l->items.p);
@@ -862,6 +867,7 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.totals = (int *)l->totals.p;
     j.items = (int4 *)l->items.p;
     j.cap_items = l->cap_items;
+    j.cap_rows = l->cap_rows;
     j.flags = l->ctx->d_flags;
     std::memcpy(out, &j, sizeof j);
     *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, j.per_item, j.totals + 1, j.totals};
@@ -927,7 +933,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         else run<8, 8>(l, a, false, nblocks, st);
         k_max_count<<<1, 1024, 0, st>>>((const int *)l->part_count.p, nregions, item_entries(g->nn),
                                          (int *)l->totals.p);
-        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        MXN_HIP(hipMemcpyAsync(ctx->h_pinned, l->totals.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
         MXN_HIP(hipMemsetAsync((int *)l->totals.p + 3, 0, sizeof(int), st));
         MXN_HIP(hipStreamSynchronize(st));
         const long mx = ctx->h_pinned[0];
@@ -950,7 +956,15 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         int rc = ensure(l->ctx, l->jcount, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->ctx, l->jstart, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->ctx, l->jrank, (size_t)l->cap_entries * 4);
-        rc = rc ? rc : ensure(l->ctx, l->fj, (size_t)l->cap_entries * g->nn * 12);
+        // j-force rows (one per entry, 12 N bytes): this build's entries plus a quarter, not the regions'
+        // capacity (about three times the entries); a later asynchronous build with more entries than that
+        // latches NB_ERR_OVERFLOW like an outgrown region
+        const long ent = ctx->h_pinned[2];
+        const long rows = std::min(l->cap_entries, ent + ent / 4 + 1024);
+        if (rows > l->cap_rows) {
+            rc = rc ? rc : ensure(l->ctx, l->fj, (size_t)rows * g->nn * 12);
+            if (rc == NB_OK) l->cap_rows = rows;
+        }
         rc = rc ? rc : ensure(l->ctx, l->fi, (size_t)l->cap_items * g->m * 16);
         if (rc) return rc;
         MXN_HIP(hipMemsetAsync(l->jcount.p, 0, (size_t)(njc + 1) * 4, st));
@@ -1048,7 +1062,8 @@ int launch_sci_view(const nb_list *l, int S, int per_item) {
     a.jcount = (int *)l->sci_jcount.p;
     int *tot = (int *)l->sci_totals.p;
     k_sci_view<<<ngroups, 256, 0, st>>>(a);
-    k_finish<<<1, 1024, 0, st>>>(ngroups, per_item, a.count, (int *)l->sci_istart.p, cap_items, tot,
+    // rows: a super-cluster entry stands for one or more of the list's entries, which fit l's rows
+    k_finish<<<1, 1024, 0, st>>>(ngroups, per_item, a.count, (int *)l->sci_istart.p, cap_items, l->cap_rows, tot,
                                  l->ctx->d_flags, a.jcount, (int *)l->sci_jstart.p, (int)njc);
     k_items<<<(ngroups + 255) / 256, 256, 0, st>>>(ngroups, 1, per_item, a.count, a.base,
                                                   (const int *)l->sci_istart.p, cap_items, (int4 *)l->sci_items.p);
@@ -1080,7 +1095,7 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     rc = rc ? rc : ensure(in->ctx, in->jcount, (size_t)(njc + 1) * 4);
     rc = rc ? rc : ensure(in->ctx, in->jstart, (size_t)(njc + 1) * 4);
     rc = rc ? rc : ensure(in->ctx, in->jrank, (size_t)outer->cap_entries * 4);
-    rc = rc ? rc : ensure(in->ctx, in->fj, (size_t)outer->cap_entries * g->nn * 12);
+    rc = rc ? rc : ensure(in->ctx, in->fj, (size_t)outer->cap_rows * g->nn * 12);
     rc = rc ? rc : ensure(in->ctx, in->fi, (size_t)outer->cap_items * g->m * 16);
     if (rc) return rc;
     if (in->jcount.p != old_jc || in->resv_nci != outer->resv_nci)
@@ -1096,6 +1111,7 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     in->resv_nci = outer->resv_nci;
     in->last_entries = outer->last_entries;
     in->est_items = outer->est_items;
+    in->cap_rows = outer->cap_rows;
     in->resv_size = outer->resv_size;
     in->sci_valid = false;
     MXN_HIP(hipMemcpyAsync(in->part_start.p, outer->part_start.p, (size_t)(nregions + 1) * 4, hipMemcpyDeviceToDevice,
