@@ -483,17 +483,19 @@ constexpr int kJposBlocks = 1024;   // workgroups of the position pass (per repl
 
 __global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x, gridDim.x); }
 
-// After a fill (or prune) pass, one workgroup of 1024 threads: the regions' item offsets (a scan of
-// their entry counts in items), the usable item count (finalize_body, by the thread that wrote the
-// totals) and each j-cluster's first row (a scan of the j-cluster counters, which it clears for the next
-// build): one launch instead of three.  The items themselves are written by k_items, many workgroups.
+// After a fill (or prune) pass, two independent workgroups of 1024 threads: the first scans the regions'
+// entry counts into item offsets and sets the usable item count (finalize_body, by the thread that wrote
+// the totals), the second scans the j-cluster counters into each j-cluster's first row and clears them
+// for the next build: one launch instead of three.  The items themselves are written by k_items.
 __global__ __launch_bounds__(1024) void k_finish(int nregions, int per_item, const int *part_count,
                                                  int *part_istart, long cap_items, long cap_rows, int *totals,
                                                  int *flags, int *jcount, int *jstart, int njc) {
-    mxn::scan_body(part_count, part_istart, nregions, 2, per_item, totals + 1, totals);
-    finalize_body(totals, cap_items, cap_rows, flags);
-    __syncthreads();   // the LDS tile is reused by the second scan
-    mxn::scan_body(jcount, jstart, njc, 0, 1, nullptr, nullptr, jcount);
+    if (blockIdx.x == 0) {
+        mxn::scan_body(part_count, part_istart, nregions, 2, per_item, totals + 1, totals);
+        finalize_body(totals, cap_items, cap_rows, flags);
+    } else {
+        mxn::scan_body(jcount, jstart, njc, 0, 1, nullptr, nullptr, jcount);
+    }
 }
 
 __global__ void k_items(int nparts_total, int parts, int per_item, const int *part_count, const int *part_start,
@@ -832,7 +834,7 @@ static JPosArgs make_jpos(const nb_list *l) {
 static void finish_list(nb_list *l, int nregions, int parts, hipStream_t st) {
     const nb_grid *g = l->grid;
     const int pe = item_entries(g->nn);
-    k_finish<<<1, 1024, 0, st>>>(nregions, pe, (const int *)l->part_count.p, (int *)l->part_istart.p, l->cap_items,
+    k_finish<<<2, 1024, 0, st>>>(nregions, pe, (const int *)l->part_count.p, (int *)l->part_istart.p, l->cap_items,
                                  l->cap_rows, (int *)l->totals.p, l->ctx->d_flags, (int *)l->jcount.p,
                                  (int *)l->jstart.p, g->slots_cap / g->nn);
     k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, pe, (const int *)l->part_count.p,
@@ -1063,7 +1065,7 @@ int launch_sci_view(const nb_list *l, int S, int per_item) {
     int *tot = (int *)l->sci_totals.p;
     k_sci_view<<<ngroups, 256, 0, st>>>(a);
     // rows: a super-cluster entry stands for one or more of the list's entries, which fit l's rows
-    k_finish<<<1, 1024, 0, st>>>(ngroups, per_item, a.count, (int *)l->sci_istart.p, cap_items, l->cap_rows, tot,
+    k_finish<<<2, 1024, 0, st>>>(ngroups, per_item, a.count, (int *)l->sci_istart.p, cap_items, l->cap_rows, tot,
                                  l->ctx->d_flags, a.jcount, (int *)l->sci_jstart.p, (int)njc);
     k_items<<<(ngroups + 255) / 256, 256, 0, st>>>(ngroups, 1, per_item, a.count, a.base,
                                                   (const int *)l->sci_istart.p, cap_items, (int4 *)l->sci_items.p);
