@@ -190,33 +190,42 @@ __device__ inline void col_sort_body(const SortArgs &a, int c) {
     for (int mine = 0; mine < nc; mine += kSortThreads) {
         int j = mine + tid;
         unsigned long long key = ~0ull;
-        int orig = -1;
-        if (j < nc) {
+        int orig = -1, t = 0, img = 0;
+        float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < nc) {   // everything the particle's slot needs, loaded before the ranking
             orig = a.bucket[start + j];
-            key = ((unsigned long long)sortable(a.atom_xw[orig].z) << 32) | (unsigned)orig;
+            p = a.atom_xw[orig];
+            t = a.type[orig];
+            img = a.atom_img[orig];
+            key = ((unsigned long long)sortable(p.z) << 32) | (unsigned)orig;
         }
         int rank = 0;
-        for (int t0 = 0; t0 < nc; t0 += kSortTile) {
+        if (nc <= kSortThreads) {   // one pass holds the column: the tile is the threads' own keys
+            tile[tid] = key;
             __syncthreads();
-            for (int k = tid; k < kSortTile && t0 + k < nc; k += kSortThreads) {
-                int o = a.bucket[start + t0 + k];
-                tile[k] = ((unsigned long long)sortable(a.atom_xw[o].z) << 32) | (unsigned)o;
-            }
-            __syncthreads();
-            int lim = nc - t0 < kSortTile ? nc - t0 : kSortTile;
             if (j < nc)
-                for (int k = 0; k < lim; ++k) rank += tile[k] < key;
+                for (int k = 0; k < nc; ++k) rank += tile[k] < key;
+        } else {
+            for (int t0 = 0; t0 < nc; t0 += kSortTile) {
+                __syncthreads();
+                for (int k = tid; k < kSortTile && t0 + k < nc; k += kSortThreads) {
+                    int o = a.bucket[start + t0 + k];
+                    tile[k] = ((unsigned long long)sortable(a.atom_xw[o].z) << 32) | (unsigned)o;
+                }
+                __syncthreads();
+                int lim = nc - t0 < kSortTile ? nc - t0 : kSortTile;
+                if (j < nc)
+                    for (int k = 0; k < lim; ++k) rank += tile[k] < key;
+            }
         }
         if (j < nc) {
             int slot = start + rank;
-            float4 p = a.atom_xw[orig];
             a.xs[slot] = p;
             a.xs_now[slot] = p;
-            const int t = a.type[orig];
             if (t < 0) atomicOr(a.flags, mxn::FLAG_TYPE);   // reported by nb_sync; -1 marks dummies
             a.type_s[slot] = max(t, 0);
             a.perm[slot] = orig;
-            a.img_s[slot] = a.atom_img[orig];
+            a.img_s[slot] = img;
             a.slot_of[orig] = slot;
             mnx = fminf(mnx, p.x); mny = fminf(mny, p.y);
             mxx = fmaxf(mxx, p.x); mxy = fmaxf(mxy, p.y);
