@@ -54,6 +54,7 @@ __device__ inline float wrap1(float x, float L, double il, int &k, bool &bad) {
 // with LDS atomics.  The placement order inside a column is arbitrary (the
 // column sort ranks by z and index).
 constexpr int kHistThreads = 1024;
+constexpr int kColsPerBlock = 4;   // columns per workgroup of the per-column prefix (one wavefront each)
 
 __device__ inline int wrap_column(const WrapArgs &a, int i) {
     float4 p = a.xyzq[i];
@@ -93,16 +94,25 @@ __global__ __launch_bounds__(kHistThreads) void k_wrap_hist(WrapArgs a, int ncol
 
 // per column: counts over blocks -> exclusive offsets per block, total count
 __device__ inline void col_prefix_body(int ncol, int nhb, int *hist, int *col_count, int blk) {
-    const int c = blk * blockDim.x + threadIdx.x;
+    // one wavefront per column (kColsPerBlock per workgroup of 256): a wavefront scan over the blocks
+    const int lane = threadIdx.x & 63;
+    const int c = blk * kColsPerBlock + (threadIdx.x >> 6);
     if (c >= ncol) return;
     int *row = hist + (long)c * nhb;
-    int s = 0;
-    for (int b = 0; b < nhb; ++b) {
-        const int v = row[b];
-        row[b] = s;
-        s += v;
+    int carry = 0;
+    for (int b0 = 0; b0 < nhb; b0 += 64) {
+        const int b = b0 + lane;
+        const int v = b < nhb ? row[b] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (b < nhb) row[b] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
     }
-    col_count[c] = s;
+    if (lane == 0) col_count[c] = carry;
 }
 
 __global__ void k_col_prefix(int ncol, int nhb, int *hist, int *col_count) {
@@ -387,7 +397,7 @@ void fill_grid_job(void *out, const nb_grid *g, const float *xyzq, const int *ty
 // workgroups of one replica in each batched stage (the histogram stages share GS_HIST)
 void grid_job_blocks(const nb_grid *g, int *blocks_per_stage) {
     blocks_per_stage[GS_HIST] = hist_blocks(g->n);
-    blocks_per_stage[GS_PREFIX] = blocks(g->ncol, 256);
+    blocks_per_stage[GS_PREFIX] = blocks(g->ncol, kColsPerBlock);
     blocks_per_stage[GS_SCAN] = 1;
     blocks_per_stage[GS_COLSORT] = g->ncol;
 }
@@ -421,7 +431,8 @@ int launch_grid_sort(nb_grid *g, const float *xyzq, const int *type) {
     const size_t hb = (size_t)ncol * sizeof(int);
     if (lds_hist) {
         k_wrap_hist<<<nhb, kHistThreads, hb, st>>>(w, ncol, nhb, (int *)g->col_hist.p);
-        k_col_prefix<<<blocks(ncol, 256), 256, 0, st>>>(ncol, nhb, (int *)g->col_hist.p, (int *)g->col_count.p);
+        k_col_prefix<<<blocks(ncol, kColsPerBlock), 256, 0, st>>>(ncol, nhb, (int *)g->col_hist.p,
+                                                                   (int *)g->col_count.p);
     } else {
         k_fill_int<<<blocks(ncol, 256), 256, 0, st>>>((int *)g->col_count.p, ncol, 0);
         k_wrap_count<<<blocks(n, 256), 256, 0, st>>>(w);
