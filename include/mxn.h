@@ -421,7 +421,7 @@ int nb_batch_set_group(nb_batch *batch, int items_per_group);
  * launch's share (lists grown by later asynchronous or batched rebuilds), so
  * any value gives the same forces, bit for bit; a value above the total
  * only launches workgroups that exit at once.  Fails with NB_ERR_ARG for a
- * negative count and NB_ERR_STATE once the batch is captured.
+ * count outside [0, 2^28] and NB_ERR_STATE once the batch is captured.
  */
 int nb_batch_set_grid(nb_batch *batch, long waves);
 int nb_batch_forces(nb_ctx *ctx, nb_batch *batch, const nb_params *p, unsigned flags, double *energy, double *virial);

@@ -789,7 +789,8 @@ int nb_batch_set_group(nb_batch *b, int waves) {
 }
 
 int nb_batch_set_grid(nb_batch *b, long waves) {
-    if (!b || waves < 0) return fail(NB_ERR_ARG, "nb_batch_set_grid: null batch or negative wavefront count");
+    if (!b || waves < 0 || waves > (1L << 28))
+        return fail(NB_ERR_ARG, "nb_batch_set_grid: null batch or wavefront count outside [0, 2^28]");
     if (b->graph_exec) return fail(NB_ERR_STATE, "nb_batch_set_grid: batch already captured");
     b->grid_waves = waves;
     return NB_OK;

@@ -124,8 +124,9 @@ def test_batch_grid_size_does_not_change_results():
             for k in range(n):
                 np.testing.assert_array_equal(f[k], ref_f[k], err_msg="grid %d group %d replica %d" % (grid, group, k))
             np.testing.assert_array_equal(e, ref_e)
-        with pytest.raises(mxn.NbError):
-            mxn.nb_batch_set_grid(batch, -1)
+        for bad in (-1, (1 << 28) + 1):
+            with pytest.raises(mxn.NbError):
+                mxn.nb_batch_set_grid(batch, bad)
         # a graph captured with the smallest main grid: nearly every item from the strided launch
         mxn.nb_batch_set_group(batch, 4)
         mxn.nb_batch_set_grid(batch, 1)
