@@ -481,7 +481,6 @@ __device__ inline void jpos_body(const JPosArgs &a, int blk, int nblk) {
 
 constexpr int kJposBlocks = 1024;   // workgroups of the position pass (per replica in a batch: 256)
 
-__global__ __launch_bounds__(256) void k_jpos(JPosArgs a) { jpos_body(a, blockIdx.x, gridDim.x); }
 
 // After a fill (or prune) pass, two independent workgroups of 1024 threads: the first scans the regions'
 // entry counts into item offsets and sets the usable item count (finalize_body, by the thread that wrote
@@ -501,6 +500,27 @@ __global__ __launch_bounds__(1024) void k_finish(int nregions, int per_item, con
 __global__ void k_items(int nparts_total, int parts, int per_item, const int *part_count, const int *part_start,
                         const int *part_istart, long cap_items, int4 *items) {
     items_body(nparts_total, parts, per_item, part_count, part_start, part_istart, cap_items, items, blockIdx.x);
+}
+
+// After k_finish (and the distance sort, if any): one wavefront per region writes the region's work items
+// and turns each of its entries' rank into the entry's row (its j-cluster's first row plus the rank), for
+// a usable list (in one launch: the items need not be read back to find the entries).
+__global__ __launch_bounds__(256) void k_items_rows(int nregions, int parts, int per_item, const int *part_count,
+                                                    const int *part_start, const int *part_istart, long cap_items,
+                                                    int4 *items, const int *totals, const nb_jentry *entries,
+                                                    const int *jstart, int *jrank) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (g >= nregions) return;
+    const int start = part_start[g], resv = part_start[g + 1] - start;
+    const int cnt = min(part_count[g], resv), ip = part_istart[g];
+    const int nit = (cnt + per_item - 1) / per_item;
+    for (int k = lane; k < nit; k += 64) {
+        if ((long)ip + k >= cap_items) break;   // overflow: latched by finalize_body
+        const int js = start + k * per_item;
+        items[ip + k] = make_int4(g / parts, js, min(js + per_item, start + cnt), 0);
+    }
+    if (totals[2] == 0) return;   // no usable items (or no entries): the rows are never read
+    for (int e = start + lane; e < start + cnt; e += 64) jrank[e] += jstart[entries[e].cj];
 }
 
 // --------------------------------------------------------------------------
@@ -830,21 +850,21 @@ static JPosArgs make_jpos(const nb_list *l) {
 }
 
 // item offsets per region (totals[0] = entries, totals[1] = items) and the work items
-// items, usable count and j-cluster first rows of a list after its fill or prune pass
-static void finish_list(nb_list *l, int nregions, int parts, hipStream_t st) {
+// usable count and j-cluster first rows of a list after its fill or prune pass
+static void finish_list(nb_list *l, int nregions, hipStream_t st) {
     const nb_grid *g = l->grid;
-    const int pe = item_entries(g->nn);
-    k_finish<<<2, 1024, 0, st>>>(nregions, pe, (const int *)l->part_count.p, (int *)l->part_istart.p, l->cap_items,
-                                 l->cap_rows, (int *)l->totals.p, l->ctx->d_flags, (int *)l->jcount.p,
-                                 (int *)l->jstart.p, g->slots_cap / g->nn);
-    k_items<<<(nregions + 255) / 256, 256, 0, st>>>(nregions, parts, pe, (const int *)l->part_count.p,
-                                                  (const int *)l->part_start.p, (const int *)l->part_istart.p,
-                                                  l->cap_items, (int4 *)l->items.p);
+    k_finish<<<2, 1024, 0, st>>>(nregions, item_entries(g->nn), (const int *)l->part_count.p,
+                                 (int *)l->part_istart.p, l->cap_items, l->cap_rows, (int *)l->totals.p,
+                                 l->ctx->d_flags, (int *)l->jcount.p, (int *)l->jstart.p, g->slots_cap / g->nn);
 }
-// each usable entry's row in the j-cluster view (after finish_list, and after the distance sort)
-static void finish_rows(nb_list *l, hipStream_t st) {
-    const int nb = (int)std::min<long>((l->cap_items + 3) / 4, kJposBlocks);
-    k_jpos<<<std::max(nb, 1), 256, 0, st>>>(make_jpos(l));
+// work items and each usable entry's row (after finish_list, and after the distance sort)
+static void finish_rows(nb_list *l, int nregions, int parts, hipStream_t st) {
+    k_items_rows<<<(nregions + 3) / 4, 256, 0, st>>>(nregions, parts, item_entries(l->grid->nn),
+                                                     (const int *)l->part_count.p, (const int *)l->part_start.p,
+                                                     (const int *)l->part_istart.p, l->cap_items,
+                                                     (int4 *)l->items.p, (const int *)l->totals.p,
+                                                     (const nb_jentry *)l->entries.p, (const int *)l->jstart.p,
+                                                     (int *)l->jrank.p);
 }
 
 size_t list_job_size() { return sizeof(ListJob); }
@@ -996,13 +1016,13 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
     else if (g->m == 4 && g->nn == 8) run<4, 8>(l, a, true, nblocks, st);
     else if (g->m == 8 && g->nn == 4) run<8, 4>(l, a, true, nblocks, st);
     else run<8, 8>(l, a, true, nblocks, st);
-    finish_list(l, nregions, parts, st);
+    finish_list(l, nregions, st);
     if (by_distance)
         k_sort_entries<<<nregions, 64, 0, st>>>((const int *)l->part_start.p, (const int *)l->part_count.p,
                                                 (const nb_jentry *)l->entries_canon.p, (const float *)l->keys.p,
                                                 (nb_jentry *)l->entries.p, (const int *)l->jrank_canon.p,
                                                 (int *)l->jrank.p);
-    finish_rows(l, st);
+    finish_rows(l, nregions, parts, st);
     l->sci_valid = false;
     MXN_HIP(hipGetLastError());
     return NB_OK;
@@ -1141,8 +1161,8 @@ int launch_prune(nb_list *in, const nb_list *outer, float r) {
     else if (g->m == 4 && g->nn == 8) k_prune<4, 8><<<nb, 256, 0, st>>>(a);
     else if (g->m == 8 && g->nn == 4) k_prune<8, 4><<<nb, 256, 0, st>>>(a);
     else k_prune<8, 8><<<nb, 256, 0, st>>>(a);
-    finish_list(in, nregions, outer->resv_parts, st);
-    finish_rows(in, st);
+    finish_list(in, nregions, st);
+    finish_rows(in, nregions, outer->resv_parts, st);
     MXN_HIP(hipGetLastError());
     return NB_OK;
 }
