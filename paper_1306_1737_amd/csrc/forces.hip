@@ -1034,8 +1034,7 @@ __global__ void k_batch_gather(BatchArgs b) {
     }
 }
 
-// Work item idx of the concatenated items of all replicas; the replica is found by binary search in the
-// item prefix.
+// Work item idx of the concatenated items of all replicas, which belongs to replica r.
 template <int M, int N, bool ENER, bool VIR>
 __device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, long idx, int r, int lane) {
     const RepDesc &d = b.rep[r];
