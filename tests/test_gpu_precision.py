@@ -33,10 +33,34 @@ def _announce(request):
     yield
 
 
-def _study(box, rc=1.0, rlist=1.1, beta=3.12, shape=(8, 8), sub_edge=6.22):
+def _grid_matches_oracle(mxn, s, box, shape):
+    """The GPU grid sort of the box equals the oracle's bit for bit (permutation, images, column starts,
+    sorted coordinates, i-cluster boxes): at 3M atoms the columns hold more particles than one pass of the
+    column-sort workgroup, the multi-pass path."""
+    ex = mxn.nb_grid_export(s.grid)
+    g = oracle.grid_sort(box.xyz, box.box, *shape)
+    assert ex["info"]["n_slots"] == g["n_slots"]
+    np.testing.assert_array_equal(ex["col_start"], g["col_start"])
+    np.testing.assert_array_equal(ex["perm"], g["perm"])
+    np.testing.assert_array_equal(ex["img"], g["img"])
+    real = g["perm"] >= 0
+    np.testing.assert_array_equal(ex["xyzq"][real, :3].view(np.uint32), g["xs"][real].view(np.uint32))
+    m = shape[0]
+    xs = g["xs"][: g["n_slots"]].reshape(-1, m, 3)
+    r = real[: g["n_slots"]].reshape(-1, m, 1)
+    np.testing.assert_array_equal(ex["bb"][:, :3], np.where(r, xs, np.float32(np.inf)).min(1))
+    np.testing.assert_array_equal(ex["bb"][:, 4:7], np.where(r, xs, np.float32(-np.inf)).max(1))
+    return int(np.diff(g["col_start"]).max())
+
+
+def _study(box, rc=1.0, rlist=1.1, beta=3.12, shape=(8, 8), sub_edge=6.22, check_grid=False):
     s = GpuSystem(box, shape, rlist, rbb=float(np.float32(default_rbb(box, shape, rlist))))
     try:
         mxn = s.mxn
+        if check_grid:
+            tallest = _grid_matches_oracle(mxn, s, box, shape)
+            _log("grid sort bit-exact; tallest column %d slots" % tallest)
+            assert tallest > 256
         t0 = time.perf_counter()
         f64, e64, v64 = s.forces(rc, beta, mxn.NB_ENERGY | mxn.NB_VIRIAL)
         f32, e32, v32 = s.forces(rc, beta, mxn.NB_ENERGY | mxn.NB_VIRIAL | mxn.NB_ACC_FP32)
@@ -93,7 +117,7 @@ def test_accumulation_precision_3m():
     _log("generating %d waters in a %.2f nm box" % (w.n_mol, w.L))
     box = synth.water_box(w.n_mol, w.L, seed=1306)
     _log("generated in %.1f s" % (time.perf_counter() - t0))
-    rep = _study(box, rc=w.rc, rlist=w.rlist, beta=w.beta, shape=(w.m, w.n))
+    rep = _study(box, rc=w.rc, rlist=w.rlist, beta=w.beta, shape=(w.m, w.n), check_grid=True)
     rep["workload"] = w.name
     if os.environ.get("MXN_PRECISION_REPORT"):
         with open(os.environ["MXN_PRECISION_REPORT"], "w") as fh:
