@@ -687,7 +687,14 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
     const int b = lane % N, g = lane / N, s = cj * N + b;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     bool bad = false;
+    const int at = v.perm[s];   // loaded early: the output index, needed at the end
     if (v.totals[2] > 0) {
+        // the i-forces of the first work item of this lane's i-cluster, loaded before the rows so that the
+        // two chains of loads overlap
+        const int ci = s / M, o = s % M;
+        const int gi = ci / v.sci, sub = ci % v.sci;
+        const int t0 = v.part_istart[gi * v.parts] + g, t1 = v.part_istart[(gi + 1) * v.parts];
+        const float4 fi0 = t0 < t1 ? ld(v.fi + ((long)t0 * v.sci + sub) * M + o) : make_float4(0.f, 0.f, 0.f, 0.f);
         const int k1 = v.jstart[cj + 1];
         for (int k0 = v.jstart[cj] + g; k0 < k1; k0 += 4 * G) {
             // all four loads issued before any is used: past the last row a
@@ -711,10 +718,10 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
                 bad |= ok && b3;
             }
         }
-        const int ci = s / M, o = s % M;
-        const int gi = ci / v.sci, sub = ci % v.sci;
-        const int t1 = v.part_istart[(gi + 1) * v.parts];
-        for (int t = v.part_istart[gi * v.parts] + g; t < t1; t += G) {
+        sx += to_fix(fi0.x, bad);
+        sy += to_fix(fi0.y, bad);
+        sz += to_fix(fi0.z, bad);
+        for (int t = t0 + G; t < t1; t += G) {
             const float4 f = ld(v.fi + ((long)t * v.sci + sub) * M + o);
             sx += to_fix(f.x, bad);
             sy += to_fix(f.y, bad);
@@ -729,7 +736,6 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
     }
     const unsigned long long badm = __ballot(bad);
     if (g == 0) {
-        const int at = v.perm[s];
         if (at >= 0) {
             bool nonfinite = false;
 #pragma unroll
