@@ -103,7 +103,8 @@ __device__ inline int lower_bound(int lo, int hi, F key, float v) {
 // (their partners' slots and positions staged in LDS once per wavefront).
 // a.parts wavefronts share an i-cluster: part p takes the p-th contiguous
 // share of every image shift's candidate columns.
-constexpr int kExclStage = 64;   // staged exclusion partners per wavefront
+constexpr int kExclStage = 64;   // staged exclusion partners per wavefront, one per lane
+static_assert(kExclStage <= 64, "a lane stages one partner");
 
 template <int M, int N, bool FILL, class A>
 __device__ inline void search_body(const A &a, int blk) {
@@ -152,14 +153,22 @@ __device__ inline void search_body(const A &a, int blk) {
         }
         nexcl = __shfl(incl, 63, 64);
         staged = nexcl <= kExclStage && (long)a.nci_cap * M < (1L << 28);   // slot * 8 + i-index fits an int
-        if (staged && lane < M) {
-            int q = incl - (e1 - e0);
-            for (int e = e0; e < e1; ++e, ++q) {
+        if (staged) {
+            // partner q of the i-cluster goes to lane q: its i-particle is the first whose inclusive
+            // count exceeds q, so every lane issues its own load chain at once
+            int ia = 0, first = 0;
+#pragma unroll
+            for (int k = 0; k < M - 1; ++k) {
+                const int ik = __shfl(incl, k, 64);
+                if (lane >= ik) { ia = k + 1; first = ik; }
+            }
+            const int e = __shfl(e0, ia, 64) + lane - first;
+            if (lane < nexcl) {
                 const int ps = a.slot_of[a.excl_idx[e]];
-                xinfo[w][q] = ps * 8 + lane;
-                xpos[w][q] = ld(a.xs + ps);
-                xlo = min(xlo, ps);
-                xhi = max(xhi, ps);
+                xinfo[w][lane] = ps * 8 + ia;
+                xpos[w][lane] = ld(a.xs + ps);
+                xlo = ps;
+                xhi = ps;
             }
         }
 #pragma unroll
