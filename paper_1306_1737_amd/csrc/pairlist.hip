@@ -110,7 +110,6 @@ template <int M, int N, bool FILL, class A>
 __device__ inline void search_body(const A &a, int blk) {
     constexpr unsigned FULL = (1u << M) - 1u;
     __shared__ float4 xpos[4][kExclStage];
-    __shared__ int xinfo[4][kExclStage];
     __shared__ float4 ipos[4][M];   // the i-cluster's particles moved by the current image shift
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gw = blk * 4 + w;
@@ -138,6 +137,7 @@ __device__ inline void search_body(const A &a, int blk) {
     int nexcl = 0;
     bool staged = true;
     int xlo = 0x7fffffff, xhi = -1;   // slot range of the staged partners
+    int xv = 0;                       // lane q < nexcl: staged partner q as slot * 8 + i-index
     if (FILL) {
         int e0 = 0, e1 = 0;
         if (lane < M && ((ireal >> lane) & 1u)) {
@@ -151,7 +151,7 @@ __device__ inline void search_body(const A &a, int blk) {
             const int v = __shfl_up(incl, o, 64);
             if (lane >= o) incl += v;
         }
-        nexcl = __shfl(incl, 63, 64);
+        nexcl = __builtin_amdgcn_readlane(incl, 63);
         staged = nexcl <= kExclStage && (long)a.nci_cap * M < (1L << 28);   // slot * 8 + i-index fits an int
         if (staged) {
             // partner q of the i-cluster goes to lane q: its i-particle is the first whose inclusive
@@ -165,7 +165,7 @@ __device__ inline void search_body(const A &a, int blk) {
             const int e = __shfl(e0, ia, 64) + lane - first;
             if (lane < nexcl) {
                 const int ps = a.slot_of[a.excl_idx[e]];
-                xinfo[w][lane] = ps * 8 + ia;
+                xv = ps * 8 + ia;
                 xpos[w][lane] = ld(a.xs + ps);
                 xlo = ps;
                 xhi = ps;
@@ -176,6 +176,8 @@ __device__ inline void search_body(const A &a, int blk) {
             xlo = min(xlo, __shfl_xor(xlo, o, 64));
             xhi = max(xhi, __shfl_xor(xhi, o, 64));
         }
+        xlo = __builtin_amdgcn_readfirstlane(xlo);
+        xhi = __builtin_amdgcn_readfirstlane(xhi);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -312,13 +314,17 @@ __device__ inline void search_body(const A &a, int blk) {
                             }
                             if (staged) {
                                 // only a j-cluster holding a staged partner's slot can lose mask bits
-                                const bool near = cj * N + N - 1 >= xlo && cj * N <= xhi;
-                                for (int q = 0; near && q < nexcl; ++q) {
-                                    const int v = xinfo[w][q], ia = v & 7, b = (v >> 3) - cj * N;
-                                    if (b < 0 || b >= N) continue;
-                                    const float4 pj = xpos[w][q], pi = ipos[w][ia];
-                                    if (sq3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < a.rl2)
-                                        mask &= ~(1ull << (b * M + ia));
+                                // partner q's slot and i-index are read from lane q's register: no
+                                // memory wait unless the partner lies in this lane's candidate
+                                if (cj * N + N - 1 >= xlo && cj * N <= xhi) {
+                                    for (int q = 0; q < nexcl; ++q) {
+                                        const int v = __builtin_amdgcn_readlane(xv, q), ia = v & 7,
+                                                  b = (v >> 3) - cj * N;
+                                        if (b < 0 || b >= N) continue;
+                                        const float4 pj = xpos[w][q], pi = ipos[w][ia];
+                                        if (sq3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < a.rl2)
+                                            mask &= ~(1ull << (b * M + ia));
+                                    }
                                 }
                             } else {   // more partners than staged: read them from the CSR arrays
                                 for (int ia = 0; ia < M; ++ia) {
