@@ -759,11 +759,12 @@ __device__ inline void fold_body(const FoldView &v, int cj, int lane) {
 // Energy and virial from the per-item partials, deterministic and in two
 // stages: the first kReduceParts fold workgroups each sum a contiguous share
 // of the items (fixed thread assignment and tree) into one value per
-// quantity, then one workgroup sums those values in order.  (A single
+// quantity, then one wavefront sums those values in a fixed order.  (A single
 // launch with a last-workgroup ticket needs a device-scope release per
 // workgroup, which writes back the L2 of every XCD: measured far slower.)
 // FP64, or FP32 throughout for the precision study.
 constexpr int kReduceParts = 256;
+static_assert(kReduceParts % 64 == 0, "the second stage gives each lane the same number of shares");
 
 template <bool ACC64>
 __device__ inline void fold_energy(const ForceArgs &a) {
@@ -788,25 +789,34 @@ __device__ inline void fold_energy(const ForceArgs &a) {
     }
 }
 
+// The second stage: one wavefront, every share's value loaded at once (one
+// memory latency instead of one per quantity), four per lane summed in order
+// and then across the lanes by a fixed butterfly.
 template <bool ACC64>
-__global__ __launch_bounds__(256) void k_reduce_parts(const double *blockpart, int R, double *energy, double *virial,
-                                                      int ener, int vir) {
+__global__ __launch_bounds__(64) void k_reduce_parts(const double *blockpart, int R, double *energy, double *virial,
+                                                     int ener, int vir) {
     using acc_t = typename std::conditional<ACC64, double, float>::type;
-    __shared__ acc_t red[256];
+    constexpr int P = kReduceParts / 64;
     const int t = threadIdx.x;
+    double v[kNAcc][P];
+#pragma unroll
+    for (int k = 0; k < kNAcc; ++k) {
+        const bool on = k < 2 ? ener : vir;
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            v[k][u] = on && t + 64 * u < R ? blockpart[(size_t)k * kReduceParts + t + 64 * u] : 0.0;
+    }
+#pragma unroll
     for (int k = 0; k < kNAcc; ++k) {
         if ((k < 2 && !ener) || (k >= 2 && !vir)) continue;
-        red[t] = t < R ? (acc_t)blockpart[(size_t)k * kReduceParts + t] : (acc_t)0;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (t < h) red[t] += red[t + h];
-            __syncthreads();
-        }
+        acc_t s = 0;
+#pragma unroll
+        for (int u = 0; u < P; ++u) s += (acc_t)v[k][u];
+        s = wave_sum(s);
         if (t == 0) {
-            if (k < 2) energy[k] = (double)red[0];
-            else virial[k - 2] = (double)red[0];
+            if (k < 2) energy[k] = (double)s;
+            else virial[k - 2] = (double)s;
         }
-        __syncthreads();
     }
 }
 
@@ -876,10 +886,10 @@ void launch_fold(const ForceArgs &a, int acc, int nb, hipStream_t st) {
         k_fold<M, N, 0><<<nb, 256, 0, st>>>(a);
     } else if (acc == 1) {
         k_fold<M, N, 1><<<nb, 256, 0, st>>>(a);
-        k_reduce_parts<false><<<1, 256, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
+        k_reduce_parts<false><<<1, 64, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
     } else {
         k_fold<M, N, 2><<<nb, 256, 0, st>>>(a);
-        k_reduce_parts<true><<<1, 256, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
+        k_reduce_parts<true><<<1, 64, 0, st>>>(a.blockpart, R, a.energy, a.virial, a.ener, a.vir);
     }
 }
 
