@@ -6,7 +6,7 @@ partners, so these boxes exclude every particle from its k nearest neighbours (p
 symmetric): the excluded pairs are then the closest ones, all inside r_list, so the masks depend on them.
 "dense" puts every i-cluster past the staging limit, "mixed" only those in the lower half of the box, so one
 search takes both paths.  Lists bit-exact against the oracle; forces, energies and virial against the FP64
-oracle, with the direct and the super-cluster force kernels.
+oracle, with the direct and the super-cluster force kernels, and through the batched rebuild.
 """
 import dataclasses
 import sys
@@ -96,3 +96,60 @@ def test_dense_exclusions(boxes, which, shape, variant):
         assert np.abs(v - vr).max() <= 1e-5 * np.abs(vr).max()
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (8, 8)])
+def test_dense_exclusions_batched_rebuild(boxes, shape):
+    """The batched rebuild (one search launch over every replica, partner arrays read from the replicas'
+    tables) on replicas with dense, mixed and water exclusions, after the particles moved: every list
+    bit-exact against the oracle's for the moved positions, forces and energies against the FP64 oracle."""
+    import torch
+    import paper_1306_1737_amd as mxn
+    dev = torch.device("cuda:0")
+    rlist, rc, beta = 1.1, 1.0, 3.12
+    systems = [boxes["dense"], synth.water_box(700, synth.box_edge_for(700), seed=2407), boxes["mixed"]]
+    ctx = mxn.nb_create(0)
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(rc, beta, F, lj)
+        reps = []
+        for b in systems:
+            r = dict(box=b, xyzq=torch.from_numpy(b.xyzq()).to(dev), type=torch.from_numpy(b.type).to(dev),
+                     eo=torch.from_numpy(b.excl_off).to(dev), ei=torch.from_numpy(b.excl_idx).to(dev),
+                     f=torch.zeros((b.n, 3), dtype=torch.float32, device=dev))
+            r["grid"] = mxn.nb_grid_sort(ctx, b.box, r["xyzq"], r["type"], shape)
+            r["lst"] = mxn.nb_pairlist_build(ctx, r["grid"], rlist, -1.0, r["eo"], r["ei"])
+            reps.append(r)
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        mxn.nb_batch_bind_topology(batch, [r["type"] for r in reps], [r["eo"] for r in reps], [r["ei"] for r in reps])
+        moved = []
+        for k, r in enumerate(reps):
+            b = r["box"]
+            x9 = synth.free_flight(b.xyz, synth.velocities(b.mass, 300.0, seed=90 + k), 0.002, 10)[9].astype(np.float32)
+            moved.append(x9)
+            r["xyzq"].copy_(torch.from_numpy(b.xyzq(x9)).to(dev))   # in place: the batch keeps the pointer
+        mxn.nb_batch_rebuild(ctx, batch)
+        energy = torch.zeros(2 * len(reps), dtype=torch.float64, device=dev)
+        mxn.nb_batch_forces(ctx, batch, p, mxn.NB_ENERGY, energy)
+        mxn.nb_sync(ctx)
+        en = energy.cpu().numpy().reshape(len(reps), 2)
+        for k, r in enumerate(reps):
+            b = r["box"]
+            got = mxn.nb_list_export_canonical(r["lst"])
+            og = oracle.grid_sort(moved[k], b.box, *shape)
+            rbb = np.float32(default_rbb(b, shape, rlist))
+            ref = oracle.pairlist(og, b.box, np.float32(rlist), rbb, b.excl_off, b.excl_idx)
+            assert len(got) == len(ref), (k, len(got), len(ref))
+            for key in ("ci", "shift", "cj", "mask"):
+                np.testing.assert_array_equal(got[key], ref[key], err_msg="replica %d %s" % (k, key))
+            fr, er, _ = oracle.forces(moved[k], b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(),
+                                      rc, beta, F)
+            assert rel_rms(r["f"].cpu().numpy().astype(np.float64), fr) <= 1e-5
+            np.testing.assert_allclose(en[k], er, rtol=1e-5)
+        mxn.nb_batch_free(batch)
+        for r in reps:
+            mxn.nb_list_free(r["lst"])
+            mxn.nb_grid_free(r["grid"])
+    finally:
+        mxn.nb_destroy(ctx)
