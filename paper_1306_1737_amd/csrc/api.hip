@@ -56,7 +56,7 @@ void release(DevBuf &b) {
             b.al.free(b.p, b.stream, b.al.user);
             if (b.mem) b.mem->via_allocator -= b.bytes;
         } else {
-            hipFree(b.p);
+            (void)hipFree(b.p);   // teardown: nothing to report to
             if (b.mem) b.mem->via_hip -= b.bytes;
         }
     }
@@ -84,12 +84,12 @@ ScopedTimer::ScopedTimer(nb_ctx *c, int w) : ctx(c), which(w) {
         stop = nullptr;
         return;
     }
-    hipEventRecord(start, ctx->stream);
+    (void)hipEventRecord(start, ctx->stream);   // a failed record shows as a missing sample
     ctx->timers[which].push_back({start, stop});
 }
 
 ScopedTimer::~ScopedTimer() {
-    if (stop) hipEventRecord(stop, ctx->stream);
+    if (stop) (void)hipEventRecord(stop, ctx->stream);
 }
 
 double analytic_drift(const nb_buffer_query &q, double rb);
@@ -162,14 +162,14 @@ int nb_create(nb_ctx **ctx, int device, void *hip_stream, const nb_allocator *al
 
 void nb_destroy(nb_ctx *c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
+    (void)hipSetDevice(c->device);   // teardown: errors cannot be reported from here
+    (void)hipStreamSynchronize(c->stream);
     for (auto &v : c->timers)
         for (auto &pr : v) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
-    for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     release(c->partials);
     release(c->blockpart);
     release(c->etab);
@@ -177,7 +177,7 @@ void nb_destroy(nb_ctx *c) {
     release(c->mlp_io);
     release(c->stats_buf);
     release(c->flags_buf);
-    if (c->h_pinned) hipHostFree(c->h_pinned);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     delete c;
 }
 
@@ -309,8 +309,8 @@ int nb_grid_sort(nb_ctx *c, const double box[3], int n, const float *xyzq, const
 
 void nb_grid_free(nb_grid *g) {
     if (!g) return;
-    hipSetDevice(g->ctx->device);
-    hipStreamSynchronize(g->ctx->stream);
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
     grid_release(g);
     delete g;
 }
@@ -471,8 +471,8 @@ int nb_pairlist_prune(nb_ctx *c, const nb_list *outer, const float *xyzq_now, fl
 
 void nb_list_free(nb_list *l) {
     if (!l) return;
-    hipSetDevice(l->ctx->device);
-    hipStreamSynchronize(l->ctx->stream);
+    (void)hipSetDevice(l->ctx->device);
+    (void)hipStreamSynchronize(l->ctx->stream);
     list_release(l);
     delete l;
 }
@@ -769,11 +769,11 @@ int nb_batch_create(nb_ctx *c, int n_rep, nb_grid *const *grids, nb_list *const 
 
 void nb_batch_free(nb_batch *b) {
     if (!b) return;
-    hipSetDevice(b->ctx->device);
-    hipStreamSynchronize(b->ctx->stream);
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     DevBuf *bufs[] = {&b->desc, &b->slot_off, &b->atom_off, &b->item_off, &b->partials,
                       &b->gjobs, &b->ljobs, &b->goff,     &b->loff,     &b->scans};
     for (DevBuf *d : bufs) release(*d);
@@ -823,11 +823,11 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
     CHECK(batch_check(c, b, p, flags, energy, virial));
     MXN_HIP(hipSetDevice(c->device));
     if (b->graph_exec) {
-        hipGraphExecDestroy(b->graph_exec);
+        (void)hipGraphExecDestroy(b->graph_exec);
         b->graph_exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     CHECK(batch_refresh(b, nullptr, nullptr, false));
@@ -845,7 +845,7 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
     c->stream = saved;
     c->timing = timing;
     if (e != hipSuccess || e2 != hipSuccess || rc != NB_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc != NB_OK ? rc : fail(NB_ERR_HIP, std::string("nb_batch_capture: ") +
                                                        hipGetErrorString(e != hipSuccess ? e : e2));
     }
@@ -1048,9 +1048,9 @@ int nb_autotune(nb_ctx *c, const nb_replicas *r, float rlist, const nb_params *p
             if (gr[k]) nb_grid_free(gr[k]);
         }
     }
-    if (ev0) hipEventDestroy(ev0);
-    if (ev1) hipEventDestroy(ev1);
-    hipStreamSynchronize(c->stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipStreamSynchronize(c->stream);
     release(fbuf);
     release(ebuf);
     return rc;
@@ -1062,11 +1062,11 @@ int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *
     CHECK(batch_check(c, b, p, flags, energy, virial));
     MXN_HIP(hipSetDevice(c->device));
     if (b->graph_exec) {
-        hipGraphExecDestroy(b->graph_exec);
+        (void)hipGraphExecDestroy(b->graph_exec);
         b->graph_exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     CHECK(rebuild_refresh(b));
@@ -1087,7 +1087,7 @@ int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *
     c->stream = saved;
     c->timing = timing;
     if (e != hipSuccess || e2 != hipSuccess || rc != NB_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc != NB_OK ? rc : fail(NB_ERR_HIP, std::string("nb_batch_capture_cycle: ") +
                                                        hipGetErrorString(e != hipSuccess ? e : e2));
     }
@@ -1164,8 +1164,8 @@ int nb_mlp_create(nb_ctx *c, const float *params, const double lo[8], const doub
 
 void nb_mlp_free(nb_mlp *m) {
     if (!m) return;
-    hipSetDevice(m->ctx->device);
-    hipStreamSynchronize(m->ctx->stream);
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipStreamSynchronize(m->ctx->stream);
     if (m->ctx->mlp == m) m->ctx->mlp = nullptr;
     DevBuf *bufs[] = {&m->params, &m->m, &m->v, &m->step, &m->lo, &m->hi};
     for (DevBuf *b : bufs) release(*b);

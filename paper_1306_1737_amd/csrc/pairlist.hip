@@ -430,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_max_count(const int *in, int n, int pe
     c[threadIdx.x] = it;
     e[threadIdx.x] = en;
     __syncthreads();
-    for (int s = 512; s > 0; s >>= 1) {
+    for (unsigned s = 512; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             m[threadIdx.x] = max(m[threadIdx.x], m[threadIdx.x + s]);
             c[threadIdx.x] += c[threadIdx.x + s];
@@ -907,7 +907,7 @@ void fill_list_job(void *out, nb_list *l, const int *excl_off, const int *excl_i
     j.cap_rows = l->cap_rows;
     j.flags = l->ctx->d_flags;
     std::memcpy(out, &j, sizeof j);
-    *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, j.per_item, j.totals + 1, j.totals};
+    *scan = ScanJob{j.part_count, j.part_istart, j.nregions, 2, j.per_item, j.totals + 1, j.totals, nullptr};
     int *jc = (int *)l->jcount.p;
     *jscan = ScanJob{jc, (int *)l->jstart.p, l->grid->slots_cap / l->grid->nn, 0, 1, nullptr, nullptr, jc};
 }
