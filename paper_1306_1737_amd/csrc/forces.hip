@@ -92,19 +92,27 @@ struct ForceArgs {
     long pstride;     // partials layout: [kNAcc][pstride]
 };
 
+// A particle's position at the evaluated time moved by the periodic image its
+// slot was sorted with (packed image offsets, 10 bits per axis, biased by 512):
+// x - (float)k * L with the product and the difference rounded separately,
+// the definition the list's particle tests are checked against (a contracted
+// multiply-add differs once k * L is inexact, for inputs many boxes away).
+__device__ inline float4 apply_image(float4 p, int im, float Lx, float Ly, float Lz) {
+    p.x = __fsub_rn(p.x, __fmul_rn((float)((im & 1023) - 512), Lx));
+    p.y = __fsub_rn(p.y, __fmul_rn((float)(((im >> 10) & 1023) - 512), Ly));
+    p.z = __fsub_rn(p.z, __fmul_rn((float)(((im >> 20) & 1023) - 512), Lz));
+    return p;
+}
+
 __global__ void k_gather(ForceArgs a) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= *a.nslots) return;
     const int o = a.perm[s];
     if (o >= 0) {
-        float4 p = a.xyzq_now[o];
-        const int im = a.img_s[s];
+        const float4 p = a.xyzq_now[o];
         if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(a.flags, mxn::FLAG_NONFINITE);
         if (a.nt > 0 && a.type_s[s] >= a.nt) atomicOr(a.flags, mxn::FLAG_TYPE);
-        p.x -= (float)((im & 1023) - 512) * a.Lx;
-        p.y -= (float)(((im >> 10) & 1023) - 512) * a.Ly;
-        p.z -= (float)(((im >> 20) & 1023) - 512) * a.Lz;
-        a.xs_now[s] = p;
+        a.xs_now[s] = apply_image(p, a.img_s[s], a.Lx, a.Ly, a.Lz);
     }
 }
 
@@ -1039,14 +1047,10 @@ __global__ void k_batch_gather(BatchArgs b) {
     if (s >= *d.nslots) return;
     const int o = d.perm[s];
     if (o >= 0) {
-        float4 p = d.xyzq_now[o];
-        const int im = d.img_s[s];
+        const float4 p = d.xyzq_now[o];
         if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w))) atomicOr(b.flags, mxn::FLAG_NONFINITE);
         if (d.type_s[s] >= b.nt) atomicOr(b.flags, mxn::FLAG_TYPE);
-        p.x -= (float)((im & 1023) - 512) * d.Lx;
-        p.y -= (float)(((im >> 10) & 1023) - 512) * d.Ly;
-        p.z -= (float)(((im >> 20) & 1023) - 512) * d.Lz;
-        d.xs_now[s] = p;
+        d.xs_now[s] = apply_image(p, d.img_s[s], d.Lx, d.Ly, d.Lz);
     }
 }
 
