@@ -3,9 +3,11 @@
     python -m paper_1306_1737_amd.build
 
 Every HIP translation unit is compiled with packed FP32 instructions disabled
-(-Xclang -target-feature -Xclang -packed-fp32-ops).  grid.hip and pairlist.hip
-are compiled with -ffp-contract=off because the sort keys, bounding boxes and
-the pair-list predicate are defined by separately rounded FP32 operations.
+(-Xclang -target-feature -Xclang -packed-fp32-ops).  grid.hip, pairlist.hip and
+rdf.hip are compiled with -ffp-contract=off because the sort keys, bounding
+boxes, the pair-list predicate and the histogram bins are defined by
+separately rounded FP32 operations (forces.hip writes its one such expression,
+the gathers' image shift, with explicit round-to-nearest operations).
 """
 from __future__ import annotations
 
