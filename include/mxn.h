@@ -407,6 +407,9 @@ int nb_set_search_parts(nb_ctx *ctx, int parts);
  * graph must then be captured again (nb_batch_replay returns NB_ERR_STATE).
  * The graph keeps the params' c6c12 pointer and the output pointers passed
  * to nb_batch_capture.  Supported flags: NB_ENERGY, NB_VIRIAL, NB_ACCUMULATE.
+ * Every Coulomb variant of nb_params (Eq. 2: analytic Ewald, reaction field,
+ * tabulated Ewald); the tabulated variant's table is built in the context on
+ * first use, and before a capture begins, so captured launches only read it.
  */
 int nb_batch_create(nb_ctx *ctx, int n_rep, nb_grid *const *grids, nb_list *const *lists,
                     const float *const *xyzq_now, float *const *f, nb_batch **batch);

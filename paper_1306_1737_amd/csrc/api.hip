@@ -807,8 +807,12 @@ static int batch_check(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flag
         return fail(NB_ERR_ARG, "nb_batch: bad interaction parameters");
     for (int r = 0; r < b->n_rep; ++r)
         if (!(p->rc <= b->lists[r]->rlist)) return fail(NB_ERR_ARG, "nb_batch: rc exceeds a replica's rlist");
-    if ((double)p->beta * p->rc > 4.0) return fail(NB_ERR_UNSUPPORTED, "nb_batch: beta*rc > 4");
-    if (p->coulomb != NB_COULOMB_EWALD) return fail(NB_ERR_UNSUPPORTED, "nb_batch: Ewald (analytic) only");
+    if (p->coulomb < NB_COULOMB_EWALD || p->coulomb > NB_COULOMB_EWALD_TABLE)
+        return fail(NB_ERR_ARG, "nb_batch: unknown coulomb type");
+    if (p->coulomb == NB_COULOMB_RF && !(p->eps_rf == 0.0f || (p->eps_rf >= 1.0f && std::isfinite(p->eps_rf))))
+        return fail(NB_ERR_ARG, "nb_batch: eps_rf must be >= 1, or 0 for a conducting boundary");
+    if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
+        return fail(NB_ERR_UNSUPPORTED, "nb_batch: beta*rc > 4 is outside the fitted Ewald range");
     return NB_OK;
 }
 
@@ -831,6 +835,7 @@ int nb_batch_capture(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flags,
         b->graph = nullptr;
     }
     CHECK(batch_refresh(b, nullptr, nullptr, false));
+    CHECK(prepare_coulomb(c, p));
     if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     MXN_HIP(hipStreamSynchronize(c->stream));
     hipStream_t saved = c->stream;
@@ -1071,6 +1076,7 @@ int nb_batch_capture_cycle(nb_ctx *c, nb_batch *b, int nsteps, const nb_params *
     }
     CHECK(rebuild_refresh(b));
     CHECK(batch_refresh(b, nullptr, nullptr, false));
+    CHECK(prepare_coulomb(c, p));
     if (!b->capture_stream) MXN_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     MXN_HIP(hipStreamSynchronize(c->stream));
     hipStream_t saved = c->stream;

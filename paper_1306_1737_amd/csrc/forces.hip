@@ -1055,19 +1055,20 @@ __global__ void k_batch_gather(BatchArgs b) {
 }
 
 // Work item idx of the concatenated items of all replicas, which belongs to replica r.
-template <int M, int N, bool ENER, bool VIR>
-__device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, long idx, int r, int lane) {
+template <int M, int N, bool ENER, bool VIR, int ELEC>
+__device__ inline void batch_item(const ForceArgs &a, const BatchArgs &b, const float4 *ljt, const float2 *tab, long idx,
+                                  int r, int lane) {
     const RepDesc &d = b.rep[r];
     const SysView v =
         make_view(d.xs_now, d.type_s, d.fj, d.fi, d.jpos, d.items, d.entries, b.partials, b.pstride, d.pbase);
-    force_item<M, N, ENER, VIR, true, 0, false>(a, v, ljt, nullptr, d.shiftvec, (int)(idx - b.item_off[r]), lane);
+    force_item<M, N, ENER, VIR, true, ELEC, false>(a, v, ljt, tab, d.shiftvec, (int)(idx - b.item_off[r]), lane);
 }
 
 // One launch over the concatenated work items of all replicas, one wavefront per item, split between the
 // XCDs like the single-system kernel: wavefront k of XCD x takes item x * per + k.  The grid is sized from
 // the replicas' item counts at their last synchronous list builds, so it may hold fewer than per
 // wavefronts per XCD; k_batch_tail takes the items beyond.
-template <int M, int N, bool ENER, bool VIR>
+template <int M, int N, bool ENER, bool VIR, int ELEC>
 __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) {
     const long total = b.item_off[b.n_rep];
     const long first = xcd_block_first(total, b.waves);
@@ -1081,19 +1082,22 @@ __global__ __launch_bounds__(512) void k_batch_forces(ForceArgs a, BatchArgs b) 
         rep0 = find_rep(b.item_off, b.n_rep, min((long)(blockIdx.x % 8) * per + first, total - 1));
     }
     fill_ljt(a, ljt);
+    float2 *tab = reinterpret_cast<float2 *>(ljt + a.nt * a.nt + 1);   // Ewald table after the LJ rows
+    if (ELEC == 2)
+        for (int t = threadIdx.x; t < a.ntab; t += blockDim.x) tab[t] = a.etab[t];
     __syncthreads();
     const long idx = xcd_item(total, b.waves, threadIdx.x >> 6);
     if (idx < 0) return;
     const long x = __builtin_amdgcn_readfirstlane(idx);
     int r = rep0;
     while (r + 1 < b.n_rep && b.item_off[r + 1] <= x) ++r;
-    batch_item<M, N, ENER, VIR>(a, b, ljt, x, r, threadIdx.x & 63);
+    batch_item<M, N, ENER, VIR, ELEC>(a, b, ljt, tab, x, r, threadIdx.x & 63);
 }
 
 // Items k >= covered of each XCD's share (covered: the main launch's wavefronts per XCD), strided over
 // this launch's wavefronts; nothing to do, and an immediate exit, while the estimate holds.  A separate
 // kernel because the loop costs registers (and occupancy) that the one-item kernel does not need.
-template <int M, int N, bool ENER, bool VIR>
+template <int M, int N, bool ENER, bool VIR, int ELEC>
 __global__ __launch_bounds__(512) void k_batch_tail(ForceArgs a, BatchArgs b, long covered) {
     const long total = b.item_off[b.n_rep];
     const long per = (total + 7) / 8;
@@ -1101,13 +1105,16 @@ __global__ __launch_bounds__(512) void k_batch_tail(ForceArgs a, BatchArgs b, lo
     if (k0 >= per) return;   // uniform over the workgroup
     extern __shared__ float4 ljt[];
     fill_ljt(a, ljt);
+    float2 *tab = reinterpret_cast<float2 *>(ljt + a.nt * a.nt + 1);
+    if (ELEC == 2)
+        for (int t = threadIdx.x; t < a.ntab; t += blockDim.x) tab[t] = a.etab[t];
     __syncthreads();
     const long x0 = (long)(blockIdx.x % 8) * per, x1 = min(x0 + per, total);
     const long stride = (long)(gridDim.x / 8) * b.waves;
     for (long idx = x0 + k0 + (threadIdx.x >> 6); idx < x1; idx += stride)
-        batch_item<M, N, ENER, VIR>(a, b, ljt, idx,
-                                    __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx)),
-                                    threadIdx.x & 63);
+        batch_item<M, N, ENER, VIR, ELEC>(a, b, ljt, tab, idx,
+                                          __builtin_amdgcn_readfirstlane(find_rep(b.item_off, b.n_rep, idx)),
+                                          threadIdx.x & 63);
 }
 
 // one wavefront per j-cluster of every replica (the replicas' slot capacities
@@ -1152,25 +1159,34 @@ __global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs b, int ener, int
     }
 }
 
-template <int M, int N, bool E, bool V>
+template <int M, int N, bool E, bool V, int ELEC>
 int launch_batch_forces_k(const ForceArgs &a, const BatchArgs &b, long est_items, size_t lds, hipStream_t st) {
     // enough workgroups for every XCD to hold an eighth of the estimated items; the tail launch
     // (32 workgroups per XCD) takes whatever lies beyond
     const long per = (est_items + 7) / 8;
     const long nb = 8 * std::max(1L, (per + b.waves - 1) / b.waves);
-    k_batch_forces<M, N, E, V><<<(unsigned)nb, 64 * b.waves, lds, st>>>(a, b);
-    k_batch_tail<M, N, E, V><<<8 * 32, 64 * b.waves, lds, st>>>(a, b, (nb / 8) * b.waves);
+    k_batch_forces<M, N, E, V, ELEC><<<(unsigned)nb, 64 * b.waves, lds, st>>>(a, b);
+    k_batch_tail<M, N, E, V, ELEC><<<8 * 32, 64 * b.waves, lds, st>>>(a, b, (nb / 8) * b.waves);
     return NB_OK;
+}
+
+template <int M, int N, int ELEC>
+int launch_batch_elec(const ForceArgs &a, const BatchArgs &b, unsigned flags, long est_items, size_t lds,
+                      hipStream_t st) {
+    const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL;
+    if (E && V) return launch_batch_forces_k<M, N, true, true, ELEC>(a, b, est_items, lds, st);
+    if (E) return launch_batch_forces_k<M, N, true, false, ELEC>(a, b, est_items, lds, st);
+    if (V) return launch_batch_forces_k<M, N, false, true, ELEC>(a, b, est_items, lds, st);
+    return launch_batch_forces_k<M, N, false, false, ELEC>(a, b, est_items, lds, st);
 }
 
 template <int M, int N>
 int launch_batch_shape(const ForceArgs &a, const BatchArgs &b, unsigned flags, long est_items, size_t lds,
                        hipStream_t st) {
-    const bool E = flags & NB_ENERGY, V = flags & NB_VIRIAL;
-    if (E && V) return launch_batch_forces_k<M, N, true, true>(a, b, est_items, lds, st);
-    if (E) return launch_batch_forces_k<M, N, true, false>(a, b, est_items, lds, st);
-    if (V) return launch_batch_forces_k<M, N, false, true>(a, b, est_items, lds, st);
-    return launch_batch_forces_k<M, N, false, false>(a, b, est_items, lds, st);
+    if (a.elec == NB_COULOMB_RF) return launch_batch_elec<M, N, 1>(a, b, flags, est_items, lds, st);
+    if (a.elec == NB_COULOMB_EWALD_TABLE)
+        return launch_batch_elec<M, N, 2>(a, b, flags, est_items, lds + (size_t)a.ntab * sizeof(float2), st);
+    return launch_batch_elec<M, N, 0>(a, b, flags, est_items, lds, st);
 }
 }  // namespace
 
@@ -1255,6 +1271,25 @@ static int ensure_ewald_table(nb_ctx *ctx, float beta, float rc, int *ntab) {
     return NB_OK;
 }
 
+
+// The Coulomb variant's constants (Eq. 2 for Ewald; the reaction field's k and c; the Ewald table, built
+// on first use and kept in the context).
+static int set_coulomb(nb_ctx *ctx, ForceArgs &a, const nb_params *p) {
+    a.elec = p->coulomb;
+    if (p->coulomb == NB_COULOMB_RF) {   // k = (eps_rf - 1) / ((2 eps_rf + 1) rc^3), 0 = conducting; c = 1/rc + k rc^2
+        const double rc = p->rc, eps = p->eps_rf;
+        const double k = eps == 0.0 ? 1.0 / (2.0 * rc * rc * rc) : (eps - 1.0) / ((2.0 * eps + 1.0) * rc * rc * rc);
+        a.krf = (float)k;
+        a.k2rf = (float)(2.0 * k);
+        a.crf = (float)(1.0 / rc + k * rc * rc);
+    } else if (p->coulomb == NB_COULOMB_EWALD_TABLE) {
+        int rc = ensure_ewald_table(ctx, p->beta, p->rc, &a.ntab);
+        if (rc) return rc;
+        a.etab = (const float2 *)ctx->etab.p;
+        a.tab_scale = (float)kTabScale;
+    }
+    return NB_OK;
+}
 
 // The rational erfc fit in powers of r instead of u = beta r (coefficient k times beta^k), so the kernels
 // evaluate it without forming u.
@@ -1341,18 +1376,9 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
     a.coulomb_f = p->coulomb_f;
     a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
-    a.elec = p->coulomb;
-    if (p->coulomb == NB_COULOMB_RF) {   // k = (eps_rf - 1) / ((2 eps_rf + 1) rc^3), 0 = conducting; c = 1/rc + k rc^2
-        const double rc = p->rc, eps = p->eps_rf;
-        const double k = eps == 0.0 ? 1.0 / (2.0 * rc * rc * rc) : (eps - 1.0) / ((2.0 * eps + 1.0) * rc * rc * rc);
-        a.krf = (float)k;
-        a.k2rf = (float)(2.0 * k);
-        a.crf = (float)(1.0 / rc + k * rc * rc);
-    } else if (p->coulomb == NB_COULOMB_EWALD_TABLE) {
-        int rc = ensure_ewald_table(ctx, p->beta, p->rc, &a.ntab);
-        if (rc) return rc;
-        a.etab = (const float2 *)ctx->etab.p;
-        a.tab_scale = (float)kTabScale;
+    {
+        const int rc_ = set_coulomb(ctx, a, p);
+        if (rc_) return rc_;
     }
     a.Lx = g->Lf[0]; a.Ly = g->Lf[1]; a.Lz = g->Lf[2];
     a.sci = 1;
@@ -1410,6 +1436,14 @@ int launch_forces(nb_ctx *ctx, const nb_grid *g, const nb_list *l, const float *
 }
 
 
+// The Coulomb variant's device tables, built before a graph capture (which may not allocate or copy from
+// the host); the captured launches then find them ready.
+int prepare_coulomb(nb_ctx *ctx, const nb_params *p) {
+    if (p->coulomb != NB_COULOMB_EWALD_TABLE) return NB_OK;
+    int ntab = 0;
+    return ensure_ewald_table(ctx, p->beta, p->rc, &ntab);
+}
+
 int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, double *energy, double *virial) {
     hipStream_t st = ctx->stream;
     ForceArgs a{};
@@ -1424,6 +1458,10 @@ int launch_batch(nb_ctx *ctx, nb_batch *bt, const nb_params *p, unsigned flags, 
     a.coulomb_f = p->coulomb_f;
     a.shiftC = p->shift_energies ? (float)(std::erfc((double)p->beta * p->rc) / (double)p->rc) : 0.0f;
     a.rc6inv = (float)(1.0 / std::pow((double)p->rc, 6));
+    {
+        const int rc_ = set_coulomb(ctx, a, p);
+        if (rc_) return rc_;
+    }
     BatchArgs b{};
     b.rep = (const RepDesc *)bt->desc.p;
     b.n_rep = bt->n_rep;

@@ -201,6 +201,7 @@ namespace mxn {
 
 constexpr int kMlpParams = 4801;
 int launch_batch(nb_ctx *ctx, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial);
+int prepare_coulomb(nb_ctx *ctx, const nb_params *p);
 size_t rep_desc_size();
 // batched list rebuild (grid sort and pair search of many replicas, one launch per stage)
 struct ScanJob {

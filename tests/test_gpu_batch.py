@@ -90,6 +90,74 @@ def test_batch_matches_per_replica_and_graph_replays(shape):
         mxn.nb_destroy(ctx)
 
 
+@pytest.mark.parametrize("shape", [(4, 4), (8, 8)])
+@pytest.mark.parametrize("coulomb,eps_rf,beta", [(1, 78.0, 0.0), (1, 0.0, 0.0), (2, 0.0, 3.12)],
+                         ids=["rf78", "rf0", "table"])
+def test_batch_coulomb_variants(shape, coulomb, eps_rf, beta):
+    """Reaction field and the tabulated Ewald correction (Eq. 2's Coulomb variants) in the batched launch: each
+    replica equals its own nb_forces with the same variant (to rounding: the batched kernel sums a work item's
+    i-forces in another order), forces, energies and virial; one replica against the FP64 oracle; a captured
+    graph of the tabulated variant (its table built before the capture) replays with eager work between."""
+    import torch
+    import paper_1306_1737_amd as mxn
+    dev = torch.device("cuda:0")
+    ctx = mxn.nb_create(0)
+    try:
+        lj = torch.from_numpy(synth.lj_table_spce().astype(np.float32)).to(dev)
+        p = mxn.make_params(1.0, beta, F, lj, True, coulomb, eps_rf)
+        reps = _replicas(torch, mxn, ctx, shape)
+        n = len(reps)
+        fl = mxn.NB_ENERGY | mxn.NB_VIRIAL
+        ref_f, ref_e, ref_v = [], [], []
+        for r in reps:
+            f = torch.zeros_like(r["f"])
+            e = torch.zeros(2, dtype=torch.float64, device=dev)
+            v = torch.zeros(9, dtype=torch.float64, device=dev)
+            mxn.nb_forces(ctx, r["grid"], r["lst"], r["xyzq"], p, fl, f, e, v)
+            mxn.nb_sync(ctx)
+            ref_f.append(f.cpu().numpy().astype(np.float64)); ref_e.append(e.cpu().numpy()); ref_v.append(v.cpu().numpy())
+        batch = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                    [r["xyzq"] for r in reps], [r["f"] for r in reps])
+        energy = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        virial = torch.zeros(9 * n, dtype=torch.float64, device=dev)
+
+        def check():
+            e = energy.cpu().numpy().reshape(n, 2)
+            v = virial.cpu().numpy().reshape(n, 9)
+            for k, r in enumerate(reps):
+                assert rel_rms(r["f"].cpu().numpy().astype(np.float64), ref_f[k]) <= 1e-6
+                np.testing.assert_allclose(e[k], ref_e[k], rtol=1e-9)
+                assert np.abs(v[k] - ref_v[k]).max() <= 1e-6 * np.abs(ref_v[k]).max()
+
+        mxn.nb_batch_forces(ctx, batch, p, fl, energy, virial)
+        mxn.nb_sync(ctx)
+        check()
+        if coulomb == mxn.NB_COULOMB_EWALD_TABLE:
+            mxn.nb_batch_capture(ctx, batch, p, fl, energy, virial)
+            for _ in range(3):
+                for r in reps:
+                    r["f"].fill_(float("nan"))   # eager work between replays
+                energy.zero_(); virial.zero_()
+                torch.cuda.synchronize()
+                mxn.nb_batch_replay(ctx, batch)
+                mxn.nb_sync(ctx)
+                check()
+        mxn.nb_batch_free(batch)
+        b = reps[2]["box"]
+        if coulomb == mxn.NB_COULOMB_RF:
+            fr, er, _ = oracle.forces_rf(b.xyz, b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(), 1.0,
+                                         eps_rf, F, shift=True, mode="brute")
+        else:
+            fr, er, _ = oracle.forces(b.xyz, b.q, b.type, b.box, b.excl_off, b.excl_idx, synth.lj_table_spce(), 1.0,
+                                      beta, F, shift=True, mode="brute")
+        assert rel_rms(ref_f[2], fr) <= 1e-5
+        np.testing.assert_allclose(ref_e[2], er, rtol=1e-5)
+        for r in reps:
+            mxn.nb_list_free(r["lst"]); mxn.nb_grid_free(r["grid"])
+    finally:
+        mxn.nb_destroy(ctx)
+
+
 def test_batch_grid_size_does_not_change_results():
     """The main launch takes one item per wavefront over a grid sized from the lists' item estimates and a
     second launch strides over the rest: any main-grid size (a single workgroup per XCD, the default, far
