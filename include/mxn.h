@@ -74,9 +74,10 @@ typedef struct { int m, n; } nb_shape;
  *               also for excluded pairs (e = 0); shift_energies affects LJ only;
  *             NB_COULOMB_EWALD_TABLE (2): Ewald as 0, with the smooth parts of
  *               force and potential interpolated linearly from a table in LDS
- *               (spacing 1 pm; Sec. 3.2 "linear table interpolation").
- *             RF and the table are supported by the direct force kernel on single
- *             systems; batches and nb_recount take Ewald only.
+ *               (spacing 1 pm, 8 KB per nm of rc: rc <= 4 nm, NB_ERR_UNSUPPORTED
+ *               beyond).
+ *             RF and the table are supported by the force kernels of single
+ *             systems and by batches; nb_recount takes Ewald only.
  *   eps_rf    reaction field: relative permittivity beyond rc (>= 1, or 0) */
 enum { NB_COULOMB_EWALD = 0, NB_COULOMB_RF = 1, NB_COULOMB_EWALD_TABLE = 2 };
 typedef struct {

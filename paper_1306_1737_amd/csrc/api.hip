@@ -595,6 +595,8 @@ static int forces_check(const char *who, nb_ctx *c, const nb_grid *g, const nb_l
         return fail(NB_ERR_ARG, w + ": eps_rf must be >= 1, or 0 for a conducting boundary");
     if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
         return fail(NB_ERR_UNSUPPORTED, w + ": beta*rc > 4 is outside the fitted Ewald range");
+    if (p->coulomb == NB_COULOMB_EWALD_TABLE && p->rc > kMaxTableRc)
+        return fail(NB_ERR_UNSUPPORTED, w + ": the Ewald table (LDS) covers rc <= 4 nm");
     return NB_OK;
 }
 
@@ -813,6 +815,8 @@ static int batch_check(nb_ctx *c, nb_batch *b, const nb_params *p, unsigned flag
         return fail(NB_ERR_ARG, "nb_batch: eps_rf must be >= 1, or 0 for a conducting boundary");
     if (p->coulomb != NB_COULOMB_RF && (double)p->beta * p->rc > 4.0)
         return fail(NB_ERR_UNSUPPORTED, "nb_batch: beta*rc > 4 is outside the fitted Ewald range");
+    if (p->coulomb == NB_COULOMB_EWALD_TABLE && p->rc > kMaxTableRc)
+        return fail(NB_ERR_UNSUPPORTED, "nb_batch: the Ewald table (LDS) covers rc <= 4 nm");
     return NB_OK;
 }
 

@@ -202,6 +202,9 @@ namespace mxn {
 constexpr int kMlpParams = 4801;
 int launch_batch(nb_ctx *ctx, nb_batch *b, const nb_params *p, unsigned flags, double *energy, double *virial);
 int prepare_coulomb(nb_ctx *ctx, const nb_params *p);
+// largest rc of the tabulated Ewald variant: its table (8 KB per nm) and the LJ rows (up to 16.4 KB) stay
+// within a workgroup's 64 KB of LDS
+constexpr float kMaxTableRc = 4.0f;
 size_t rep_desc_size();
 // batched list rebuild (grid sort and pair search of many replicas, one launch per stage)
 struct ScanJob {

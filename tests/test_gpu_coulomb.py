@@ -106,6 +106,42 @@ def test_unsupported_combinations(c1):
         s.close()
 
 
+def test_table_rc_bound():
+    """The tabulated Ewald variant keeps its table in LDS (8 KB per nm of rc): rc up to 4 nm runs, beyond it
+    the call is refused as unsupported, for single systems and batches.  Both Ewald variants are held to the
+    usual 1e-5 against FP64 at rc = 3.95 nm; in this dilute box the forces are about a hundred times smaller
+    than in liquid water, so the table's interpolation error, fixed in absolute terms, is a larger fraction
+    of them than on the production box (3.5e-6 relative between the two variants here)."""
+    import torch
+    box = synth.water_box(300, 8.6, seed=17)   # dilute: a list at 4.2 nm stays small
+    s = GpuSystem(box, (8, 8), 4.2)
+    try:
+        mxn = s.mxn
+        fr, er, _ = oracle.forces(box.xyz, box.q, box.type, box.box, box.excl_off, box.excl_idx,
+                                  synth.lj_table_spce(), 3.95, 1.0, F, shift=True, mode="brute")
+        for coulomb in (mxn.NB_COULOMB_EWALD_TABLE, mxn.NB_COULOMB_EWALD):
+            f, e, _ = _run(s, 3.95, 1.0, mxn.NB_ENERGY, coulomb)
+            assert rel_rms(f, fr) <= 1e-5
+            # the LJ energy of this dilute box is a small residue (about 14 kJ/mol beside 2.5e4 of Coulomb
+            # energy): each energy is held to 1e-5 of the total's magnitude
+            np.testing.assert_allclose(e, er, rtol=1e-5, atol=1e-5 * np.abs(er).sum())
+        with pytest.raises(mxn.NbError) as ei:
+            _run(s, 4.1, 0.9, 0, mxn.NB_COULOMB_EWALD_TABLE)
+        assert ei.value.status == mxn.NB_ERR_UNSUPPORTED
+        f = torch.zeros((box.n, 3), dtype=torch.float32, device=s.dev)
+        batch = mxn.nb_batch_create(s.ctx, [s.grid], [s.lst], [s.xyzq], [f])
+        try:
+            e = torch.zeros(2, dtype=torch.float64, device=s.dev)
+            with pytest.raises(mxn.NbError) as ei:
+                mxn.nb_batch_forces(s.ctx, batch, mxn.make_params(4.1, 0.9, F, s.lj, True,
+                                                                  mxn.NB_COULOMB_EWALD_TABLE), mxn.NB_ENERGY, e)
+            assert ei.value.status == mxn.NB_ERR_UNSUPPORTED
+        finally:
+            mxn.nb_batch_free(batch)
+    finally:
+        s.close()
+
+
 def _particles_near_cutoff(box, rc, delta):
     """Particles with a partner whose FP64 minimum-image distance lies within delta of rc."""
     from scipy.spatial import cKDTree
