@@ -39,8 +39,8 @@ PEAK_FP32 = 157.3e12
 # HBM traffic of one force-kernel launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device-to-device copy
 # (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid only for the kernel sources the counters were taken on.
-FORCE_TRAFFIC = {"sources_sha1": "a6cf9470ec29508015e019ac4f4c4c1748191c94", "fetch_kib": 16355.3,
-                 "write_kib": 105314.1, "fetch_scale": 2.0, "write_scale": 1.0}
+FORCE_TRAFFIC = {"sources_sha1": "b2d8739c097e1351acc57e7d893ff20860a228f8", "fetch_kib": 16351.0,
+                 "write_kib": 105339.7, "fetch_scale": 2.0, "write_scale": 1.0}
 FORCE_SOURCES = ("paper_1306_1737_amd/csrc/forces.hip", "paper_1306_1737_amd/csrc/devptr.h",
                  "paper_1306_1737_amd/csrc/ewald_fit.h")
 METRIC = "atom-pair interactions/s (FP32, ≤1e-5 rel force err) + % FP32 VALU peak"
