@@ -96,8 +96,9 @@ def test_batch_matches_per_replica_and_graph_replays(shape):
 def test_batch_coulomb_variants(shape, coulomb, eps_rf, beta):
     """Reaction field and the tabulated Ewald correction (Eq. 2's Coulomb variants) in the batched launch: each
     replica equals its own nb_forces with the same variant (to rounding: the batched kernel sums a work item's
-    i-forces in another order), forces, energies and virial; one replica against the FP64 oracle; a captured
-    graph of the tabulated variant (its table built before the capture) replays with eager work between."""
+    i-forces in another order), forces, energies and virial; one replica against the FP64 oracle; captured
+    graphs of the tabulated variant (its table built before the capture), of a force call and of a whole
+    cycle (batched rebuild + two force calls), replay with eager work between."""
     import torch
     import paper_1306_1737_amd as mxn
     dev = torch.device("cuda:0")
@@ -142,6 +143,29 @@ def test_batch_coulomb_variants(shape, coulomb, eps_rf, beta):
                 mxn.nb_batch_replay(ctx, batch)
                 mxn.nb_sync(ctx)
                 check()
+            # the whole cycle (batched rebuild + two force evaluations) as one graph, on a second batch (a
+            # captured batch takes no new topology): replays equal an eager rebuild and force call
+            cyc = mxn.nb_batch_create(ctx, [r["grid"] for r in reps], [r["lst"] for r in reps],
+                                      [r["xyzq"] for r in reps], [r["f"] for r in reps])
+            mxn.nb_batch_bind_topology(cyc, [r["type"] for r in reps], [r["eo"] for r in reps],
+                                       [r["ei"] for r in reps])
+            mxn.nb_batch_rebuild(ctx, cyc)
+            mxn.nb_batch_forces(ctx, cyc, p, fl, energy, virial)
+            mxn.nb_sync(ctx)
+            eager_f = [r["f"].clone() for r in reps]
+            eager_e, eager_v = energy.clone(), virial.clone()
+            mxn.nb_batch_capture_cycle(ctx, cyc, 2, p, fl, energy, virial)
+            for _ in range(2):
+                for r in reps:
+                    r["f"].fill_(float("nan"))
+                energy.zero_(); virial.zero_()
+                torch.cuda.synchronize()
+                mxn.nb_batch_replay(ctx, cyc)
+                mxn.nb_sync(ctx)
+                for k, r in enumerate(reps):
+                    assert torch.equal(r["f"], eager_f[k])
+                assert torch.equal(energy, eager_e) and torch.equal(virial, eager_v)
+            mxn.nb_batch_free(cyc)
         mxn.nb_batch_free(batch)
         b = reps[2]["box"]
         if coulomb == mxn.NB_COULOMB_RF:
