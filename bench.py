@@ -18,8 +18,8 @@ algorithmic flops = 63 per interacting pair (full LJ + Ewald evaluation; FP32
 VALU count of the built 8x8 force+energy kernel, FMA = 2) + 8 per listed pair
 beyond rc (distance and cut-off test), divided by the force kernel's average
 duration from HIP events on the library stream; peak = 157.3 TFLOP/s
-(MI355X FP32 vector, 256 CUs x 2.4 GHz, counting packed FP32; the non-packed
-ceiling this build can reach is half of it).  roofline.traffic = measured HBM
+(MI355X FP32 vector, 256 CUs x 2.4 GHz, counting packed FP32; code compiled
+without packed FP32 reaches at most half of it).  roofline.traffic = measured HBM
 bytes per force-kernel launch (scaled FETCH_SIZE + WRITE_SIZE counters, see
 FORCE_TRAFFIC), null once the kernel sources differ from the profiled ones.
 """
@@ -226,7 +226,7 @@ def main():
         print(json.dumps({"copy_probe_mib": args.copy_probe, "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: measures one GPU only; multi-GPU runs are not part of it "
               "(the path would shard by replica or by spatial domain, see the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":

@@ -44,7 +44,7 @@ typedef enum {
     NB_ERR_OVERFLOW = -5,    /* pair-list capacity exceeded during an asynchronous build: rebuild */
     NB_ERR_STATE = -6,       /* handle used with an incompatible grid, list or context */
     NB_ERR_NONFINITE = -7,   /* non-finite or out-of-range coordinate seen by a kernel */
-    NB_ERR_UNSUPPORTED = -8  /* valid request this build does not implement (for example beta*rc > 4) */
+    NB_ERR_UNSUPPORTED = -8  /* valid request the library does not implement (for example beta*rc > 4) */
 } nb_status;
 
 typedef struct nb_ctx nb_ctx;

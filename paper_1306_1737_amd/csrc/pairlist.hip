@@ -993,7 +993,7 @@ int launch_pairlist(nb_list *l, const int *excl_off, const int *excl_idx, bool s
         int rc = ensure(l->ctx, l->jcount, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->ctx, l->jstart, (size_t)(njc + 1) * 4);
         rc = rc ? rc : ensure(l->ctx, l->jrank, (size_t)l->cap_entries * 4);
-        // j-force rows (one per entry, 12 N bytes): this build's entries plus a quarter, not the regions'
+        // j-force rows (one per entry, 12 N bytes): the synchronous build's entries plus a quarter, not the regions'
         // capacity (about three times the entries); a later asynchronous build with more entries than that
         // latches NB_ERR_OVERFLOW like an outgrown region
         const long ent = ctx->h_pinned[2];
