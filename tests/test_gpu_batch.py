@@ -36,7 +36,7 @@ def _replicas(torch, mxn, ctx, shape, rlist=1.1):
     return reps
 
 
-@pytest.mark.parametrize("shape", [(4, 4), (8, 8)])
+@pytest.mark.parametrize("shape", [(4, 4), (4, 8), (8, 4), (8, 8)])
 def test_batch_matches_per_replica_and_graph_replays(shape):
     import torch
     import paper_1306_1737_amd as mxn
@@ -90,7 +90,7 @@ def test_batch_matches_per_replica_and_graph_replays(shape):
         mxn.nb_destroy(ctx)
 
 
-@pytest.mark.parametrize("shape", [(4, 4), (8, 8)])
+@pytest.mark.parametrize("shape", [(4, 4), (4, 8), (8, 4), (8, 8)])
 @pytest.mark.parametrize("coulomb,eps_rf,beta", [(1, 78.0, 0.0), (1, 0.0, 0.0), (2, 0.0, 3.12)],
                          ids=["rf78", "rf0", "table"])
 def test_batch_coulomb_variants(shape, coulomb, eps_rf, beta):
